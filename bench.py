@@ -1,0 +1,236 @@
+"""Benchmark of the deform-then-splat render on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+
+A step is one frame of the whole hot path: the HexPlane deformation of all
+Gaussians at timestamp t (g4d_deform) followed by the tile render through
+one camera (g4d_render), inputs resident in HBM, image left on the device.
+Workload: 100k Gaussians on a noisy sphere shell (SH degree 3), planes at
+spatial 64/128 and temporal 25 with 32 features, MLP 64-64-10, 800x800,
+frames cycling through 20 ring cameras x 20 timestamps.
+
+Prints one JSON line with frames/s, the roofline of the dominant kernel
+(timed live with HIP events around it on the render stream) and the CPU
+oracle timed on a bounded sample on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "deform+splat frames/s @800², 100k Gaussians; served p50/p99 ms vs plain"
+
+# MI355X published peaks
+PEAK_HBM_GBS = 8000.0
+PEAK_FP32_TFLOPS = 157.3
+
+# Algorithmic work per unit (measurement section)
+BLEND_FLOP_PER_EVAL = 14          # binary32 ops per evaluated (pixel, Gaussian) pair
+STAGES = ["clear", "preprocess", "depth_sort", "offsets", "emit", "tile_sort", "ranges", "blend"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+class HipEvents:
+    """hipEvent_t handles through the HIP runtime torch has loaded."""
+
+    def __init__(self):
+        self.lib = ctypes.CDLL("libamdhip64.so.7")
+        self.lib.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        self.lib.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
+        self.lib.hipEventDestroy.argtypes = [ctypes.c_void_p]
+        self.lib.hipEventRecord.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+
+    def create(self):
+        e = ctypes.c_void_p()
+        assert self.lib.hipEventCreate(ctypes.byref(e)) == 0
+        return e.value
+
+    def record(self, e, stream):
+        assert self.lib.hipEventRecord(e, stream) == 0
+
+    def elapsed(self, a, b) -> float:
+        ms = ctypes.c_float()
+        assert self.lib.hipEventElapsedTime(ctypes.byref(ms), a, b) == 0
+        return ms.value
+
+    def destroy(self, e):
+        self.lib.hipEventDestroy(e)
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_cores() -> int:
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, int(os.environ.get("OMP_NUM_THREADS", n))))
+
+
+def cpu_baseline(sc, frames, n_frames: int):
+    """The CPU oracle (FP64 deform + render) on the first n_frames frames."""
+    import oracle
+    cores = host_cores()
+    oracle.set_threads(cores)
+    oracle.build_lib(force=False)
+    t0 = time.perf_counter()
+    for (ci, t) in frames[:n_frames]:
+        oracle.deform_render(sc.gaussians, sc.planes, sc.mlp, t, sc.cameras[ci])
+    dt = time.perf_counter() - t0
+    return {"value": n_frames / dt, "unit": "frames/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n_frames} full frames (deform + render, 100k Gaussians, 800x800) of the same "
+                      f"frame sequence; {dt:.1f} s on {cores} threads of {cpu_model()}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-frames", type=int, default=3)
+    ap.add_argument("--n", type=int, default=100_000)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the render shards by requests or image tiles; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2310_08528_amd import g4d, synth
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    ev = HipEvents()
+
+    sc = synth.config2(n=args.n)
+    frames = [(k % len(sc.cameras), float(sc.timestamps[(k // len(sc.cameras)) % len(sc.timestamps)]))
+              for k in range(len(sc.cameras) * len(sc.timestamps))]
+    G = g4d.DeviceGaussians(sc.gaussians, dev)
+    P = g4d.DevicePlanes(sc.planes, dev)
+    M = g4d.DeviceMLP(sc.mlp, dev)
+    S = g4d.DeviceSplats(G.n, G.sh_degree, G.sh, dev)
+    cams = [g4d.camera_struct(c) for c in sc.cameras]
+    W, H = sc.cameras[0].width, sc.cameras[0].height
+    img = torch.empty((3, H, W), dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream()
+    sp = stream.cuda_stream
+
+    # size the instance capacity over every frame of the sequence
+    ws = g4d.RenderWorkspace(G.n, W, H, 48 << 20, dev)
+    kmax, evals = 0, []
+    for (ci, t) in frames:
+        g4d.deform(G, P, M, t, S)
+        g4d.render(S, cams[ci], ws, img)
+        st = g4d.read_status(ws)
+        assert st.overflow == 0 and st.sort_error == 0, "sizing pass overflowed"
+        kmax = max(kmax, int(st.instances))
+    capacity = int(kmax * 1.05) + 4096
+    del ws
+    torch.cuda.empty_cache()
+    ws = g4d.RenderWorkspace(G.n, W, H, capacity, dev)
+    log(f"instances: max {kmax} over {len(frames)} frames, capacity {capacity}, "
+        f"workspace {ws.ws.bytes / 2**20:.1f} MiB")
+
+    # structs marshalled once; the loop only passes pointers
+    lib = g4d.load()
+    gs, ps, ms_, ss = G.struct(), P.struct(), M.struct(), S.struct()
+    bG, bP, bM, bS, bW = (ctypes.byref(x) for x in (gs, ps, ms_, ss, ws.ws))
+    bC = [ctypes.byref(c) for c in cams]
+    ip = img.data_ptr()
+
+    def step(k, stage_events=None):
+        ci, t = frames[k % len(frames)]
+        r1 = lib.g4d_deform(bG, bP, bM, ctypes.c_float(t), bS, sp)
+        if stage_events is not None:
+            lib.g4d_set_stage_events(stage_events, 9)
+        r2 = lib.g4d_render(bS, bC[ci], bW, ip, None, None, sp)
+        if stage_events is not None:
+            lib.g4d_set_stage_events(None, 0)
+        if r1 or r2:
+            raise g4d.G4DError(r1 or r2, "bench step")
+
+    for k in range(args.warmup):
+        step(k)
+    torch.cuda.synchronize()
+
+    # ---- timed region: K frames; HIP events around the blend kernel only
+    K = args.steps
+    blend_ev = [(ev.create(), ev.create()) for _ in range(K)]
+    blend_arr = [(ctypes.c_void_p * 9)(*([None] * 7 + [a, b])) for a, b in blend_ev]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(K):
+        step(args.warmup + k, blend_arr[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    fps = K / wall
+    blend_ms = float(np.mean([ev.elapsed(a, b) for a, b in blend_ev]))
+    st = g4d.read_status(ws)
+    assert st.overflow == 0 and st.sort_error == 0
+
+    # ---- per-stage breakdown (separate pass with events at every boundary)
+    n_prof = min(K, 100)
+    stage_ev = [[ev.create() for _ in range(9)] for _ in range(n_prof)]
+    dfm_ev = [(ev.create(), ev.create()) for _ in range(n_prof)]
+    evals_tot = 0
+    for k in range(n_prof):
+        ci, t = frames[(args.warmup + k) % len(frames)]
+        ev.record(dfm_ev[k][0], sp)
+        g4d.deform(G, P, M, t, S)
+        ev.record(dfm_ev[k][1], sp)
+        g4d.set_stage_events(stage_ev[k])
+        g4d.render(S, cams[ci], ws, img)
+        g4d.set_stage_events(None)
+        evals_tot += int(g4d.read_status(ws).blend_evals)
+    torch.cuda.synchronize()
+    stages = {"deform": float(np.mean([ev.elapsed(a, b) for a, b in dfm_ev]))}
+    for i, name in enumerate(STAGES):
+        stages[name] = float(np.mean([ev.elapsed(e[i], e[i + 1]) for e in stage_ev]))
+    evals_per_frame = evals_tot / n_prof
+
+    # ---- roofline of the dominant kernel (the blend: VALU-bound)
+    blend_flop = evals_per_frame * BLEND_FLOP_PER_EVAL
+    achieved = blend_flop / (blend_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "kernel": "k_blend", "achieved": round(achieved, 3),
+                "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                "traffic": None, "evals_per_frame": int(evals_per_frame),
+                "flop_per_eval": BLEND_FLOP_PER_EVAL, "avg_ms": round(blend_ms, 4)}
+
+    out = {"metric": METRIC, "value": round(fps, 2), "unit": "frames/s", "n_gpus": 1, "steps": K,
+           "warmup": args.warmup, "ms_per_step": round(1e3 * wall / K, 4), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "100k Gaussians (noisy sphere shell + 10% fill, SH3), HexPlane 64/128 x t25 "
+                                  "F32, MLP 64-64-10 FP32, 800x800, 20 ring cameras x 20 timestamps",
+                      "gaussians": G.n, "width": W, "height": H, "instances_max": kmax,
+                      "capacity": capacity},
+           "stages_ms": {k: round(v, 4) for k, v in stages.items()},
+           "roofline": roofline}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(sc, frames, args.cpu_frames)
+    for e in blend_ev:
+        ev.destroy(e[0]); ev.destroy(e[1])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

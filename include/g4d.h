@@ -1,0 +1,300 @@
+/*
+ * g4d.h - C ABI of the MI355X (gfx950) deform-then-splat render of
+ * 4D Gaussian Splatting ("4D Gaussian Splatting for Real-Time Dynamic Scene
+ * Rendering").
+ *
+ * The library computes  I = S(M, G')  with  G' = G + F(G, t)  (Sec. 4.1):
+ *   g4d_deform  evaluates the Gaussian deformation field F (Sec. 4.2: the
+ *               multi-resolution HexPlane encoder of Eq. 7, the feature MLP
+ *               phi_d and the heads phi_x, phi_r, phi_s) and applies Eq. 8;
+ *   g4d_render  splats the deformed Gaussians through a view M (Sec. 3.1:
+ *               Eq. 1-4, with the tile rasterizer of 3D Gaussian Splatting).
+ * A static render S(M, G) (the warm-up path of Sec. 4.3) is g4d_render on
+ * activated canonical Gaussians.
+ *
+ * Conventions shared by every call
+ *   - Every array pointer is a DEVICE pointer, allocated and owned by the
+ *     caller; the library never allocates device memory in these calls
+ *     (the serving calls at the end are the documented exception: the
+ *     server owns what it allocates).
+ *   - Per-Gaussian arrays are structure-of-arrays, component-major:
+ *     means[3][n] is x[0..n), y[0..n), z[0..n).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls only enqueue work; nothing synchronises unless stated.
+ *   - Errors detected on the host are returned synchronously, nothing is
+ *     enqueued then.  Device-side conditions (instance overflow) are
+ *     recorded in the workspace and read with g4d_read_status.
+ *   - No C++ exception crosses the ABI.  Calls on distinct workspaces and
+ *     streams may run concurrently.
+ */
+#ifndef G4D_H
+#define G4D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    G4D_OK = 0,
+    G4D_EINVAL = -1,        /* bad argument (null pointer, size out of range) */
+    G4D_EUNSUPPORTED = -2,  /* shape outside the compiled set (feat, scales, hidden) */
+    G4D_ECAPACITY = -3,     /* tile instances exceeded the workspace capacity */
+    G4D_EHIP = -4,          /* a HIP runtime call failed; see g4d_last_hip_error */
+    G4D_EBUSY = -5,         /* serving: no slot or memory free right now */
+    G4D_ENOMEM = -6,        /* serving: request larger than the memory budget */
+    G4D_ENOTFOUND = -7,     /* serving: unknown scene or ticket */
+    G4D_EDEVICE = -8        /* a device-side consistency check failed */
+} g4d_status;
+
+#define G4D_MAX_SCALES 4
+#define G4D_TILE 16
+
+/* Canonical 3D Gaussians G (Sec. 3.1): position X, SH colour coefficients,
+ * opacity, rotation r and scaling s.  Scales are stored as logarithms and
+ * opacity as a logit; g4d_deform applies exp and sigmoid after Eq. 8. */
+typedef struct {
+    int32_t n;                  /* number of Gaussians, >= 0 */
+    int32_t sh_degree;          /* 0..3 */
+    const float *means;         /* [3][n] */
+    const float *log_scales;    /* [3][n] */
+    const float *quats;         /* [4][n], (w, x, y, z), need not be unit */
+    const float *opacity_logits;/* [n] */
+    const float *sh;            /* [(d+1)^2][3][n]; not read by g4d_deform */
+} g4d_gaussians;
+
+/* Multi-resolution HexPlane R_l(i, j) (Sec. 4.2, Eq. 7).  For each scale l
+ * there are six planes in the order (x,y), (x,z), (y,z), (x,t), (y,t), (z,t);
+ * plane (a, b) is stored channels-last as [res_b][res_a][feat] float32.
+ * Canonical means are mapped to [-1, 1] through the box [bmin, bmax] and t
+ * in [0, 1] to 2t - 1; lookups use align-corners bilinear interpolation
+ * with clamping at the border.  Features are multiplied element-wise over
+ * the six planes of a scale and concatenated over scales: in_dim = feat *
+ * n_scales.  Supported: feat in {16, 32}, n_scales in {1, 2, 3}, every
+ * resolution >= 2. */
+typedef struct {
+    int32_t n_scales;
+    int32_t feat;
+    float bmin[3];
+    float bmax[3];
+    int32_t res[G4D_MAX_SCALES][4];            /* (Rx, Ry, Rz, Rt) per scale */
+    const float *plane[G4D_MAX_SCALES][6];
+} g4d_planes;
+
+typedef enum { G4D_MLP_F32 = 0, G4D_MLP_BF16 = 1 } g4d_mlp_precision;
+
+/* Deformation decoder (Sec. 4.2): h = ReLU(W1 f_h + b1) (the feature
+ * merger phi_d), then three linear heads dX = Wx h + bx (3), dr = Wr h + br
+ * (4), ds = Ws h + bs (3).  Row-major float32 weights.  precision
+ * G4D_MLP_BF16 rounds f_h, the weights and h to bfloat16 for the matrix
+ * products (FP32 accumulation, FP32 biases).  Supported hidden: 32, 64,
+ * 128. */
+typedef struct {
+    int32_t in_dim;             /* must equal feat * n_scales */
+    int32_t hidden;
+    int32_t precision;          /* g4d_mlp_precision */
+    const float *w1, *b1;       /* [hidden][in_dim], [hidden] */
+    const float *wx, *bx;       /* [3][hidden], [3] */
+    const float *wr, *br;       /* [4][hidden], [4] */
+    const float *ws, *bs;       /* [3][hidden], [3] */
+} g4d_mlp;
+
+/* Render-ready Gaussians G' (the set after Eq. 8 and activation): linear
+ * scales, unit quaternions, opacity in (0, 1).  g4d_deform writes means,
+ * scales, quats and opacity; g4d_render only reads. */
+typedef struct {
+    int32_t n;
+    int32_t sh_degree;          /* 0..3 */
+    float *means;               /* [3][n] */
+    float *scales;              /* [3][n] */
+    float *quats;               /* [4][n] (w, x, y, z), unit */
+    float *opacity;             /* [n] */
+    const float *sh;            /* [(d+1)^2][3][n] */
+} g4d_splats;
+
+/* Pinhole view M = [R, T] (Sec. 4.1).  Camera axes: x right, y down,
+ * z forward.  viewmat is the row-major 3x4 world-to-camera matrix whose
+ * 3x3 block is the viewing transform W of Eq. 3.  Pixel (px, py) is
+ * sampled at image coordinates (px, py); projection u = fx x/z + cx.
+ * Gaussians with camera depth z <= near_plane are culled. */
+typedef struct {
+    int32_t width, height;      /* 1..4096 */
+    float viewmat[12];
+    float fx, fy, cx, cy;
+    float tan_half_fov_x, tan_half_fov_y;
+    float near_plane;
+    float campos[3];            /* camera centre in world space (for SH view direction) */
+    float bg[3];                /* background colour */
+} g4d_camera;
+
+/* Caller-owned device scratch for one render at a time.  `ptr` holds at
+ * least g4d_render_workspace_bytes(n_max, width_max, height_max,
+ * instance_capacity) bytes, 256-byte aligned.  A workspace may be reused
+ * by renders of any size within its maxima; two renders in flight need two
+ * workspaces. */
+typedef struct {
+    void *ptr;
+    size_t bytes;
+    int32_t n_max;
+    int32_t width_max, height_max;
+    int64_t instance_capacity;  /* max number of (Gaussian, tile) pairs, < 2^30 */
+} g4d_workspace;
+
+/* Device-side outcome of the last render on a workspace. */
+typedef struct {
+    int64_t instances;          /* K: (Gaussian, tile) pairs the frame needed */
+    int32_t overflow;           /* 1 if instances > instance_capacity (image invalid) */
+    int32_t sort_error;         /* nonzero if a bounded wait in the sort gave up */
+    int32_t visible;            /* Gaussians that touched at least one tile */
+    int32_t tiles;              /* tiles_x * tiles_y of the frame */
+    int64_t blend_evals;        /* (pixel, Gaussian) pairs the compositing loop evaluated */
+} g4d_device_status;
+
+/* ---------------------------------------------------------------- deform */
+
+/* Eq. 7 + Eq. 8 + activations for G->n Gaussians at time t in [0, 1].
+ * Writes out->means (X + dX), out->scales (exp(log_s + ds)), out->quats
+ * (normalise(r + dr), identity if the sum is zero) and out->opacity
+ * (sigmoid(logit)); out->n must equal G->n.  out->sh and out->sh_degree are
+ * not touched (callers point out->sh at G->sh).  The output buffers must
+ * not alias the inputs. */
+g4d_status g4d_deform(const g4d_gaussians *G, const g4d_planes *P, const g4d_mlp *M, float t,
+                      g4d_splats *out, void *stream);
+
+/* One deformation job of a batched launch. */
+typedef struct {
+    const g4d_gaussians *G;
+    const g4d_planes *P;
+    const g4d_mlp *M;
+    float t;
+    g4d_splats *out;
+} g4d_deform_job;
+
+#define G4D_MAX_BATCH_JOBS 8
+
+/* Several g4d_deform calls in one kernel launch (continuous batching).  All
+ * jobs must share feat, n_scales, hidden and precision; each thread block
+ * works on Gaussians of a single job, so every job's output is bitwise the
+ * same as a lone g4d_deform call.  1 <= n_jobs <= G4D_MAX_BATCH_JOBS. */
+g4d_status g4d_deform_batched(const g4d_deform_job *jobs, int32_t n_jobs, void *stream);
+
+/* The encoder output f_h (Eq. 7) alone, [n][in_dim] float32: exposes the
+ * intermediate of g4d_deform for verification.  Same kernel code path. */
+g4d_status g4d_deform_features(const g4d_gaussians *G, const g4d_planes *P, float t,
+                               float *features, void *stream);
+
+/* ---------------------------------------------------------------- render */
+
+/* Bytes of workspace for renders of up to n Gaussians at up to width x
+ * height with up to instance_capacity tile instances.  Returns 0 for
+ * arguments out of range. */
+size_t g4d_render_workspace_bytes(int32_t n, int32_t width, int32_t height,
+                                  int64_t instance_capacity);
+
+/* I = S(M, G') (Sec. 3.1, Eq. 1-4).  Per Gaussian: project (Eq. 2-3 with
+ * a 0.3-pixel dilation of the 2D covariance), bound by a square of radius
+ * ceil(3 sqrt(lambda_max)), bin into 16x16 tiles.  Instances are keyed
+ * (tile_id << 32) | float_bits(depth) and radix-sorted (ties keep Gaussian
+ * index order).  Per pixel, Gaussians of its tile are composited front to
+ * back: alpha = min(0.99, o exp(-d^T Sigma'^-1 d / 2)), skipped below
+ * 1/255, stopping before transmittance would fall below 1e-4; the output
+ * is sum c alpha T + T_final bg.
+ *   image     [3][height][width] float32 (required)
+ *   final_T   [height][width] float32 or NULL
+ *   n_contrib [height][width] int32 or NULL: list entries visited up to the
+ *             last contributing Gaussian
+ * If the frame needs more instances than the workspace holds, the image is
+ * left incomplete and g4d_read_status reports overflow with the required
+ * count.  Asynchronous; graph-capturable (no host synchronisation, no
+ * allocation, fixed launch shapes for fixed arguments). */
+g4d_status g4d_render(const g4d_splats *G, const g4d_camera *C, const g4d_workspace *ws,
+                      float *image, float *final_T, int32_t *n_contrib, void *stream);
+
+/* Copies the device status of the last render on `ws` to the host.  Waits
+ * for `stream` to finish. */
+g4d_status g4d_read_status(const g4d_workspace *ws, g4d_device_status *out, void *stream);
+
+/* Intermediates of the last render on `ws`, copied device-to-device into
+ * `dst` (asynchronous on `stream`); for verification. */
+typedef enum {
+    G4D_EXPORT_SORTED_KEYS = 0,   /* uint64 [K]: (tile << 32) | depth bits, sorted */
+    G4D_EXPORT_SORTED_GIDS = 1,   /* uint32 [K]: Gaussian index per sorted instance */
+    G4D_EXPORT_RECT = 2,          /* int32 [n][4]: tile rectangle x0, y0, x1, y1 (empty if culled) */
+    G4D_EXPORT_DEPTH_BITS = 3,    /* uint32 [n]: float bits of camera depth, 0xffffffff if culled */
+    G4D_EXPORT_RANGES = 4,        /* uint32 [tiles][2]: [start, end) into the sorted list */
+    G4D_EXPORT_SPLAT2D = 5,       /* float32 [n][12]: u, v, -A/2, -C/2, -B, opacity, r, g, b, 0,0,0
+                                     where (A, B, C) is the conic Sigma'^-1 */
+    G4D_EXPORT_DEPTH_ORDER = 6    /* uint32 [n]: Gaussian indices sorted by (depth bits, index) */
+} g4d_export_kind;
+
+/* n: Gaussians of the frame; k: instances to copy for the SORTED kinds
+ * (at most K, use g4d_read_status), or the frame's tile count for RANGES.
+ * dst: device buffer of at least dst_bytes. */
+g4d_status g4d_render_export(const g4d_workspace *ws, int32_t kind, int32_t n, int64_t k,
+                             void *dst, size_t dst_bytes, void *stream);
+
+/* Stage timing: after this call, every g4d_render on the calling thread
+ * records events[i] (a hipEvent_t, or NULL to skip) on its stream at stage
+ * boundary i: 0 start, 1 after clearing, 2 preprocess, 3 depth sort,
+ * 4 instance offsets, 5 emit, 6 tile sort, 7 ranges, 8 blend.  count must
+ * be 9; events == NULL turns recording off.  The caller owns the events. */
+g4d_status g4d_set_stage_events(void *const *events, int32_t count);
+
+/* -------------------------------------------------------------- utilities */
+
+const char *g4d_status_string(int32_t status);
+int32_t g4d_last_hip_error(void);   /* hipError_t of the last G4D_EHIP */
+const char *g4d_version(void);
+
+/* ------------------------------------------------------------- serving */
+
+/* A request loop that keeps several scenes resident in HBM and renders
+ * (scene, camera, t) requests with continuous batching: requests are
+ * admitted while render slots and the memory budget allow, the
+ * deformations of newly admitted requests run as one batched launch per
+ * shape class, and each admitted request renders on its own stream (a
+ * captured graph per slot and frame size in steady state), so requests
+ * that arrive while others run overlap on the device.  The server owns all
+ * memory it allocates; images are written to caller device buffers. */
+typedef struct g4d_server g4d_server;
+
+typedef struct {
+    size_t hbm_budget;          /* bytes for per-request memory (workspaces, deformed sets) */
+    int32_t max_slots;          /* concurrent requests on the device, 1..64 */
+    int32_t use_graphs;         /* capture steady-state renders as HIP graphs */
+    int32_t batch_deform;       /* 1: batched deformation per admission round */
+    int32_t max_width, max_height;
+    double instance_factor;     /* capacity = factor * n * tiles-per-Gaussian bound; see server.cpp */
+} g4d_server_config;
+
+typedef struct {
+    int64_t submitted, completed, rejected;
+    double p50_ms, p99_ms, mean_ms, max_ms;
+    double wall_s;              /* first submit to last completion */
+    double frames_per_s;
+    int64_t batched_launches, graph_replays, eager_renders, overflow_retries;
+    size_t peak_bytes;
+} g4d_server_stats;
+
+g4d_status g4d_server_create(const g4d_server_config *cfg, g4d_server **out);
+/* Copies the scene into server-owned HBM; the caller's buffers may be
+ * freed afterwards.  Device pointers in G, P, M. */
+g4d_status g4d_server_add_scene(g4d_server *srv, const g4d_gaussians *G, const g4d_planes *P,
+                                const g4d_mlp *M, int32_t *scene_id);
+/* Non-blocking.  out_image: device [3][H][W] float32 owned by the caller,
+ * valid once g4d_server_wait returns G4D_OK for the ticket. */
+g4d_status g4d_server_submit(g4d_server *srv, int32_t scene_id, const g4d_camera *cam, float t,
+                             float *out_image, uint64_t *ticket);
+/* Blocks until the request completes; latency from submit to completion. */
+g4d_status g4d_server_wait(g4d_server *srv, uint64_t ticket, double *latency_ms);
+g4d_status g4d_server_drain(g4d_server *srv);
+g4d_status g4d_server_stats_get(g4d_server *srv, g4d_server_stats *out);
+g4d_status g4d_server_reset_stats(g4d_server *srv);
+g4d_status g4d_server_destroy(g4d_server *srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* G4D_H */

@@ -1,0 +1,454 @@
+// Gaussian deformation field on gfx950 (Sec. 4.2, Eq. 7-8).
+//
+// One thread block of 256 threads (four wave64s) deforms 64 Gaussians:
+//   A. HexPlane encoder (Eq. 7): for every scale and each of the six planes,
+//      an align-corners bilinear query at the canonical mean (and t), the
+//      element-wise product over the six planes, concatenation over scales.
+//      feat/4 lanes share one Gaussian and each loads float4 slices of the
+//      four channels-last corner rows, so a corner of a 32-feature plane is
+//      one 128-byte line read by eight lanes.  f_h stays in LDS.
+//   B. Feature merger h = ReLU(W1 f_h + b1) as a [64 x in] x [in x hidden]
+//      product on MFMA (v_mfma_f32_16x16x4_f32, or 16x16x32 bf16 with FP32
+//      accumulation in the bf16 mode); each wave owns 16 Gaussians.
+//   C. The three heads, concatenated into one [hidden x 16] matrix (rows
+//      dx 0-2, dr 3-6, ds 7-9, zero padding) on MFMA.
+//   D. Eq. 8 and activations: X + dX, exp(log s + ds), normalise(r + dr),
+//      sigmoid(opacity logit); structure-of-arrays stores.
+// A launch carries up to G4D_MAX_BATCH_JOBS jobs (continuous batching); a
+// block never mixes jobs, so a job's result does not depend on its batch.
+#include "g4d_internal.h"
+
+namespace g4d {
+
+struct DeformJob {
+    const float *means, *log_scales, *quats, *opac;
+    const float *planes[G4D_MAX_SCALES * 6];
+    const float *w1, *b1, *wx, *bx, *wr, *br, *ws, *bs;
+    float *out_means, *out_scales, *out_quats, *out_opac;
+    float *out_features;                 // non-null: write f_h and stop after phase A
+    int res[G4D_MAX_SCALES][4];
+    float gscale[G4D_MAX_SCALES][4];     // (res - 1) / (bmax - bmin) per axis; res_t - 1 for t
+    float bmin[3];
+    int n;
+    float t;
+    int block_begin;
+};
+
+struct DeformBatch {
+    int n_jobs;
+    DeformJob job[G4D_MAX_BATCH_JOBS];
+};
+
+namespace {
+
+constexpr int kGB = 64;        // Gaussians per block
+constexpr int kThreads = 256;
+
+typedef float float4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// Plane (a, b) axis pairs in storage order xy, xz, yz, xt, yt, zt.
+__device__ constexpr int plane_axis_a(int p) { return p == 2 ? 1 : (p == 5 ? 2 : (p == 4 ? 1 : 0)); }
+__device__ constexpr int plane_axis_b(int p) { return p == 0 ? 1 : (p == 1 || p == 2 ? 2 : 3); }
+
+// Align-corners grid coordinate: with u = 2 (x - bmin) / (bmax - bmin) - 1,
+// g = (u + 1) / 2 (n - 1) = (x - bmin) * scale, evaluated with two roundings.
+__device__ __forceinline__ void grid_coord(float x, float scale, int n, int &i0, float &w) {
+    float g = x * scale;
+    g = fminf(fmaxf(g, 0.0f), (float)(n - 1));
+    int i = (int)floorf(g);
+    i = min(i, n - 2);
+    i0 = i;
+    w = g - (float)i;
+}
+
+template <int F, int L, int HID, bool BF16>
+struct Smem {
+    static constexpr int K = F * L;                        // in_dim
+    static constexpr int KP = BF16 ? ((K + 31) / 32) * 32 : K;   // padded K
+    static constexpr int FH_LD = BF16 ? KP + 8 : K + 4;    // row strides (elements)
+    static constexpr int H_LD = BF16 ? HID + 8 : HID + 4;
+    static constexpr int W1_LD = FH_LD;
+    static constexpr int W2_LD = H_LD;
+    using E = typename std::conditional<BF16, uint16_t, float>::type;
+    static constexpr size_t fh_bytes = (size_t)kGB * FH_LD * sizeof(E);
+    static constexpr size_t h_bytes = (size_t)kGB * H_LD * sizeof(E);
+    static constexpr size_t act_bytes = fh_bytes > h_bytes ? fh_bytes : h_bytes;   // f_h, then h
+    static constexpr size_t w1_bytes = (size_t)HID * W1_LD * sizeof(E);
+    static constexpr size_t w2_bytes = (size_t)16 * W2_LD * sizeof(E);
+    static constexpr size_t delta_bytes = (size_t)kGB * 17 * sizeof(float);
+    static constexpr size_t bias_bytes = (size_t)(HID + 16) * sizeof(float);
+    static constexpr size_t total = act_bytes + w1_bytes + w2_bytes + delta_bytes + bias_bytes;
+};
+
+template <int F, int L, int HID, bool BF16>
+__global__ __launch_bounds__(kThreads) void k_deform(DeformBatch batch) {
+    using S = Smem<F, L, HID, BF16>;
+    using E = typename S::E;
+    constexpr int K = S::K;
+    constexpr int KP = S::KP;
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    E *s_act = reinterpret_cast<E *>(smem);
+    E *s_w1 = reinterpret_cast<E *>(smem + S::act_bytes);
+    E *s_w2 = reinterpret_cast<E *>(smem + S::act_bytes + S::w1_bytes);
+    float *s_delta = reinterpret_cast<float *>(smem + S::act_bytes + S::w1_bytes + S::w2_bytes);
+    float *s_b1 = s_delta + kGB * 17;
+    float *s_b2 = s_b1 + HID;
+
+    // job of this block
+    int j = 0;
+    for (int q = 1; q < batch.n_jobs; ++q)
+        if ((int)blockIdx.x >= batch.job[q].block_begin) j = q;
+    const DeformJob &job = batch.job[j];
+    const int g0 = ((int)blockIdx.x - job.block_begin) * kGB;
+    const int n = job.n;
+    const int tid = threadIdx.x;
+    const bool features_only = job.out_features != nullptr;
+
+    // ---- stage decoder weights (rows of W1; heads padded to 16 rows)
+    if (!features_only) {
+        for (int i = tid; i < HID * KP; i += kThreads) {
+            int r = i / KP, c = i - r * KP;
+            float v = c < K ? job.w1[r * K + c] : 0.0f;
+            if constexpr (BF16) s_w1[r * S::W1_LD + c] = f32_to_bf16_rne(v);
+            else s_w1[r * S::W1_LD + c] = v;
+        }
+        for (int i = tid; i < 16 * HID; i += kThreads) {
+            int r = i / HID, c = i - r * HID;
+            float v = 0.0f;
+            if (r < 3) v = job.wx[r * HID + c];
+            else if (r < 7) v = job.wr[(r - 3) * HID + c];
+            else if (r < 10) v = job.ws[(r - 7) * HID + c];
+            if constexpr (BF16) s_w2[r * S::W2_LD + c] = f32_to_bf16_rne(v);
+            else s_w2[r * S::W2_LD + c] = v;
+        }
+        for (int i = tid; i < HID; i += kThreads) s_b1[i] = job.b1[i];
+        if (tid < 16) {
+            float v = 0.0f;
+            if (tid < 3) v = job.bx[tid];
+            else if (tid < 7) v = job.br[tid - 3];
+            else if (tid < 10) v = job.bs[tid - 7];
+            s_b2[tid] = v;
+        }
+    }
+
+    // ---- A. encoder: f_h for 64 Gaussians
+    constexpr int LPG = F / 4;                 // lanes per Gaussian
+    constexpr int GPP = kThreads / LPG;        // Gaussians per pass
+#pragma unroll 1
+    for (int pass = 0; pass < kGB / GPP; ++pass) {
+        const int gl = pass * GPP + tid / LPG;
+        const int c4 = tid % LPG;
+        const int g = g0 + gl;
+        float x[4];   // offsets from the box corner; t for the time axis
+        const bool valid = g < n;
+        if (valid) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) x[k] = job.means[(size_t)k * n + g] - job.bmin[k];
+        } else {
+            x[0] = x[1] = x[2] = 0.0f;
+        }
+        x[3] = job.t;
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            float4 prod = make_float4(1.0f, 1.0f, 1.0f, 1.0f);
+#pragma unroll
+            for (int p = 0; p < 6; ++p) {
+                const int a = plane_axis_a(p), b = plane_axis_b(p);
+                const int na = job.res[l][a], nb = job.res[l][b];
+                int ia, ib;
+                float wa, wb;
+                grid_coord(x[a], job.gscale[l][a], na, ia, wa);
+                grid_coord(x[b], job.gscale[l][b], nb, ib, wb);
+                const float *base = job.planes[l * 6 + p] + ((size_t)ib * na + ia) * F + 4 * c4;
+                const float4 v00 = *reinterpret_cast<const float4 *>(base);
+                const float4 v10 = *reinterpret_cast<const float4 *>(base + F);
+                const float4 v01 = *reinterpret_cast<const float4 *>(base + (size_t)na * F);
+                const float4 v11 = *reinterpret_cast<const float4 *>(base + (size_t)na * F + F);
+                const float w00 = (1.0f - wa) * (1.0f - wb), w10 = wa * (1.0f - wb);
+                const float w01 = (1.0f - wa) * wb, w11 = wa * wb;
+                prod.x *= w00 * v00.x + w10 * v10.x + w01 * v01.x + w11 * v11.x;
+                prod.y *= w00 * v00.y + w10 * v10.y + w01 * v01.y + w11 * v11.y;
+                prod.z *= w00 * v00.z + w10 * v10.z + w01 * v01.z + w11 * v11.z;
+                prod.w *= w00 * v00.w + w10 * v10.w + w01 * v01.w + w11 * v11.w;
+            }
+            if (!valid) prod = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            const int col = l * F + 4 * c4;
+            if (features_only) {
+                if (valid)
+                    *reinterpret_cast<float4 *>(job.out_features + (size_t)g * K + col) = prod;
+            } else if constexpr (BF16) {
+                uint16_t *dst = reinterpret_cast<uint16_t *>(s_act) + gl * S::FH_LD + col;
+                dst[0] = f32_to_bf16_rne(prod.x);
+                dst[1] = f32_to_bf16_rne(prod.y);
+                dst[2] = f32_to_bf16_rne(prod.z);
+                dst[3] = f32_to_bf16_rne(prod.w);
+            } else {
+                *reinterpret_cast<float4 *>(reinterpret_cast<float *>(s_act) + gl * S::FH_LD + col) = prod;
+            }
+        }
+    }
+    if (features_only) return;
+    if constexpr (BF16 && KP > K) {
+        // zero the padding columns K..KP of f_h
+        for (int i = tid; i < kGB * (KP - K); i += kThreads) {
+            int r = i / (KP - K), c = K + i % (KP - K);
+            s_act[r * S::FH_LD + c] = 0;
+        }
+    }
+    __syncthreads();
+
+    const int wave = tid >> 6;
+    const int lane = tid & 63;
+    const int lrow = lane & 15;        // row (A) / column (B) inside a 16x16 tile
+    const int lk = lane >> 4;          // k group of this lane
+    const int row0 = wave * 16;        // this wave's Gaussians
+
+    // ---- B. h = ReLU(W1 f_h + b1)
+    float4_t acc[HID / 16];
+#pragma unroll
+    for (int c = 0; c < HID / 16; ++c) acc[c] = float4_t{0.0f, 0.0f, 0.0f, 0.0f};
+    if constexpr (!BF16) {
+        const float *fh = reinterpret_cast<const float *>(s_act);
+        const float *w1 = reinterpret_cast<const float *>(s_w1);
+#pragma unroll 4
+        for (int kk = 0; kk < K / 4; ++kk) {
+            const float a = fh[(row0 + lrow) * S::FH_LD + kk * 4 + lk];
+#pragma unroll
+            for (int c = 0; c < HID / 16; ++c) {
+                const float b = w1[(c * 16 + lrow) * S::W1_LD + kk * 4 + lk];
+                acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[c], 0, 0, 0);
+            }
+        }
+    } else {
+        const uint16_t *fh = reinterpret_cast<const uint16_t *>(s_act);
+        const uint16_t *w1 = reinterpret_cast<const uint16_t *>(s_w1);
+#pragma unroll
+        for (int kk = 0; kk < KP / 32; ++kk) {
+            const bf16x8_t a = *reinterpret_cast<const bf16x8_t *>(fh + (row0 + lrow) * S::FH_LD + kk * 32 + lk * 8);
+#pragma unroll
+            for (int c = 0; c < HID / 16; ++c) {
+                const bf16x8_t b = *reinterpret_cast<const bf16x8_t *>(w1 + (c * 16 + lrow) * S::W1_LD + kk * 32 + lk * 8);
+                acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[c], 0, 0, 0);
+            }
+        }
+    }
+    __syncthreads();   // all waves done reading f_h before h overwrites it
+    // bias + ReLU; lane holds rows row0 + 4*lk + i of column c*16 + lrow
+#pragma unroll
+    for (int c = 0; c < HID / 16; ++c) {
+        const int col = c * 16 + lrow;
+        const float bias = s_b1[col];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float h = fmaxf(acc[c][i] + bias, 0.0f);
+            const int row = row0 + 4 * lk + i;
+            if constexpr (BF16) reinterpret_cast<uint16_t *>(s_act)[row * S::H_LD + col] = f32_to_bf16_rne(h);
+            else reinterpret_cast<float *>(s_act)[row * S::H_LD + col] = h;
+        }
+    }
+    __syncthreads();
+
+    // ---- C. heads: delta[64 x 16] = h W2^T + b2
+    float4_t acc2 = float4_t{0.0f, 0.0f, 0.0f, 0.0f};
+    if constexpr (!BF16) {
+        const float *hs = reinterpret_cast<const float *>(s_act);
+        const float *w2 = reinterpret_cast<const float *>(s_w2);
+#pragma unroll 4
+        for (int kk = 0; kk < HID / 4; ++kk) {
+            const float a = hs[(row0 + lrow) * S::H_LD + kk * 4 + lk];
+            const float b = w2[lrow * S::W2_LD + kk * 4 + lk];
+            acc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc2, 0, 0, 0);
+        }
+    } else {
+        const uint16_t *hs = reinterpret_cast<const uint16_t *>(s_act);
+        const uint16_t *w2 = reinterpret_cast<const uint16_t *>(s_w2);
+#pragma unroll
+        for (int kk = 0; kk < HID / 32; ++kk) {
+            const bf16x8_t a = *reinterpret_cast<const bf16x8_t *>(hs + (row0 + lrow) * S::H_LD + kk * 32 + lk * 8);
+            const bf16x8_t b = *reinterpret_cast<const bf16x8_t *>(w2 + lrow * S::W2_LD + kk * 32 + lk * 8);
+            acc2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc2, 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) s_delta[(row0 + 4 * lk + i) * 17 + lrow] = acc2[i] + s_b2[lrow];
+    __syncthreads();
+
+    // ---- D. Eq. 8 + activations
+    if (tid < kGB) {
+        const int g = g0 + tid;
+        if (g < n) {
+            const float *d = s_delta + tid * 17;
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                job.out_means[(size_t)k * n + g] = job.means[(size_t)k * n + g] + d[k];
+            float q[4];
+            float qn = 0.0f;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                q[k] = job.quats[(size_t)k * n + g] + d[3 + k];
+                qn += q[k] * q[k];
+            }
+            if (qn > 0.0f) {
+                const float inv = 1.0f / sqrtf(qn);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) job.out_quats[(size_t)k * n + g] = q[k] * inv;
+            } else {
+                job.out_quats[g] = 1.0f;
+#pragma unroll
+                for (int k = 1; k < 4; ++k) job.out_quats[(size_t)k * n + g] = 0.0f;
+            }
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                job.out_scales[(size_t)k * n + g] = expf(job.log_scales[(size_t)k * n + g] + d[7 + k]);
+            job.out_opac[g] = 1.0f / (1.0f + expf(-job.opac[g]));
+        }
+    }
+}
+
+using DeformKernel = void (*)(DeformBatch);
+
+struct KernelEntry {
+    int feat, scales, hidden, bf16;
+    DeformKernel fn;
+    size_t smem;
+};
+
+#define G4D_DEFORM_ENTRY(F, L, H, B) {F, L, H, B, k_deform<F, L, H, (bool)B>, Smem<F, L, H, (bool)B>::total}
+
+const KernelEntry kDeformKernels[] = {
+    G4D_DEFORM_ENTRY(16, 1, 32, 0), G4D_DEFORM_ENTRY(16, 1, 64, 0), G4D_DEFORM_ENTRY(16, 1, 128, 0),
+    G4D_DEFORM_ENTRY(16, 2, 64, 0), G4D_DEFORM_ENTRY(16, 3, 64, 0),
+    G4D_DEFORM_ENTRY(32, 1, 64, 0), G4D_DEFORM_ENTRY(32, 2, 64, 0), G4D_DEFORM_ENTRY(32, 2, 128, 0),
+    G4D_DEFORM_ENTRY(32, 3, 64, 0), G4D_DEFORM_ENTRY(32, 3, 128, 0),
+    G4D_DEFORM_ENTRY(16, 1, 32, 1), G4D_DEFORM_ENTRY(16, 1, 64, 1), G4D_DEFORM_ENTRY(16, 1, 128, 1),
+    G4D_DEFORM_ENTRY(16, 2, 64, 1), G4D_DEFORM_ENTRY(16, 3, 64, 1),
+    G4D_DEFORM_ENTRY(32, 1, 64, 1), G4D_DEFORM_ENTRY(32, 2, 64, 1), G4D_DEFORM_ENTRY(32, 2, 128, 1),
+    G4D_DEFORM_ENTRY(32, 3, 64, 1), G4D_DEFORM_ENTRY(32, 3, 128, 1),
+};
+
+const KernelEntry *find_kernel(int feat, int scales, int hidden, int bf16) {
+    for (const auto &e : kDeformKernels)
+        if (e.feat == feat && e.scales == scales && e.hidden == hidden && e.bf16 == bf16) return &e;
+    return nullptr;
+}
+
+bool planes_ok(const g4d_planes *P) {
+    if (!P || P->n_scales < 1 || P->n_scales > 3 || (P->feat != 16 && P->feat != 32)) return false;
+    for (int k = 0; k < 3; ++k)
+        if (!(P->bmax[k] > P->bmin[k])) return false;
+    for (int l = 0; l < P->n_scales; ++l) {
+        for (int k = 0; k < 4; ++k)
+            if (P->res[l][k] < 2 || P->res[l][k] > 65536) return false;
+        for (int p = 0; p < 6; ++p)
+            if (!P->plane[l][p] || (reinterpret_cast<uintptr_t>(P->plane[l][p]) & 15)) return false;
+    }
+    return true;
+}
+
+g4d_status fill_job(const g4d_gaussians *G, const g4d_planes *P, const g4d_mlp *M, float t,
+                    g4d_splats *out, float *features, DeformJob *J) {
+    if (!G || !P || G->n < 0 || !planes_ok(P)) return G4D_EINVAL;
+    if (!(t >= 0.0f && t <= 1.0f)) return G4D_EINVAL;
+    if (G->n > 0 && (!G->means || !G->log_scales || !G->quats || !G->opacity_logits)) return G4D_EINVAL;
+    *J = DeformJob{};
+    J->means = G->means; J->log_scales = G->log_scales; J->quats = G->quats;
+    J->opac = G->opacity_logits;
+    for (int l = 0; l < P->n_scales; ++l) {
+        for (int p = 0; p < 6; ++p) J->planes[l * 6 + p] = P->plane[l][p];
+        for (int k = 0; k < 4; ++k) J->res[l][k] = P->res[l][k];
+        for (int k = 0; k < 3; ++k)
+            J->gscale[l][k] = (float)((double)(P->res[l][k] - 1) / ((double)P->bmax[k] - (double)P->bmin[k]));
+        J->gscale[l][3] = (float)(P->res[l][3] - 1);
+    }
+    for (int k = 0; k < 3; ++k) J->bmin[k] = P->bmin[k];
+    J->n = G->n;
+    J->t = t;
+    J->out_features = features;
+    if (!features) {
+        if (!M || !out || out->n != G->n) return G4D_EINVAL;
+        if (M->in_dim != P->feat * P->n_scales) return G4D_EINVAL;
+        if (G->n > 0 && (!out->means || !out->scales || !out->quats || !out->opacity)) return G4D_EINVAL;
+        if (!M->w1 || !M->b1 || !M->wx || !M->bx || !M->wr || !M->br || !M->ws || !M->bs) return G4D_EINVAL;
+        J->w1 = M->w1; J->b1 = M->b1; J->wx = M->wx; J->bx = M->bx;
+        J->wr = M->wr; J->br = M->br; J->ws = M->ws; J->bs = M->bs;
+        J->out_means = out->means; J->out_scales = out->scales;
+        J->out_quats = out->quats; J->out_opac = out->opacity;
+    }
+    return G4D_OK;
+}
+
+g4d_status launch(DeformBatch &B, const KernelEntry *ke, hipStream_t s) {
+    int blocks = 0;
+    for (int j = 0; j < B.n_jobs; ++j) {
+        B.job[j].block_begin = blocks;
+        blocks += (B.job[j].n + kGB - 1) / kGB;
+    }
+    if (blocks == 0) return G4D_OK;
+    static bool attr_done[sizeof(kDeformKernels) / sizeof(kDeformKernels[0])] = {};
+    size_t idx = (size_t)(ke - kDeformKernels);
+    if (!attr_done[idx]) {
+        G4D_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void *>(ke->fn),
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)ke->smem));
+        attr_done[idx] = true;
+    }
+    hipLaunchKernelGGL(ke->fn, dim3(blocks), dim3(kThreads), ke->smem, s, B);
+    G4D_HIP_CHECK(hipGetLastError());
+    return G4D_OK;
+}
+
+}  // namespace
+
+g4d_status deform_batched(const g4d_deform_job *jobs, int n_jobs, hipStream_t s) {
+    if (!jobs || n_jobs < 1 || n_jobs > G4D_MAX_BATCH_JOBS) return G4D_EINVAL;
+    DeformBatch B{};
+    B.n_jobs = n_jobs;
+    const KernelEntry *ke = nullptr;
+    for (int j = 0; j < n_jobs; ++j) {
+        const g4d_deform_job &q = jobs[j];
+        if (!q.M || !q.P) return G4D_EINVAL;
+        g4d_status st = fill_job(q.G, q.P, q.M, q.t, q.out, nullptr, &B.job[j]);
+        if (st != G4D_OK) return st;
+        const KernelEntry *e = find_kernel(q.P->feat, q.P->n_scales, q.M->hidden,
+                                           q.M->precision == G4D_MLP_BF16 ? 1 : 0);
+        if (!e || (q.M->precision != G4D_MLP_F32 && q.M->precision != G4D_MLP_BF16)) return G4D_EUNSUPPORTED;
+        if (ke && e != ke) return G4D_EINVAL;   // one shape class per launch
+        ke = e;
+    }
+    return launch(B, ke, s);
+}
+
+g4d_status deform_features(const g4d_gaussians *G, const g4d_planes *P, float t, float *features,
+                           hipStream_t s) {
+    if (!features && G && G->n > 0) return G4D_EINVAL;
+    DeformBatch B{};
+    B.n_jobs = 1;
+    g4d_status st = fill_job(G, P, nullptr, t, nullptr, features, &B.job[0]);
+    if (st != G4D_OK) return st;
+    const KernelEntry *e = find_kernel(P->feat, P->n_scales, 64, 0);
+    if (!e) return G4D_EUNSUPPORTED;
+    return launch(B, e, s);
+}
+
+}  // namespace g4d
+
+extern "C" g4d_status g4d_deform(const g4d_gaussians *G, const g4d_planes *P, const g4d_mlp *M,
+                                 float t, g4d_splats *out, void *stream) {
+    g4d_deform_job j{G, P, M, t, out};
+    return g4d::deform_batched(&j, 1, reinterpret_cast<hipStream_t>(stream));
+}
+
+extern "C" g4d_status g4d_deform_batched(const g4d_deform_job *jobs, int32_t n_jobs, void *stream) {
+    return g4d::deform_batched(jobs, n_jobs, reinterpret_cast<hipStream_t>(stream));
+}
+
+extern "C" g4d_status g4d_deform_features(const g4d_gaussians *G, const g4d_planes *P, float t,
+                                          float *features, void *stream) {
+    return g4d::deform_features(G, P, t, features, reinterpret_cast<hipStream_t>(stream));
+}

@@ -1,0 +1,146 @@
+// Internal definitions shared by the HIP translation units of libg4d.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <type_traits>
+
+#include "../../include/g4d.h"
+
+namespace g4d {
+
+constexpr int kTile = G4D_TILE;              // 16x16 pixel tiles
+constexpr int kTilePixels = kTile * kTile;   // one blend block per tile
+
+// Radix-sort tiling: 256 threads x 16 items per block.
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortThreads * kSortItems;   // 4096 keys per block
+constexpr int kScanTile = 256 * 16;                    // 4096 values per scan block
+
+// Lookback status words: flag in the top two bits, value in the low 30.
+constexpr uint32_t kFlagShift = 30;
+constexpr uint32_t kValueMask = (1u << kFlagShift) - 1u;
+constexpr uint32_t kFlagAggregate = 1u;
+constexpr uint32_t kFlagInclusive = 2u;
+constexpr uint32_t kSpinLimit = 1u << 22;    // bounded wait: gives up and flags an error
+
+// Device status block at the start of the workspace.
+struct DevStatus {
+    unsigned long long k_total;      // instances the frame needs
+    uint32_t k_used;                 // min(k_total, capacity)
+    uint32_t overflow;
+    uint32_t sort_error;
+    uint32_t visible;
+    uint32_t tiles;
+    uint32_t passes;
+    uint32_t tile_counter[16];       // onesweep tile tickets, one per sort pass / scan
+    unsigned long long blend_evals;  // (pixel, Gaussian) pairs evaluated by the blend
+};
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+inline int ceil_log2(uint32_t x) {
+    int b = 0;
+    while ((1u << b) < x) ++b;
+    return b;
+}
+
+// Byte offsets of every array in a render workspace.  The first `zero_bytes`
+// bytes are cleared at the start of each render.
+struct WsLayout {
+    int32_t n_max, w_max, h_max;
+    int64_t cap;
+    int32_t tiles_max;
+    int32_t nblk_n;      // sort blocks over n
+    int32_t nblk_k;      // sort blocks over capacity
+    int32_t nscan;       // scan blocks over n
+    size_t status, depth_hist, tile_hist, lb_depth, lb_tile, lb_scan, ranges;
+    size_t zero_bytes;
+    size_t cam;
+    size_t recA, recB, recC, rect, touched, dgid, dk0, dk1, dv0, dv1, offsets, tk0, tk1, tv0, tv1;
+    size_t total;
+};
+
+inline bool make_layout(int32_t n, int32_t w, int32_t h, int64_t cap, WsLayout *L) {
+    if (n < 0 || n > (1 << 26) || w < 1 || h < 1 || w > 4096 || h > 4096 || cap < 1 ||
+        cap >= (int64_t(1) << 30))
+        return false;
+    L->n_max = n; L->w_max = w; L->h_max = h; L->cap = cap;
+    int tx = (w + kTile - 1) / kTile, ty = (h + kTile - 1) / kTile;
+    L->tiles_max = tx * ty;
+    int32_t nn = n > 0 ? n : 1;
+    L->nblk_n = (nn + kSortTile - 1) / kSortTile;
+    L->nblk_k = (int32_t)((cap + kSortTile - 1) / kSortTile);
+    L->nscan = (nn + kScanTile - 1) / kScanTile;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes, 256); return r; };
+    L->status = take(sizeof(DevStatus));
+    L->depth_hist = take(4 * 256 * 4);
+    L->tile_hist = take(2 * 256 * 4);
+    L->lb_depth = take((size_t)4 * L->nblk_n * 256 * 4);
+    L->lb_tile = take((size_t)2 * L->nblk_k * 256 * 4);
+    L->lb_scan = take((size_t)L->nscan * 8);
+    L->ranges = take((size_t)L->tiles_max * 8);
+    L->zero_bytes = o;
+    L->cam = take(256);
+    L->recA = take((size_t)nn * 16);
+    L->recB = take((size_t)nn * 16);
+    L->recC = take((size_t)nn * 4);
+    L->rect = take((size_t)nn * 8);
+    L->touched = take((size_t)nn * 4);
+    L->dgid = take((size_t)nn * 4);
+    L->dk0 = take((size_t)nn * 4);
+    L->dk1 = take((size_t)nn * 4);
+    L->dv0 = take((size_t)nn * 4);
+    L->dv1 = take((size_t)nn * 4);
+    L->offsets = take((size_t)nn * 8);
+    L->tk0 = take((size_t)cap * 4);
+    L->tk1 = take((size_t)cap * 4);
+    L->tv0 = take((size_t)cap * 4);
+    L->tv1 = take((size_t)cap * 4);
+    L->total = o;
+    return true;
+}
+
+// Sort-pass plan for the tile ids of a frame with `tiles` tiles: digit
+// widths of at most 8 bits, balanced over the passes.
+struct TilePassPlan {
+    int passes;
+    int shift[2];
+    int bits[2];
+};
+
+inline TilePassPlan tile_pass_plan(int tiles) {
+    TilePassPlan p{};
+    int b = ceil_log2((uint32_t)(tiles > 1 ? tiles : 2));
+    if (b <= 8) {
+        p.passes = 1; p.shift[0] = 0; p.bits[0] = b;
+    } else {
+        p.passes = 2;
+        p.bits[0] = (b + 1) / 2; p.shift[0] = 0;
+        p.bits[1] = b - p.bits[0]; p.shift[1] = p.bits[0];
+    }
+    return p;
+}
+
+// Host-side error plumbing.
+void set_hip_error(hipError_t e);
+
+// Stage events of the calling thread (null when off).
+constexpr int kStageEvents = 9;
+hipEvent_t stage_event(int i);
+
+}  // namespace g4d
+
+#define G4D_HIP_CHECK(expr)                                   \
+    do {                                                      \
+        hipError_t _e = (expr);                               \
+        if (_e != hipSuccess) {                               \
+            g4d::set_hip_error(_e);                           \
+            return G4D_EHIP;                                  \
+        }                                                     \
+    } while (0)

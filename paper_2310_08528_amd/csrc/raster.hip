@@ -1,0 +1,895 @@
+// Tile rasterizer of the splatting renderer S(M, G') on gfx950
+// (Sec. 3.1, Eq. 1-4; Sec. 4.1).
+//
+// Pipeline per frame (all on one stream, no host synchronisation):
+//   k_zero        clear status words, digit histograms, look-back state, tile ranges
+//   k_preprocess  per Gaussian: EWA projection (Eq. 2-3), cull, radius, tile
+//                 rectangle, depth key, conic, SH colour; depth digit histograms
+//   k_sort_pass x4  stable LSD radix sort of (depth bits, index) over Gaussians
+//   k_scan_offsets  exclusive scan of tiles-per-Gaussian in depth order -> K
+//   k_emit        one (tile id, Gaussian) instance per touched tile, in depth order
+//   k_sort_pass x1-2  stable LSD radix sort of the instances by tile id
+//   k_ranges      [start, end) of every tile in the sorted list
+//   k_blend       one 256-thread block per 16x16 tile: front-to-back compositing
+//                 (Eq. 1, Eq. 4) over LDS-staged batches with early exit
+//
+// Sorting the depth digits before the fan-out to tiles is the same LSD radix
+// sort of the 64-bit key (tile << 32) | depth_bits: every instance of a
+// Gaussian carries the same depth digits, so the low-digit passes can run
+// once per Gaussian (N keys) instead of once per instance (K keys); the
+// remaining passes sort K instances by the tile digits only, stably.
+//
+// This translation unit is compiled without FMA contraction, with correctly
+// rounded division and square root and without denormal flushing: the
+// discrete structure (cull, radius, rectangle, depth key) and the per-pixel
+// skip/stop decisions are fixed binary32 operation sequences.
+#include "g4d_internal.h"
+
+#include <vector>
+
+namespace g4d {
+namespace {
+
+// ---------------------------------------------------------------- helpers
+
+__device__ __forceinline__ uint32_t atomic_load_u32(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void atomic_store_u32(uint32_t *p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long atomic_load_u64(const unsigned long long *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void atomic_store_u64(unsigned long long *p, unsigned long long v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt64() {
+    const int lane = __lane_id();
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Camera as the kernels read it.  It lives in the workspace: the first
+// kernel of a render (k_zero) writes it from its launch argument, so a
+// captured render graph changes view through that one node's parameters.
+struct CamK {
+    float v[12];
+    float fx, fy, cx, cy, tanx, tany, near_plane;
+    float campos[3];
+    float bg[3];
+    int width, height, tiles_x, tiles_y;
+};
+
+// ---------------------------------------------------------------- k_zero
+
+__global__ void k_zero(uint4 *__restrict__ p, size_t n16, CamK cam, CamK *__restrict__ camd) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *camd = cam;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+// ---------------------------------------------------------------- k_preprocess
+
+// Real SH basis constants (degree <= 3), Cartesian form on a unit direction.
+#define SH_C0 0.28209479177387814f
+#define SH_C1 0.4886025119029199f
+
+__device__ __forceinline__ float3 sh_colour(int deg, const float *__restrict__ sh, int n, int g, float x, float y,
+                                            float z) {
+    float3 c;
+    const size_t cs = (size_t)n;          // channel stride
+    const size_t ks = (size_t)3 * n;      // coefficient stride
+    auto coef = [&](int k, int ch) { return sh[(size_t)k * ks + ch * cs + g]; };
+    float r = SH_C0 * coef(0, 0), gg = SH_C0 * coef(0, 1), b = SH_C0 * coef(0, 2);
+    if (deg >= 1) {
+        const float y1 = -SH_C1 * y, y2 = SH_C1 * z, y3 = -SH_C1 * x;
+        r += y1 * coef(1, 0) + y2 * coef(2, 0) + y3 * coef(3, 0);
+        gg += y1 * coef(1, 1) + y2 * coef(2, 1) + y3 * coef(3, 1);
+        b += y1 * coef(1, 2) + y2 * coef(2, 2) + y3 * coef(3, 2);
+        if (deg >= 2) {
+            const float xx = x * x, yy = y * y, zz = z * z, xy = x * y, yz = y * z, xz = x * z;
+            const float Y[5] = {1.0925484305920792f * xy, -1.0925484305920792f * yz,
+                                0.31539156525252005f * (2.0f * zz - xx - yy), -1.0925484305920792f * xz,
+                                0.5462742152960396f * (xx - yy)};
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                r += Y[k] * coef(4 + k, 0);
+                gg += Y[k] * coef(4 + k, 1);
+                b += Y[k] * coef(4 + k, 2);
+            }
+            if (deg >= 3) {
+                const float Z[7] = {-0.5900435899266435f * y * (3.0f * xx - yy),
+                                    2.890611442640554f * xy * z,
+                                    -0.4570457994644658f * y * (4.0f * zz - xx - yy),
+                                    0.3731763325901154f * z * (2.0f * zz - 3.0f * xx - 3.0f * yy),
+                                    -0.4570457994644658f * x * (4.0f * zz - xx - yy),
+                                    1.445305721320277f * z * (xx - yy),
+                                    -0.5900435899266435f * x * (xx - 3.0f * yy)};
+#pragma unroll
+                for (int k = 0; k < 7; ++k) {
+                    r += Z[k] * coef(9 + k, 0);
+                    gg += Z[k] * coef(9 + k, 1);
+                    b += Z[k] * coef(9 + k, 2);
+                }
+            }
+        }
+    }
+    c.x = fmaxf(r + 0.5f, 0.0f);
+    c.y = fmaxf(gg + 0.5f, 0.0f);
+    c.z = fmaxf(b + 0.5f, 0.0f);
+    return c;
+}
+
+__global__ __launch_bounds__(256) void k_preprocess(int n, int sh_degree, const float *__restrict__ means,
+                                                    const float *__restrict__ scales,
+                                                    const float *__restrict__ quats,
+                                                    const float *__restrict__ opac, const float *__restrict__ sh,
+                                                    const CamK *__restrict__ camd, float4 *__restrict__ recA,
+                                                    float4 *__restrict__ recB,
+                                                    float *__restrict__ recC, uint2 *__restrict__ rect,
+                                                    uint32_t *__restrict__ touched, uint32_t *__restrict__ dkeys,
+                                                    uint32_t *__restrict__ depth_hist, DevStatus *__restrict__ st) {
+    __shared__ uint32_t h[4][256];
+    for (int i = threadIdx.x; i < 4 * 256; i += blockDim.x) (&h[0][0])[i] = 0;
+    __syncthreads();
+    const CamK cam = *camd;
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    bool vis = false;
+    if (g < n) {
+        uint32_t key = 0xffffffffu, cnt = 0;
+        uint2 rc = make_uint2(0u, 0u);
+        float4 A = make_float4(0.f, 0.f, 0.f, 0.f), B = A;
+        float Cb = 0.0f;
+        const float mx = means[g], my = means[(size_t)n + g], mz = means[2 * (size_t)n + g];
+        const float sx = scales[g], sy = scales[(size_t)n + g], sz = scales[2 * (size_t)n + g];
+        const float qw = quats[g], qx = quats[(size_t)n + g], qy = quats[2 * (size_t)n + g],
+                    qz = quats[3 * (size_t)n + g];
+        const bool finite = isfinite(mx) && isfinite(my) && isfinite(mz) && isfinite(sx) && isfinite(sy) &&
+                            isfinite(sz) && isfinite(qw) && isfinite(qx) && isfinite(qy) && isfinite(qz);
+        const float *V = cam.v;
+        const float px = ((V[0] * mx + V[1] * my) + V[2] * mz) + V[3];
+        const float py = ((V[4] * mx + V[5] * my) + V[6] * mz) + V[7];
+        const float pz = ((V[8] * mx + V[9] * my) + V[10] * mz) + V[11];
+        if (finite && pz > cam.near_plane) {
+            // Eq. 2: Sigma = R S S^T R^T
+            const float xx = qx * qx, yy = qy * qy, zz = qz * qz;
+            const float xy = qx * qy, xz = qx * qz, yz = qy * qz;
+            const float wx = qw * qx, wy = qw * qy, wz = qw * qz;
+            const float R00 = 1.0f - 2.0f * (yy + zz), R01 = 2.0f * (xy - wz), R02 = 2.0f * (xz + wy);
+            const float R10 = 2.0f * (xy + wz), R11 = 1.0f - 2.0f * (xx + zz), R12 = 2.0f * (yz - wx);
+            const float R20 = 2.0f * (xz - wy), R21 = 2.0f * (yz + wx), R22 = 1.0f - 2.0f * (xx + yy);
+            const float M00 = R00 * sx, M01 = R01 * sy, M02 = R02 * sz;
+            const float M10 = R10 * sx, M11 = R11 * sy, M12 = R12 * sz;
+            const float M20 = R20 * sx, M21 = R21 * sy, M22 = R22 * sz;
+            const float S00 = (M00 * M00 + M01 * M01) + M02 * M02;
+            const float S01 = (M00 * M10 + M01 * M11) + M02 * M12;
+            const float S02 = (M00 * M20 + M01 * M21) + M02 * M22;
+            const float S11 = (M10 * M10 + M11 * M11) + M12 * M12;
+            const float S12 = (M10 * M20 + M11 * M21) + M12 * M22;
+            const float S22 = (M20 * M20 + M21 * M21) + M22 * M22;
+            // Eq. 3: Sigma' = J W Sigma W^T J^T, J at the (clamped) camera-space mean
+            const float limx = 1.3f * cam.tanx, limy = 1.3f * cam.tany;
+            const float rx = px / pz, ry = py / pz;
+            const float tx = fminf(limx, fmaxf(-limx, rx)) * pz;
+            const float ty = fminf(limy, fmaxf(-limy, ry)) * pz;
+            const float z2 = pz * pz;
+            const float j00 = cam.fx / pz, j02 = -((cam.fx * tx) / z2);
+            const float j11 = cam.fy / pz, j12 = -((cam.fy * ty) / z2);
+            const float T00 = j00 * V[0] + j02 * V[8], T01 = j00 * V[1] + j02 * V[9], T02 = j00 * V[2] + j02 * V[10];
+            const float T10 = j11 * V[4] + j12 * V[8], T11 = j11 * V[5] + j12 * V[9], T12 = j11 * V[6] + j12 * V[10];
+            const float U00 = (T00 * S00 + T01 * S01) + T02 * S02;
+            const float U01 = (T00 * S01 + T01 * S11) + T02 * S12;
+            const float U02 = (T00 * S02 + T01 * S12) + T02 * S22;
+            const float U10 = (T10 * S00 + T11 * S01) + T12 * S02;
+            const float U11 = (T10 * S01 + T11 * S11) + T12 * S12;
+            const float U12 = (T10 * S02 + T11 * S12) + T12 * S22;
+            float ca = (U00 * T00 + U01 * T01) + U02 * T02;
+            const float cb = (U00 * T10 + U01 * T11) + U02 * T12;
+            float cc = (U10 * T10 + U11 * T11) + U12 * T12;
+            ca = ca + 0.3f;
+            cc = cc + 0.3f;
+            const float det = ca * cc - cb * cb;
+            if (det > 0.0f) {
+                const float mid = 0.5f * (ca + cc);
+                const float disc = fmaxf(0.1f, mid * mid - det);
+                const float lam = mid + sqrtf(disc);
+                const float rad = ceilf(3.0f * sqrtf(lam));
+                const float u = cam.fx * rx + cam.cx;
+                const float v = cam.fy * ry + cam.cy;
+                if (isfinite(u) && isfinite(v) && isfinite(rad)) {
+                    const float fx0 = floorf((u - rad) * 0.0625f);
+                    const float fx1 = floorf((u + rad) * 0.0625f) + 1.0f;
+                    const float fy0 = floorf((v - rad) * 0.0625f);
+                    const float fy1 = floorf((v + rad) * 0.0625f) + 1.0f;
+                    const int x0 = (int)fminf(fmaxf(fx0, 0.0f), (float)cam.tiles_x);
+                    const int x1 = (int)fminf(fmaxf(fx1, 0.0f), (float)cam.tiles_x);
+                    const int y0 = (int)fminf(fmaxf(fy0, 0.0f), (float)cam.tiles_y);
+                    const int y1 = (int)fminf(fmaxf(fy1, 0.0f), (float)cam.tiles_y);
+                    if (x1 > x0 && y1 > y0) {
+                        vis = true;
+                        cnt = (uint32_t)((x1 - x0) * (y1 - y0));
+                        rc = make_uint2((uint32_t)x0 | ((uint32_t)y0 << 16), (uint32_t)x1 | ((uint32_t)y1 << 16));
+                        key = __float_as_uint(pz);
+                        const float inv = 1.0f / det;
+                        const float cA = cc * inv, cB = -(cb * inv), cC = ca * inv;
+                        // view-dependent colour from SH at the deformed mean
+                        float dx = mx - cam.campos[0], dy = my - cam.campos[1], dz = mz - cam.campos[2];
+                        const float il = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+                        dx *= il; dy *= il; dz *= il;
+                        const float3 col = sh_colour(sh_degree, sh, n, g, dx, dy, dz);
+                        A = make_float4(u, v, -0.5f * cA, -0.5f * cC);
+                        B = make_float4(-cB, opac[g], col.x, col.y);
+                        Cb = col.z;
+                    }
+                }
+            }
+        }
+        recA[g] = A;
+        recB[g] = B;
+        recC[g] = Cb;
+        rect[g] = rc;
+        touched[g] = cnt;
+        dkeys[g] = key;   // per-Gaussian depth key (kept for export and as the first sort input)
+        atomicAdd(&h[0][key & 255u], 1u);
+        atomicAdd(&h[1][(key >> 8) & 255u], 1u);
+        atomicAdd(&h[2][(key >> 16) & 255u], 1u);
+        atomicAdd(&h[3][key >> 24], 1u);
+    }
+    const uint64_t vb = __ballot(vis);
+    if (__lane_id() == 0 && vb) atomicAdd(&st->visible, (uint32_t)__popcll(vb));
+    __syncthreads();
+    for (int i = threadIdx.x; i < 4 * 256; i += blockDim.x) {
+        const uint32_t c = (&h[0][0])[i];
+        if (c) atomicAdd(&depth_hist[i], c);
+    }
+}
+
+// ---------------------------------------------------------------- k_sort_pass
+//
+// One stable LSD radix pass over (key, value) pairs with a `bits`-wide digit
+// at `shift` (onesweep: global digit counts are known in advance; blocks take
+// tiles in launch order from a ticket counter and chain their per-digit
+// counts through a decoupled look-back).  Each wave ranks a contiguous 1024-
+// key sub-tile: wave-wide digit matching with ballots, running per-wave digit
+// counters in LDS.  Waits are bounded; a wait that gives up sets sort_error.
+
+__global__ __launch_bounds__(kSortThreads) void k_sort_pass(
+    const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
+    uint32_t *__restrict__ vout, const uint32_t *__restrict__ d_count, uint32_t count_max, int shift, int bits,
+    const uint32_t *__restrict__ ghist, uint32_t *__restrict__ lookback, uint32_t *__restrict__ ticket,
+    uint32_t *__restrict__ err) {
+    __shared__ uint32_t s_wcnt[4][256];
+    __shared__ uint32_t s_base[256];
+    __shared__ uint32_t s_g[256];
+    __shared__ uint32_t s_tile;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int NB = 1 << bits;
+    const uint32_t mask = (uint32_t)NB - 1u;
+    if (tid == 0) s_tile = atomicAdd(ticket, 1u);
+    for (int i = tid; i < 4 * 256; i += kSortThreads) (&s_wcnt[0][0])[i] = 0;
+    if (tid < NB) s_g[tid] = ghist[tid];
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    uint32_t count = count_max;
+    if (d_count) count = min(*d_count, count_max);
+    const uint32_t ntiles = (count + kSortTile - 1) / kSortTile;
+    if (tile >= ntiles) return;
+
+    uint32_t keys[kSortItems], vals[kSortItems], rank[kSortItems];
+    const uint32_t base_idx = tile * kSortTile + wave * (kSortItems * 64);
+    const uint64_t lt = lanemask_lt64();
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        const uint32_t idx = base_idx + r * 64 + lane;
+        const bool valid = idx < count;
+        const uint32_t k = valid ? kin[idx] : 0u;
+        keys[r] = k;
+        vals[r] = valid ? (vin ? vin[idx] : idx) : 0u;
+        const uint32_t d = (k >> shift) & mask;
+        uint64_t peers = __ballot(valid);
+        for (int b = 0; b < bits; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bb = __ballot(bit);
+            peers &= bit ? bb : ~bb;
+        }
+        uint32_t old = 0;
+        if (valid) old = s_wcnt[wave][d];
+        if (valid && (peers & lt) == 0) s_wcnt[wave][d] = old + (uint32_t)__popcll(peers);
+        rank[r] = old + (uint32_t)__popcll(peers & lt);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    if (tid < NB) {
+        const int d = tid;
+        const uint32_t t0 = s_wcnt[0][d], t1 = s_wcnt[1][d], t2 = s_wcnt[2][d], t3 = s_wcnt[3][d];
+        const uint32_t total = t0 + t1 + t2 + t3;
+        s_wcnt[0][d] = 0;
+        s_wcnt[1][d] = t0;
+        s_wcnt[2][d] = t0 + t1;
+        s_wcnt[3][d] = t0 + t1 + t2;
+        uint32_t *mine = lookback + (size_t)tile * NB + d;
+        uint32_t excl = 0;
+        if (tile == 0) {
+            atomic_store_u32(mine, (kFlagInclusive << kFlagShift) | total);
+        } else {
+            atomic_store_u32(mine, (kFlagAggregate << kFlagShift) | total);
+            int j = (int)tile - 1;
+            while (j >= 0) {
+                const uint32_t *p = lookback + (size_t)j * NB + d;
+                uint32_t s = atomic_load_u32(p);
+                uint32_t spins = 0;
+                while ((s >> kFlagShift) == 0u && spins < kSpinLimit) {
+                    __builtin_amdgcn_s_sleep(1);
+                    s = atomic_load_u32(p);
+                    ++spins;
+                }
+                const uint32_t f = s >> kFlagShift;
+                if (f == 0u) {
+                    atomicOr(err, 1u);
+                    break;
+                }
+                excl += s & kValueMask;
+                if (f == kFlagInclusive) break;
+                --j;
+            }
+            atomic_store_u32(mine, (kFlagInclusive << kFlagShift) | (excl + total));
+        }
+        uint32_t gex = 0;
+        for (int q = 0; q < d; ++q) gex += s_g[q];
+        s_base[d] = gex + excl;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        const uint32_t idx = base_idx + r * 64 + lane;
+        if (idx < count) {
+            const uint32_t d = (keys[r] >> shift) & mask;
+            const uint32_t pos = s_base[d] + s_wcnt[wave][d] + rank[r];
+            if (pos < count) {
+                kout[pos] = keys[r];
+                vout[pos] = vals[r];
+            } else {
+                atomicOr(err, 4u);   // inconsistent counts: never write out of bounds
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- k_scan_offsets
+//
+// offsets[i] = sum_{j < i} touched[order[j]] (64-bit), single pass with a
+// decoupled look-back over 4096-element tiles; the last tile records the
+// total K and the capacity verdict.
+
+constexpr unsigned long long kF64Agg = 1ull << 62;
+constexpr unsigned long long kF64Inc = 2ull << 62;
+constexpr unsigned long long kV64Mask = (1ull << 62) - 1ull;
+
+__global__ __launch_bounds__(256) void k_scan_offsets(int n, const uint32_t *__restrict__ order,
+                                                      const uint32_t *__restrict__ touched,
+                                                      unsigned long long *__restrict__ offsets,
+                                                      unsigned long long *__restrict__ lookback,
+                                                      uint32_t *__restrict__ ticket, DevStatus *__restrict__ st,
+                                                      uint32_t capacity) {
+    __shared__ unsigned long long s_w[4];
+    __shared__ unsigned long long s_prefix;
+    __shared__ uint32_t s_tile;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    if (tid == 0) s_tile = atomicAdd(ticket, 1u);
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    const uint32_t ntiles = ((uint32_t)n + kScanTile - 1) / kScanTile;
+    if (tile >= ntiles) return;
+    const uint32_t base = tile * kScanTile + tid * 16;
+    uint32_t v[16];
+    unsigned long long sum = 0;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const uint32_t i = base + r;
+        const uint32_t g = i < (uint32_t)n ? order[i] : 0xffffffffu;
+        v[r] = g < (uint32_t)n ? touched[g] : 0u;
+        sum += v[r];
+    }
+    // wave inclusive scan of per-thread sums
+    unsigned long long x = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned long long y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) s_w[wave] = x;
+    __syncthreads();
+    unsigned long long wpre = 0, btotal = 0;
+    for (int w = 0; w < 4; ++w) {
+        if (w < wave) wpre += s_w[w];
+        btotal += s_w[w];
+    }
+    if (tid == 0) {
+        unsigned long long excl = 0;
+        unsigned long long *mine = lookback + tile;
+        if (tile == 0) {
+            atomic_store_u64(mine, kF64Inc | btotal);
+        } else {
+            atomic_store_u64(mine, kF64Agg | btotal);
+            int j = (int)tile - 1;
+            while (j >= 0) {
+                const unsigned long long *p = lookback + j;
+                unsigned long long s = atomic_load_u64(p);
+                uint32_t spins = 0;
+                while ((s >> 62) == 0ull && spins < kSpinLimit) {
+                    __builtin_amdgcn_s_sleep(1);
+                    s = atomic_load_u64(p);
+                    ++spins;
+                }
+                if ((s >> 62) == 0ull) {
+                    atomicOr(&st->sort_error, 2u);
+                    break;
+                }
+                excl += s & kV64Mask;
+                if ((s & kF64Inc) != 0ull) break;
+                --j;
+            }
+            atomic_store_u64(mine, kF64Inc | (excl + btotal));
+        }
+        s_prefix = excl;
+        if (tile == ntiles - 1) {
+            const unsigned long long K = excl + btotal;
+            st->k_total = K;
+            st->k_used = (uint32_t)(K < capacity ? K : capacity);
+            st->overflow = K > capacity ? 1u : 0u;
+        }
+    }
+    __syncthreads();
+    unsigned long long run = s_prefix + wpre + (x - sum);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const uint32_t i = base + r;
+        if (i < (uint32_t)n) offsets[i] = run;
+        run += v[r];
+    }
+}
+
+// ---------------------------------------------------------------- k_emit
+
+__global__ __launch_bounds__(256) void k_emit(int n, const uint32_t *__restrict__ order,
+                                              const unsigned long long *__restrict__ offsets,
+                                              const uint2 *__restrict__ rect, int tiles_x, uint32_t capacity,
+                                              uint32_t *__restrict__ tkeys, uint32_t *__restrict__ tvals,
+                                              int passes, int shift0, int bits0, int shift1, int bits1,
+                                              uint32_t *__restrict__ tile_hist) {
+    __shared__ uint32_t h[2][256];
+    for (int i = threadIdx.x; i < 512; i += blockDim.x) (&h[0][0])[i] = 0;
+    __syncthreads();
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t g = i < n ? order[i] : 0xffffffffu;
+    if (g < (uint32_t)n) {
+        const uint2 rc = rect[g];
+        const int x0 = rc.x & 0xffff, y0 = rc.x >> 16, x1 = rc.y & 0xffff, y1 = rc.y >> 16;
+        unsigned long long o = offsets[i];
+        const uint32_t m0 = (1u << bits0) - 1u, m1 = (1u << bits1) - 1u;
+        for (int ty = y0; ty < y1; ++ty) {
+            for (int tx = x0; tx < x1; ++tx, ++o) {
+                if (o >= capacity) break;
+                const uint32_t t = (uint32_t)(ty * tiles_x + tx);
+                tkeys[o] = t;
+                tvals[o] = g;
+                atomicAdd(&h[0][(t >> shift0) & m0], 1u);
+                if (passes > 1) atomicAdd(&h[1][(t >> shift1) & m1], 1u);
+            }
+        }
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < 512; q += blockDim.x) {
+        const uint32_t c = (&h[0][0])[q];
+        if (c) atomicAdd(&tile_hist[q], c);
+    }
+}
+
+// ---------------------------------------------------------------- k_ranges
+
+__global__ __launch_bounds__(256) void k_ranges(const DevStatus *__restrict__ st, const uint32_t *__restrict__ tkeys,
+                                                uint2 *__restrict__ ranges, uint32_t n_tiles) {
+    const uint32_t K = st->k_used;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < K; i += gridDim.x * blockDim.x) {
+        const uint32_t t = tkeys[i];
+        if (t >= n_tiles) continue;   // only possible if the sort failed (flagged there)
+        if (i == 0 || tkeys[i - 1] != t) ranges[t].x = i;
+        if (i == K - 1 || tkeys[i + 1] != t) ranges[t].y = i + 1;
+    }
+}
+
+// ---------------------------------------------------------------- k_blend
+
+__global__ __launch_bounds__(kTilePixels) void k_blend(const uint2 *__restrict__ ranges,
+                                                       const uint32_t *__restrict__ gids,
+                                                       const float4 *__restrict__ recA,
+                                                       const float4 *__restrict__ recB,
+                                                       const float *__restrict__ recC, int width, int height,
+                                                       int tiles_x, int n_tiles, const CamK *__restrict__ camd,
+                                                       float *__restrict__ image, float *__restrict__ final_T,
+                                                       int32_t *__restrict__ n_contrib, DevStatus *__restrict__ st,
+                                                       int passes, int n) {
+    __shared__ float4 sA[kTilePixels];
+    __shared__ float4 sB[kTilePixels];
+    __shared__ float sC[kTilePixels];
+    // XCD-aware tile order: consecutive blocks go to different XCDs, so give
+    // each XCD a contiguous band of tiles (neighbouring tiles share Gaussians).
+    // The grid is 8 * ceil(n_tiles / 8) blocks; block b runs on XCD b % 8.
+    const int b = (int)blockIdx.x;
+    const int per = (int)gridDim.x / 8;
+    const int tile = (b % 8) * per + b / 8;
+    if (tile >= n_tiles) return;
+    const int tx = tile % tiles_x, ty = tile / tiles_x;
+    const int tid = threadIdx.x;
+    if (tile == 0 && tid == 0) {
+        st->tiles = (uint32_t)n_tiles;
+        st->passes = (uint32_t)passes;
+    }
+    const int px = tx * kTile + (tid & 15), py = ty * kTile + (tid >> 4);
+    const bool inside = px < width && py < height;
+    const uint2 rg = ranges[tile];
+    const int start = (int)rg.x, end = (int)rg.y;
+    const float fpx = (float)px, fpy = (float)py;
+    float T = 1.0f, cr = 0.0f, cg = 0.0f, cbl = 0.0f;
+    bool done = !inside;
+    int last = 0;
+    int evals = inside ? end - start : 0;   // list entries this pixel evaluates
+    const float a_min = 1.0f / 255.0f;
+    for (int b0 = start; b0 < end; b0 += kTilePixels) {
+        if (__syncthreads_count(done) == kTilePixels) break;
+        const int i = b0 + tid;
+        if (i < end) {
+            uint32_t g = gids[i];
+            if (g >= (uint32_t)n) g = 0;   // only possible if the sort failed (flagged there)
+            sA[tid] = recA[g];
+            sB[tid] = recB[g];
+            sC[tid] = recC[g];
+        }
+        __syncthreads();
+        const int cnt = min(kTilePixels, end - b0);
+        if (!done) {
+            for (int j = 0; j < cnt; ++j) {
+                const float4 A = sA[j];
+                const float4 B = sB[j];
+                const float dx = A.x - fpx, dy = A.y - fpy;
+                const float power = ((A.z * dx) * dx + (A.w * dy) * dy) + (B.x * dx) * dy;
+                if (power > 0.0f) continue;
+                const float alpha = fminf(0.99f, B.y * __expf(power));
+                if (alpha < a_min) continue;
+                const float test = T * (1.0f - alpha);
+                if (test < 0.0001f) {
+                    done = true;
+                    evals = b0 - start + j + 1;
+                    break;
+                }
+                const float w = alpha * T;
+                cr += B.z * w;
+                cg += B.w * w;
+                cbl += sC[j] * w;
+                T = test;
+                last = b0 - start + j + 1;
+            }
+        }
+    }
+    {
+        __shared__ unsigned long long s_ev[kTilePixels / 64];
+        unsigned long long e = (unsigned long long)evals;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) e += __shfl_xor(e, o, 64);
+        if ((tid & 63) == 0) s_ev[tid >> 6] = e;
+        __syncthreads();
+        if (tid == 0) {
+            unsigned long long sum = 0;
+            for (int w = 0; w < kTilePixels / 64; ++w) sum += s_ev[w];
+            if (sum) atomicAdd(&st->blend_evals, sum);
+        }
+    }
+    if (inside) {
+        const float bg0 = camd->bg[0], bg1 = camd->bg[1], bg2 = camd->bg[2];
+        const size_t pix = (size_t)py * width + px;
+        const size_t plane = (size_t)width * height;
+        image[pix] = cr + T * bg0;
+        image[plane + pix] = cg + T * bg1;
+        image[2 * plane + pix] = cbl + T * bg2;
+        if (final_T) final_T[pix] = T;
+        if (n_contrib) n_contrib[pix] = last;
+    }
+}
+
+// ---------------------------------------------------------------- k_export
+
+__global__ void k_export_keys(const DevStatus *__restrict__ st, const uint32_t *__restrict__ tkeys,
+                              const uint32_t *__restrict__ tvals, const uint32_t *__restrict__ dkeys_by_gid,
+                              unsigned long long *__restrict__ out, uint32_t k) {
+    const uint32_t K = min(st->k_used, k);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < K; i += gridDim.x * blockDim.x)
+        out[i] = ((unsigned long long)tkeys[i] << 32) | dkeys_by_gid[tvals[i]];
+}
+
+__global__ void k_export_splat2d(int n, const float4 *__restrict__ recA, const float4 *__restrict__ recB,
+                                 const float *__restrict__ recC, float *__restrict__ out) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    const float4 A = recA[g], B = recB[g];
+    float *o = out + (size_t)g * 12;
+    o[0] = A.x; o[1] = A.y; o[2] = A.z; o[3] = A.w;
+    o[4] = B.x; o[5] = B.y; o[6] = B.z; o[7] = B.w;
+    o[8] = recC[g]; o[9] = 0.f; o[10] = 0.f; o[11] = 0.f;
+}
+
+__global__ void k_export_rect(int n, const uint2 *__restrict__ rect, int32_t *__restrict__ out) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    const uint2 r = rect[g];
+    out[4 * g + 0] = r.x & 0xffff;
+    out[4 * g + 1] = r.x >> 16;
+    out[4 * g + 2] = r.y & 0xffff;
+    out[4 * g + 3] = r.y >> 16;
+}
+
+__global__ void k_copy_u32(const uint32_t *__restrict__ src, uint32_t *__restrict__ dst, const DevStatus *st,
+                           uint32_t k, int use_k) {
+    uint32_t K = k;
+    if (use_k) K = min(st->k_used, k);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < K; i += gridDim.x * blockDim.x) dst[i] = src[i];
+}
+
+inline CamK make_cam(const g4d_camera *C) {
+    CamK k{};
+    for (int i = 0; i < 12; ++i) k.v[i] = C->viewmat[i];
+    k.fx = C->fx; k.fy = C->fy; k.cx = C->cx; k.cy = C->cy;
+    k.tanx = C->tan_half_fov_x; k.tany = C->tan_half_fov_y; k.near_plane = C->near_plane;
+    for (int i = 0; i < 3; ++i) k.campos[i] = C->campos[i];
+    for (int i = 0; i < 3; ++i) k.bg[i] = C->bg[i];
+    k.width = C->width; k.height = C->height;
+    k.tiles_x = (C->width + kTile - 1) / kTile;
+    k.tiles_y = (C->height + kTile - 1) / kTile;
+    return k;
+}
+
+template <typename T>
+T *at(const g4d_workspace *ws, size_t off) {
+    return reinterpret_cast<T *>(static_cast<char *>(ws->ptr) + off);
+}
+
+bool ws_layout(const g4d_workspace *ws, WsLayout *L) {
+    if (!ws || !ws->ptr || (reinterpret_cast<uintptr_t>(ws->ptr) & 255)) return false;
+    if (!make_layout(ws->n_max, ws->width_max, ws->height_max, ws->instance_capacity, L)) return false;
+    return ws->bytes >= L->total;
+}
+
+}  // namespace
+
+// Buffer roles (fixed, so that the export path needs no frame state):
+//   dgid        per-Gaussian depth key, indexed by Gaussian
+//   dk/dv       depth sort ping-pong: dgid -> 1 -> 0 -> 1 -> 0; order = dv0
+//   tk/tv       tile sort: emitted into buffer 1 for one pass, 0 for two, so
+//               the sorted instances always end in tk0/tv0
+g4d_status render(const g4d_splats *G, const g4d_camera *C, const g4d_workspace *ws, float *image,
+                  float *final_T, int32_t *n_contrib, hipStream_t s) {
+    if (!G || !C || !ws || !image) return G4D_EINVAL;
+    WsLayout L;
+    if (!ws_layout(ws, &L)) return G4D_EINVAL;
+    const int n = G->n;
+    if (n < 0 || n > L.n_max || G->sh_degree < 0 || G->sh_degree > 3) return G4D_EINVAL;
+    if (C->width < 1 || C->height < 1 || C->width > L.w_max || C->height > L.h_max) return G4D_EINVAL;
+    if (n > 0 && (!G->means || !G->scales || !G->quats || !G->opacity || !G->sh)) return G4D_EINVAL;
+    if (!(C->fx > 0.0f) || !(C->fy > 0.0f) || !(C->near_plane > 0.0f)) return G4D_EINVAL;
+    const CamK cam = make_cam(C);
+    const int tiles = cam.tiles_x * cam.tiles_y;
+    const uint32_t cap = (uint32_t)L.cap;
+    const TilePassPlan plan = tile_pass_plan(tiles);
+
+    DevStatus *st = at<DevStatus>(ws, L.status);
+    CamK *camd = at<CamK>(ws, L.cam);
+    uint32_t *depth_hist = at<uint32_t>(ws, L.depth_hist);
+    uint32_t *tile_hist = at<uint32_t>(ws, L.tile_hist);
+    uint32_t *lb_depth = at<uint32_t>(ws, L.lb_depth);
+    uint32_t *lb_tile = at<uint32_t>(ws, L.lb_tile);
+    unsigned long long *lb_scan = at<unsigned long long>(ws, L.lb_scan);
+    uint2 *ranges = at<uint2>(ws, L.ranges);
+    float4 *recA = at<float4>(ws, L.recA);
+    float4 *recB = at<float4>(ws, L.recB);
+    float *recC = at<float>(ws, L.recC);
+    uint2 *rect = at<uint2>(ws, L.rect);
+    uint32_t *touched = at<uint32_t>(ws, L.touched);
+    uint32_t *dgid = at<uint32_t>(ws, L.dgid);
+    uint32_t *dk[2] = {at<uint32_t>(ws, L.dk0), at<uint32_t>(ws, L.dk1)};
+    uint32_t *dv[2] = {at<uint32_t>(ws, L.dv0), at<uint32_t>(ws, L.dv1)};
+    unsigned long long *offsets = at<unsigned long long>(ws, L.offsets);
+    uint32_t *tk[2] = {at<uint32_t>(ws, L.tk0), at<uint32_t>(ws, L.tk1)};
+    uint32_t *tv[2] = {at<uint32_t>(ws, L.tv0), at<uint32_t>(ws, L.tv1)};
+
+    auto mark = [&](int i) {
+        if (hipEvent_t e = stage_event(i)) (void)hipEventRecord(e, s);
+    };
+    mark(0);
+    // 0. clear status, histograms, look-back state and ranges
+    {
+        const size_t n16 = L.zero_bytes / 16;
+        const int blocks = (int)std::min<size_t>((n16 + 255) / 256, 2048);
+        hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, s, reinterpret_cast<uint4 *>(ws->ptr), n16, cam, camd);
+    }
+    mark(1);
+    const int blend_grid = 8 * ((tiles + 7) / 8);
+    if (n > 0) {
+        const int nb_n = (n + 255) / 256;
+        // 1. preprocess
+        hipLaunchKernelGGL(k_preprocess, dim3(nb_n), dim3(256), 0, s, n, G->sh_degree, G->means, G->scales,
+                           G->quats, G->opacity, G->sh, camd, recA, recB, recC, rect, touched, dgid, depth_hist, st);
+        mark(2);
+        // 2. depth sort: four 8-bit passes over n keys; values start as the identity
+        const int sblocks = (n + kSortTile - 1) / kSortTile;
+        const uint32_t *kin[4] = {dgid, dk[1], dk[0], dk[1]};
+        const uint32_t *vin[4] = {nullptr, dv[1], dv[0], dv[1]};
+        uint32_t *kout[4] = {dk[1], dk[0], dk[1], dk[0]};
+        uint32_t *vout[4] = {dv[1], dv[0], dv[1], dv[0]};
+        for (int p = 0; p < 4; ++p) {
+            hipLaunchKernelGGL(k_sort_pass, dim3(sblocks), dim3(kSortThreads), 0, s, kin[p], vin[p], kout[p], vout[p],
+                               nullptr, (uint32_t)n, 8 * p, 8, depth_hist + 256 * p,
+                               lb_depth + (size_t)p * L.nblk_n * 256, &st->tile_counter[p], &st->sort_error);
+        }
+        mark(3);
+        const uint32_t *order = dv[0];
+        // 3. instance offsets in depth order and K
+        const int scan_blocks = (n + kScanTile - 1) / kScanTile;
+        hipLaunchKernelGGL(k_scan_offsets, dim3(scan_blocks), dim3(256), 0, s, n, order, touched, offsets, lb_scan,
+                           &st->tile_counter[4], st, cap);
+        mark(4);
+        // 4. emit instances (first tile-sort buffer chosen so the result lands in tk0/tv0)
+        const int e = plan.passes == 1 ? 1 : 0;
+        hipLaunchKernelGGL(k_emit, dim3(nb_n), dim3(256), 0, s, n, order, offsets, rect, cam.tiles_x, cap, tk[e],
+                           tv[e], plan.passes, plan.shift[0], plan.bits[0], plan.shift[1],
+                           plan.passes > 1 ? plan.bits[1] : 1, tile_hist);
+        mark(5);
+        // 5. tile sort over K instances (device count), grid sized by capacity
+        const int kblocks = (int)((L.cap + kSortTile - 1) / kSortTile);
+        int cur = e;
+        for (int p = 0; p < plan.passes; ++p) {
+            hipLaunchKernelGGL(k_sort_pass, dim3(kblocks), dim3(kSortThreads), 0, s, tk[cur], tv[cur], tk[cur ^ 1],
+                               tv[cur ^ 1], &st->k_used, cap, plan.shift[p], plan.bits[p], tile_hist + 256 * p,
+                               lb_tile + (size_t)p * L.nblk_k * 256, &st->tile_counter[5 + p], &st->sort_error);
+            cur ^= 1;
+        }
+        mark(6);
+        // 6. ranges
+        {
+            const int rblocks = (int)std::min<int64_t>((L.cap + 255) / 256, 4096);
+            hipLaunchKernelGGL(k_ranges, dim3(rblocks), dim3(256), 0, s, st, tk[0], ranges, (uint32_t)tiles);
+        }
+    } else {
+        for (int i = 2; i <= 6; ++i) mark(i);
+    }
+    mark(7);
+    // 7. blend (with n == 0 every range is empty and the image is the background)
+    hipLaunchKernelGGL(k_blend, dim3(blend_grid), dim3(kTilePixels), 0, s, ranges, tv[0], recA, recB, recC, C->width,
+                       C->height, cam.tiles_x, tiles, camd, image, final_T, n_contrib, st,
+                       plan.passes, std::max(n, 1));
+    mark(8);
+    G4D_HIP_CHECK(hipGetLastError());
+    return G4D_OK;
+}
+
+g4d_status read_status(const g4d_workspace *ws, g4d_device_status *out, hipStream_t s) {
+    WsLayout L;
+    if (!out || !ws_layout(ws, &L)) return G4D_EINVAL;
+    DevStatus h{};
+    G4D_HIP_CHECK(hipMemcpyAsync(&h, at<DevStatus>(ws, L.status), sizeof(h), hipMemcpyDeviceToHost, s));
+    G4D_HIP_CHECK(hipStreamSynchronize(s));
+    out->instances = (int64_t)h.k_total;
+    out->overflow = (int32_t)h.overflow;
+    out->sort_error = (int32_t)h.sort_error;
+    out->visible = (int32_t)h.visible;
+    out->tiles = (int32_t)h.tiles;
+    out->blend_evals = (int64_t)h.blend_evals;
+    return G4D_OK;
+}
+
+g4d_status render_export(const g4d_workspace *ws, int32_t kind, int32_t n, int64_t k, void *dst, size_t bytes,
+                         hipStream_t s) {
+    WsLayout L;
+    if (!dst || !ws_layout(ws, &L) || n < 0 || n > L.n_max || k < 0) return G4D_EINVAL;
+    const DevStatus *st = at<DevStatus>(ws, L.status);
+    const int nb = std::max(1, (n + 255) / 256);
+    switch (kind) {
+        case G4D_EXPORT_SORTED_KEYS: {
+            if (k > L.cap || bytes < (size_t)k * 8) return G4D_EINVAL;
+            if (k == 0) return G4D_OK;
+            hipLaunchKernelGGL(k_export_keys, dim3(256), dim3(256), 0, s, st, at<uint32_t>(ws, L.tk0),
+                               at<uint32_t>(ws, L.tv0), at<uint32_t>(ws, L.dgid),
+                               static_cast<unsigned long long *>(dst), (uint32_t)k);
+            break;
+        }
+        case G4D_EXPORT_SORTED_GIDS: {
+            if (k > L.cap || bytes < (size_t)k * 4) return G4D_EINVAL;
+            if (k == 0) return G4D_OK;
+            hipLaunchKernelGGL(k_copy_u32, dim3(256), dim3(256), 0, s, at<uint32_t>(ws, L.tv0),
+                               static_cast<uint32_t *>(dst), st, (uint32_t)k, 1);
+            break;
+        }
+        case G4D_EXPORT_RECT: {
+            if (bytes < (size_t)n * 16) return G4D_EINVAL;
+            if (n == 0) return G4D_OK;
+            hipLaunchKernelGGL(k_export_rect, dim3(nb), dim3(256), 0, s, n, at<uint2>(ws, L.rect),
+                               static_cast<int32_t *>(dst));
+            break;
+        }
+        case G4D_EXPORT_DEPTH_BITS:
+        case G4D_EXPORT_DEPTH_ORDER: {
+            if (bytes < (size_t)n * 4) return G4D_EINVAL;
+            if (n == 0) return G4D_OK;
+            const uint32_t *src = at<uint32_t>(ws, kind == G4D_EXPORT_DEPTH_BITS ? L.dgid : L.dv0);
+            hipLaunchKernelGGL(k_copy_u32, dim3(nb), dim3(256), 0, s, src, static_cast<uint32_t *>(dst), st,
+                               (uint32_t)n, 0);
+            break;
+        }
+        case G4D_EXPORT_RANGES: {
+            // k = number of tiles of the frame
+            if (k > L.tiles_max || bytes < (size_t)k * 8) return G4D_EINVAL;
+            if (k == 0) return G4D_OK;
+            hipLaunchKernelGGL(k_copy_u32, dim3(256), dim3(256), 0, s, at<uint32_t>(ws, L.ranges),
+                               static_cast<uint32_t *>(dst), st, (uint32_t)(2 * k), 0);
+            break;
+        }
+        case G4D_EXPORT_SPLAT2D: {
+            if (bytes < (size_t)n * 48) return G4D_EINVAL;
+            if (n == 0) return G4D_OK;
+            hipLaunchKernelGGL(k_export_splat2d, dim3(nb), dim3(256), 0, s, n, at<float4>(ws, L.recA),
+                               at<float4>(ws, L.recB), at<float>(ws, L.recC), static_cast<float *>(dst));
+            break;
+        }
+        default:
+            return G4D_EINVAL;
+    }
+    G4D_HIP_CHECK(hipGetLastError());
+    return G4D_OK;
+}
+
+// ---------------------------------------------------------------- graphs
+//
+// A render captured into a graph keeps every pointer and launch shape of its
+// workspace and frame size; the view enters only through k_zero's CamK
+// argument.  These helpers find that node and rewrite its parameters.
+
+g4d_status graph_find_camera_node(hipGraph_t g, hipGraphNode_t *out) {
+    size_t count = 0;
+    G4D_HIP_CHECK(hipGraphGetNodes(g, nullptr, &count));
+    std::vector<hipGraphNode_t> nodes(count);
+    G4D_HIP_CHECK(hipGraphGetNodes(g, nodes.data(), &count));
+    for (hipGraphNode_t nd : nodes) {
+        hipGraphNodeType ty;
+        G4D_HIP_CHECK(hipGraphNodeGetType(nd, &ty));
+        if (ty != hipGraphNodeTypeKernel) continue;
+        hipKernelNodeParams kp{};
+        G4D_HIP_CHECK(hipGraphKernelNodeGetParams(nd, &kp));
+        if (kp.func == reinterpret_cast<void *>(k_zero)) {
+            *out = nd;
+            return G4D_OK;
+        }
+    }
+    return G4D_EDEVICE;
+}
+
+g4d_status graph_set_camera(hipGraphExec_t exec, hipGraphNode_t node, const g4d_workspace *ws,
+                            const g4d_camera *C) {
+    WsLayout L;
+    if (!C || !ws_layout(ws, &L)) return G4D_EINVAL;
+    uint4 *p = reinterpret_cast<uint4 *>(ws->ptr);
+    size_t n16 = L.zero_bytes / 16;
+    CamK cam = make_cam(C);
+    CamK *camd = at<CamK>(ws, L.cam);
+    void *args[4] = {&p, &n16, &cam, &camd};
+    hipKernelNodeParams kp{};
+    kp.func = reinterpret_cast<void *>(k_zero);
+    kp.gridDim = dim3((unsigned)std::min<size_t>((n16 + 255) / 256, 2048));
+    kp.blockDim = dim3(256);
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = args;
+    kp.extra = nullptr;
+    G4D_HIP_CHECK(hipGraphExecKernelNodeSetParams(exec, node, &kp));
+    return G4D_OK;
+}
+
+}  // namespace g4d

@@ -1,0 +1,332 @@
+"""Thin ctypes binding of libg4d (declared in include/g4d.h).
+
+Argument marshalling only: torch tensors provide device memory and the
+current HIP stream; every step of the deform and render path runs in the
+library's HIP kernels.  There is no fallback: if libg4d.so is missing or
+cannot be loaded, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libg4d.so")
+
+c_i32, c_i64, c_f32, c_f64, c_sz, c_p = (ctypes.c_int32, ctypes.c_int64, ctypes.c_float,
+                                         ctypes.c_double, ctypes.c_size_t, ctypes.c_void_p)
+
+MAX_SCALES = 4
+TILE = 16
+MAX_BATCH_JOBS = 8
+
+OK, EINVAL, EUNSUPPORTED, ECAPACITY, EHIP, EBUSY, ENOMEM, ENOTFOUND, EDEVICE = 0, -1, -2, -3, -4, -5, -6, -7, -8
+MLP_F32, MLP_BF16 = 0, 1
+EXPORT_SORTED_KEYS, EXPORT_SORTED_GIDS, EXPORT_RECT, EXPORT_DEPTH_BITS, EXPORT_RANGES, \
+    EXPORT_SPLAT2D, EXPORT_DEPTH_ORDER = range(7)
+
+
+class Gaussians(ctypes.Structure):
+    _fields_ = [("n", c_i32), ("sh_degree", c_i32), ("means", c_p), ("log_scales", c_p),
+                ("quats", c_p), ("opacity_logits", c_p), ("sh", c_p)]
+
+
+class Planes(ctypes.Structure):
+    _fields_ = [("n_scales", c_i32), ("feat", c_i32), ("bmin", c_f32 * 3), ("bmax", c_f32 * 3),
+                ("res", (c_i32 * 4) * MAX_SCALES), ("plane", (c_p * 6) * MAX_SCALES)]
+
+
+class MLP(ctypes.Structure):
+    _fields_ = [("in_dim", c_i32), ("hidden", c_i32), ("precision", c_i32),
+                ("w1", c_p), ("b1", c_p), ("wx", c_p), ("bx", c_p), ("wr", c_p), ("br", c_p),
+                ("ws", c_p), ("bs", c_p)]
+
+
+class Splats(ctypes.Structure):
+    _fields_ = [("n", c_i32), ("sh_degree", c_i32), ("means", c_p), ("scales", c_p), ("quats", c_p),
+                ("opacity", c_p), ("sh", c_p)]
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("width", c_i32), ("height", c_i32), ("viewmat", c_f32 * 12), ("fx", c_f32),
+                ("fy", c_f32), ("cx", c_f32), ("cy", c_f32), ("tan_half_fov_x", c_f32),
+                ("tan_half_fov_y", c_f32), ("near_plane", c_f32), ("campos", c_f32 * 3),
+                ("bg", c_f32 * 3)]
+
+
+class Workspace(ctypes.Structure):
+    _fields_ = [("ptr", c_p), ("bytes", c_sz), ("n_max", c_i32), ("width_max", c_i32),
+                ("height_max", c_i32), ("instance_capacity", c_i64)]
+
+
+class DeviceStatus(ctypes.Structure):
+    _fields_ = [("instances", c_i64), ("overflow", c_i32), ("sort_error", c_i32), ("visible", c_i32),
+                ("tiles", c_i32), ("blend_evals", c_i64)]
+
+
+class DeformJob(ctypes.Structure):
+    _fields_ = [("G", ctypes.POINTER(Gaussians)), ("P", ctypes.POINTER(Planes)),
+                ("M", ctypes.POINTER(MLP)), ("t", c_f32), ("out", ctypes.POINTER(Splats))]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget", c_sz), ("max_slots", c_i32), ("use_graphs", c_i32),
+                ("batch_deform", c_i32), ("max_width", c_i32), ("max_height", c_i32),
+                ("instance_factor", c_f64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", c_i64), ("completed", c_i64), ("rejected", c_i64), ("p50_ms", c_f64),
+                ("p99_ms", c_f64), ("mean_ms", c_f64), ("max_ms", c_f64), ("wall_s", c_f64),
+                ("frames_per_s", c_f64), ("batched_launches", c_i64), ("graph_replays", c_i64),
+                ("eager_renders", c_i64), ("overflow_retries", c_i64), ("peak_bytes", c_sz)]
+
+
+# symbol -> (restype, argtypes); the full set declared in include/g4d.h
+SIGNATURES = {
+    "g4d_deform": (c_i32, [ctypes.POINTER(Gaussians), ctypes.POINTER(Planes), ctypes.POINTER(MLP), c_f32,
+                           ctypes.POINTER(Splats), c_p]),
+    "g4d_deform_batched": (c_i32, [ctypes.POINTER(DeformJob), c_i32, c_p]),
+    "g4d_deform_features": (c_i32, [ctypes.POINTER(Gaussians), ctypes.POINTER(Planes), c_f32, c_p, c_p]),
+    "g4d_render_workspace_bytes": (c_sz, [c_i32, c_i32, c_i32, c_i64]),
+    "g4d_render": (c_i32, [ctypes.POINTER(Splats), ctypes.POINTER(Camera), ctypes.POINTER(Workspace), c_p, c_p,
+                           c_p, c_p]),
+    "g4d_read_status": (c_i32, [ctypes.POINTER(Workspace), ctypes.POINTER(DeviceStatus), c_p]),
+    "g4d_render_export": (c_i32, [ctypes.POINTER(Workspace), c_i32, c_i32, c_i64, c_p, c_sz, c_p]),
+    "g4d_set_stage_events": (c_i32, [ctypes.POINTER(c_p), c_i32]),
+    "g4d_status_string": (ctypes.c_char_p, [c_i32]),
+    "g4d_last_hip_error": (c_i32, []),
+    "g4d_version": (ctypes.c_char_p, []),
+    "g4d_server_create": (c_i32, [ctypes.POINTER(ServerConfig), ctypes.POINTER(c_p)]),
+    "g4d_server_add_scene": (c_i32, [c_p, ctypes.POINTER(Gaussians), ctypes.POINTER(Planes), ctypes.POINTER(MLP),
+                                     ctypes.POINTER(c_i32)]),
+    "g4d_server_submit": (c_i32, [c_p, c_i32, ctypes.POINTER(Camera), c_f32, c_p, ctypes.POINTER(ctypes.c_uint64)]),
+    "g4d_server_wait": (c_i32, [c_p, ctypes.c_uint64, ctypes.POINTER(c_f64)]),
+    "g4d_server_drain": (c_i32, [c_p]),
+    "g4d_server_stats_get": (c_i32, [c_p, ctypes.POINTER(ServerStats)]),
+    "g4d_server_reset_stats": (c_i32, [c_p]),
+    "g4d_server_destroy": (c_i32, [c_p]),
+}
+
+_lib = None
+
+
+class G4DError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        msg = load().g4d_status_string(status).decode()
+        if status == EHIP:
+            msg += f" (hipError {load().g4d_last_hip_error()})"
+        super().__init__(f"{what}: {msg} [{status}]" if what else f"{msg} [{status}]")
+
+
+def load():
+    """Load libg4d.so (built by paper_2310_08528_amd.build).  Raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2310_08528_amd.build`")
+    # torch first: its bundled HIP runtime carries the same soname as the
+    # system one, so libg4d then binds to the runtime torch already uses
+    # (one runtime per process, shared streams and device pointers).
+    import torch  # noqa: F401
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def check(status: int, what: str = "") -> None:
+    if status != OK:
+        raise G4DError(status, what)
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream=None) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+# ------------------------------------------------------- device-side objects
+
+class DeviceGaussians:
+    """Canonical Gaussians in device tensors (SoA float32)."""
+
+    def __init__(self, g, device):
+        import torch
+        f = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(device)
+        self.n, self.sh_degree = int(g.n), int(g.sh_degree)
+        self.means, self.log_scales, self.quats = f(g.means), f(g.log_scales), f(g.quats)
+        self.opacity_logits, self.sh = f(g.opacity_logits), f(g.sh)
+
+    def struct(self) -> Gaussians:
+        return Gaussians(self.n, self.sh_degree, _ptr(self.means), _ptr(self.log_scales), _ptr(self.quats),
+                         _ptr(self.opacity_logits), _ptr(self.sh))
+
+    def nbytes(self) -> int:
+        return sum(t.numel() * 4 for t in (self.means, self.log_scales, self.quats, self.opacity_logits, self.sh))
+
+
+class DevicePlanes:
+    def __init__(self, planes, device):
+        import torch
+        self.n_scales, self.feat = planes.n_scales, planes.feat
+        self.res = [tuple(int(x) for x in r) for r in planes.res]
+        self.bmin = [float(x) for x in planes.bmin]
+        self.bmax = [float(x) for x in planes.bmax]
+        self.tensors = [[torch.from_numpy(np.ascontiguousarray(p, dtype=np.float32)).to(device) for p in lv]
+                        for lv in planes.planes]
+
+    def struct(self) -> Planes:
+        s = Planes()
+        s.n_scales, s.feat = self.n_scales, self.feat
+        for k in range(3):
+            s.bmin[k], s.bmax[k] = self.bmin[k], self.bmax[k]
+        for l in range(self.n_scales):
+            for k in range(4):
+                s.res[l][k] = self.res[l][k]
+            for p in range(6):
+                s.plane[l][p] = _ptr(self.tensors[l][p])
+        return s
+
+    def nbytes(self) -> int:
+        return sum(t.numel() * 4 for lv in self.tensors for t in lv)
+
+
+class DeviceMLP:
+    def __init__(self, mlp, device, precision: int = MLP_F32):
+        import torch
+        f = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(device)
+        self.in_dim, self.hidden, self.precision = mlp.in_dim, mlp.hidden, precision
+        self.w = {k: f(getattr(mlp, k)) for k in ("w1", "b1", "wx", "bx", "wr", "br", "ws", "bs")}
+
+    def struct(self) -> MLP:
+        w = self.w
+        return MLP(self.in_dim, self.hidden, self.precision, _ptr(w["w1"]), _ptr(w["b1"]), _ptr(w["wx"]),
+                   _ptr(w["bx"]), _ptr(w["wr"]), _ptr(w["br"]), _ptr(w["ws"]), _ptr(w["bs"]))
+
+
+class DeviceSplats:
+    """Render-ready Gaussians (deform output / render input) in device tensors."""
+
+    def __init__(self, n, sh_degree, sh, device, means=None, scales=None, quats=None, opacity=None):
+        import torch
+        mk = lambda shape, t: (torch.empty(shape, dtype=torch.float32, device=device) if t is None
+                               else torch.as_tensor(np.ascontiguousarray(t, dtype=np.float32)).to(device)
+                               if not isinstance(t, torch.Tensor) else t.contiguous())
+        self.n, self.sh_degree = int(n), int(sh_degree)
+        self.means, self.scales = mk((3, n), means), mk((3, n), scales)
+        self.quats, self.opacity = mk((4, n), quats), mk((n,), opacity)
+        self.sh = sh if isinstance(sh, torch.Tensor) else torch.as_tensor(
+            np.ascontiguousarray(sh, dtype=np.float32)).to(device)
+
+    @classmethod
+    def from_host(cls, s, device):
+        return cls(s.n, s.sh_degree, s.sh, device, s.means, s.scales, s.quats, s.opacity)
+
+    def struct(self) -> Splats:
+        return Splats(self.n, self.sh_degree, _ptr(self.means), _ptr(self.scales), _ptr(self.quats),
+                      _ptr(self.opacity), _ptr(self.sh))
+
+
+def camera_struct(cam) -> Camera:
+    c = Camera()
+    c.width, c.height = int(cam.width), int(cam.height)
+    v = np.asarray(cam.viewmat, dtype=np.float32).reshape(-1)
+    for i in range(12):
+        c.viewmat[i] = float(v[i])
+    c.fx, c.fy, c.cx, c.cy = cam.fx, cam.fy, cam.cx, cam.cy
+    c.tan_half_fov_x, c.tan_half_fov_y, c.near_plane = cam.tan_half_fov_x, cam.tan_half_fov_y, cam.near
+    for i in range(3):
+        c.campos[i] = float(cam.campos[i])
+        c.bg[i] = float(cam.bg[i])
+    return c
+
+
+def workspace_bytes(n: int, width: int, height: int, capacity: int) -> int:
+    return int(load().g4d_render_workspace_bytes(n, width, height, capacity))
+
+
+class RenderWorkspace:
+    """Caller-owned render scratch (a torch uint8 tensor on the device)."""
+
+    def __init__(self, n_max: int, width_max: int, height_max: int, capacity: int, device):
+        import torch
+        nbytes = workspace_bytes(n_max, width_max, height_max, capacity)
+        if nbytes == 0:
+            raise G4DError(EINVAL, "workspace size")
+        self.buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        base = self.buf.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        self.ws = Workspace(aligned, nbytes, n_max, width_max, height_max, capacity)
+        self.n_max, self.width_max, self.height_max, self.capacity = n_max, width_max, height_max, capacity
+
+    def fits(self, n, width, height) -> bool:
+        return n <= self.n_max and width <= self.width_max and height <= self.height_max
+
+
+# --------------------------------------------------------------- the calls
+
+def deform(G: DeviceGaussians, P: DevicePlanes, M: DeviceMLP, t: float, out: DeviceSplats, stream=None):
+    gs, ps, ms, os_ = G.struct(), P.struct(), M.struct(), out.struct()
+    check(load().g4d_deform(ctypes.byref(gs), ctypes.byref(ps), ctypes.byref(ms), float(t), ctypes.byref(os_),
+                            _stream(stream)), "g4d_deform")
+
+
+def deform_batched(jobs, stream=None):
+    """jobs: list of (DeviceGaussians, DevicePlanes, DeviceMLP, t, DeviceSplats)."""
+    keep = []
+    arr = (DeformJob * len(jobs))()
+    for i, (G, P, M, t, out) in enumerate(jobs):
+        gs, ps, ms, os_ = G.struct(), P.struct(), M.struct(), out.struct()
+        keep += [gs, ps, ms, os_]
+        arr[i] = DeformJob(ctypes.pointer(gs), ctypes.pointer(ps), ctypes.pointer(ms), float(t), ctypes.pointer(os_))
+    check(load().g4d_deform_batched(arr, len(jobs), _stream(stream)), "g4d_deform_batched")
+
+
+def deform_features(G: DeviceGaussians, P: DevicePlanes, t: float, features, stream=None):
+    gs, ps = G.struct(), P.struct()
+    check(load().g4d_deform_features(ctypes.byref(gs), ctypes.byref(ps), float(t), _ptr(features),
+                                     _stream(stream)), "g4d_deform_features")
+
+
+def render(S: DeviceSplats, cam, ws: RenderWorkspace, image, final_T=None, n_contrib=None, stream=None):
+    ss = S.struct()
+    cs = cam if isinstance(cam, Camera) else camera_struct(cam)
+    check(load().g4d_render(ctypes.byref(ss), ctypes.byref(cs), ctypes.byref(ws.ws), _ptr(image), _ptr(final_T),
+                            _ptr(n_contrib), _stream(stream)), "g4d_render")
+
+
+def read_status(ws: RenderWorkspace, stream=None) -> DeviceStatus:
+    st = DeviceStatus()
+    check(load().g4d_read_status(ctypes.byref(ws.ws), ctypes.byref(st), _stream(stream)), "g4d_read_status")
+    return st
+
+
+def export(ws: RenderWorkspace, kind: int, n: int, k: int, dst, stream=None):
+    check(load().g4d_render_export(ctypes.byref(ws.ws), int(kind), int(n), int(k), _ptr(dst),
+                                   dst.numel() * dst.element_size(), _stream(stream)), "g4d_render_export")
+
+
+def set_stage_events(events):
+    """events: list of 9 raw hipEvent_t handles (int or None), or None to stop."""
+    if events is None:
+        check(load().g4d_set_stage_events(None, 0), "g4d_set_stage_events")
+        return
+    arr = (c_p * len(events))(*[e or None for e in events])
+    check(load().g4d_set_stage_events(arr, len(events)), "g4d_set_stage_events")
+
+
+def version() -> str:
+    return load().g4d_version().decode()
