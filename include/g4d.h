@@ -294,6 +294,40 @@ g4d_status g4d_server_stats_get(g4d_server *srv, g4d_server_stats *out);
 g4d_status g4d_server_reset_stats(g4d_server *srv);
 g4d_status g4d_server_destroy(g4d_server *srv);
 
+/* The scheduler of the serving loop on a simulated device, in virtual time:
+ * the same FIFO admission, memory-budget accounting with buffer reuse, slot
+ * and batching logic as g4d_server_*, driven by a given arrival trace.  Each
+ * request i arrives at arrival_s[i], needs bytes[i] of request memory while
+ * it runs (reused by a later request of the same class_id once released) and
+ * takes service_s[i] of device time when alone; with m requests on the
+ * device each progresses at rate (1 + overlap (m - 1)) / m.  Needs no GPU;
+ * used to verify the scheduler. */
+typedef struct {
+    size_t hbm_budget;
+    int32_t max_slots;
+    int32_t batch_deform;
+    int32_t n_requests;
+    const double *arrival_s;    /* [n], non-decreasing */
+    const double *service_s;    /* [n] */
+    const size_t *bytes;        /* [n] */
+    const int32_t *class_id;    /* [n] */
+    const int32_t *shape_class; /* [n]: requests of one shape class share a batched deform launch */
+    double overlap;             /* 0..1 */
+} g4d_sim_config;
+
+typedef struct {
+    double p50_ms, p99_ms, mean_ms, max_ms, makespan_s;
+    size_t peak_bytes;          /* request memory held at once (in use + kept for reuse) */
+    int32_t max_in_flight;
+    int32_t rejected;
+    int64_t batched_launches;
+    int64_t buffer_reuses;
+    double *latency_ms;         /* optional [n]: per request, -1 if rejected */
+    int32_t *admit_order;       /* optional [n]: request indices in admission order */
+} g4d_sim_result;
+
+g4d_status g4d_server_simulate(const g4d_sim_config *cfg, g4d_sim_result *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -3,9 +3,6 @@
 #include "g4d_internal.h"
 
 namespace g4d {
-g4d_status render(const g4d_splats *G, const g4d_camera *C, const g4d_workspace *ws, float *image,
-                  float *final_T, int32_t *n_contrib, hipStream_t s);
-g4d_status read_status(const g4d_workspace *ws, g4d_device_status *out, hipStream_t s);
 g4d_status render_export(const g4d_workspace *ws, int32_t kind, int32_t n, int64_t k, void *dst, size_t bytes,
                          hipStream_t s);
 

@@ -18,7 +18,9 @@ constexpr int kTilePixels = kTile * kTile;   // one blend block per tile
 // Radix-sort tiling: 256 threads x 16 items per block.
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;
-constexpr int kSortTile = kSortThreads * kSortItems;   // 4096 keys per block
+constexpr int kSortTile = kSortThreads * kSortItems;   // 4096 keys per block (instances)
+constexpr int kSortItemsN = 4;
+constexpr int kSortTileN = kSortThreads * kSortItemsN; // 1024 keys per block (per-Gaussian depth)
 constexpr int kScanTile = 256 * 16;                    // 4096 values per scan block
 
 // Lookback status words: flag in the top two bits, value in the low 30.
@@ -73,7 +75,7 @@ inline bool make_layout(int32_t n, int32_t w, int32_t h, int64_t cap, WsLayout *
     int tx = (w + kTile - 1) / kTile, ty = (h + kTile - 1) / kTile;
     L->tiles_max = tx * ty;
     int32_t nn = n > 0 ? n : 1;
-    L->nblk_n = (nn + kSortTile - 1) / kSortTile;
+    L->nblk_n = (nn + kSortTileN - 1) / kSortTileN;
     L->nblk_k = (int32_t)((cap + kSortTile - 1) / kSortTile);
     L->nscan = (nn + kScanTile - 1) / kScanTile;
     size_t o = 0;
@@ -129,6 +131,17 @@ inline TilePassPlan tile_pass_plan(int tiles) {
 
 // Host-side error plumbing.
 void set_hip_error(hipError_t e);
+
+// Entry points shared between translation units.
+g4d_status render(const g4d_splats *G, const g4d_camera *C, const g4d_workspace *ws, float *image,
+                  float *final_T, int32_t *n_contrib, hipStream_t s);
+g4d_status read_status(const g4d_workspace *ws, g4d_device_status *out, hipStream_t s);
+g4d_status deform_batched(const g4d_deform_job *jobs, int n_jobs, hipStream_t s);
+g4d_status graph_find_camera_node(hipGraph_t g, hipGraphNode_t *out);
+g4d_status graph_set_frame(hipGraphExec_t exec, hipGraphNode_t node, const g4d_workspace *ws,
+                           const g4d_camera *C, float *image, float *final_T, int32_t *n_contrib);
+// Byte offset of the device status block inside a workspace.
+size_t status_offset(const g4d_workspace *ws);
 
 // Stage events of the calling thread (null when off).
 constexpr int kStageEvents = 9;

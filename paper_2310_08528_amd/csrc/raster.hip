@@ -50,15 +50,20 @@ __device__ __forceinline__ uint64_t lanemask_lt64() {
     return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
-// Camera as the kernels read it.  It lives in the workspace: the first
-// kernel of a render (k_zero) writes it from its launch argument, so a
-// captured render graph changes view through that one node's parameters.
+// Frame descriptor as the kernels read it: camera, background and output
+// pointers.  It lives in the workspace: the first kernel of a render
+// (k_zero) writes it from its launch argument, so a captured render graph
+// takes a new view and new output buffers through that one node's
+// parameters.
 struct CamK {
     float v[12];
     float fx, fy, cx, cy, tanx, tany, near_plane;
     float campos[3];
     float bg[3];
     int width, height, tiles_x, tiles_y;
+    float *image;
+    float *final_T;
+    int32_t *n_contrib;
 };
 
 // ---------------------------------------------------------------- k_zero
@@ -254,6 +259,7 @@ __global__ __launch_bounds__(256) void k_preprocess(int n, int sh_degree, const 
 // key sub-tile: wave-wide digit matching with ballots, running per-wave digit
 // counters in LDS.  Waits are bounded; a wait that gives up sets sort_error.
 
+template <int ITEMS>
 __global__ __launch_bounds__(kSortThreads) void k_sort_pass(
     const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
     uint32_t *__restrict__ vout, const uint32_t *__restrict__ d_count, uint32_t count_max, int shift, int bits,
@@ -263,24 +269,41 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_pass(
     __shared__ uint32_t s_base[256];
     __shared__ uint32_t s_g[256];
     __shared__ uint32_t s_tile;
+    __shared__ int s_trivial;
+    constexpr uint32_t TILE = kSortThreads * ITEMS;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int NB = 1 << bits;
     const uint32_t mask = (uint32_t)NB - 1u;
-    if (tid == 0) s_tile = atomicAdd(ticket, 1u);
-    for (int i = tid; i < 4 * 256; i += kSortThreads) (&s_wcnt[0][0])[i] = 0;
-    if (tid < NB) s_g[tid] = ghist[tid];
-    __syncthreads();
-    const uint32_t tile = s_tile;
     uint32_t count = count_max;
     if (d_count) count = min(*d_count, count_max);
-    const uint32_t ntiles = (count + kSortTile - 1) / kSortTile;
+    if (tid == 0) {
+        s_tile = atomicAdd(ticket, 1u);
+        s_trivial = 0;
+    }
+    for (int i = tid; i < 4 * 256; i += kSortThreads) (&s_wcnt[0][0])[i] = 0;
+    __syncthreads();
+    if (tid < NB) {
+        s_g[tid] = ghist[tid];
+        if (s_g[tid] == count) s_trivial = 1;   // every key has this digit
+    }
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    const uint32_t ntiles = (count + TILE - 1) / TILE;
     if (tile >= ntiles) return;
+    if (s_trivial) {
+        // the pass is the identity permutation: stream the tile through
+        for (uint32_t idx = tile * TILE + tid; idx < min(count, (tile + 1) * TILE); idx += kSortThreads) {
+            kout[idx] = kin[idx];
+            vout[idx] = vin ? vin[idx] : idx;
+        }
+        return;
+    }
 
-    uint32_t keys[kSortItems], vals[kSortItems], rank[kSortItems];
-    const uint32_t base_idx = tile * kSortTile + wave * (kSortItems * 64);
+    uint32_t keys[ITEMS], vals[ITEMS], rank[ITEMS];
+    const uint32_t base_idx = tile * TILE + wave * (ITEMS * 64);
     const uint64_t lt = lanemask_lt64();
 #pragma unroll
-    for (int r = 0; r < kSortItems; ++r) {
+    for (int r = 0; r < ITEMS; ++r) {
         const uint32_t idx = base_idx + r * 64 + lane;
         const bool valid = idx < count;
         const uint32_t k = valid ? kin[idx] : 0u;
@@ -301,6 +324,8 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_pass(
         __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
+    // Per-digit totals and per-wave exclusive prefixes of this tile.
+    __shared__ uint32_t s_tot[256];
     if (tid < NB) {
         const int d = tid;
         const uint32_t t0 = s_wcnt[0][d], t1 = s_wcnt[1][d], t2 = s_wcnt[2][d], t3 = s_wcnt[3][d];
@@ -309,40 +334,61 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_pass(
         s_wcnt[1][d] = t0;
         s_wcnt[2][d] = t0 + t1;
         s_wcnt[3][d] = t0 + t1 + t2;
-        uint32_t *mine = lookback + (size_t)tile * NB + d;
+        s_tot[d] = total;
+        // publish early so that successors can proceed
+        atomic_store_u32(lookback + (size_t)tile * NB + d,
+                         ((tile == 0 ? kFlagInclusive : kFlagAggregate) << kFlagShift) | total);
+    }
+    __syncthreads();
+    // Windowed look-back: LB = 256 / NB consecutive threads per digit read LB
+    // predecessors at once; the nearest inclusive prefix ends the walk.
+    {
+        const int LB = min(kSortThreads / NB, 64);   // a group never spans two waves
+        const int d = tid / LB, k = tid % LB;
         uint32_t excl = 0;
-        if (tile == 0) {
-            atomic_store_u32(mine, (kFlagInclusive << kFlagShift) | total);
-        } else {
-            atomic_store_u32(mine, (kFlagAggregate << kFlagShift) | total);
+        if (tile > 0 && d < NB) {
             int j = (int)tile - 1;
-            while (j >= 0) {
-                const uint32_t *p = lookback + (size_t)j * NB + d;
-                uint32_t s = atomic_load_u32(p);
-                uint32_t spins = 0;
-                while ((s >> kFlagShift) == 0u && spins < kSpinLimit) {
-                    __builtin_amdgcn_s_sleep(1);
-                    s = atomic_load_u32(p);
-                    ++spins;
+            while (true) {
+                const int jj = j - k;
+                uint32_t st = (kFlagInclusive << kFlagShift);   // before tile 0: inclusive zero
+                if (jj >= 0) {
+                    const uint32_t *p = lookback + (size_t)jj * NB + d;
+                    st = atomic_load_u32(p);
+                    uint32_t spins = 0;
+                    while ((st >> kFlagShift) == 0u && spins < kSpinLimit) {
+                        __builtin_amdgcn_s_sleep(1);
+                        st = atomic_load_u32(p);
+                        ++spins;
+                    }
+                    if ((st >> kFlagShift) == 0u) {
+                        atomicOr(err, 1u);
+                        st = (kFlagInclusive << kFlagShift);
+                    }
                 }
-                const uint32_t f = s >> kFlagShift;
-                if (f == 0u) {
-                    atomicOr(err, 1u);
-                    break;
-                }
-                excl += s & kValueMask;
-                if (f == kFlagInclusive) break;
-                --j;
+                const bool inc = (st >> kFlagShift) == kFlagInclusive;
+                const uint64_t bal = __ballot(inc);
+                const uint32_t grp = (uint32_t)(bal >> (lane - k)) & ((1u << LB) - 1u);
+                const int kfirst = grp ? __builtin_ctz(grp) : LB;
+                uint32_t v = (k <= kfirst) ? (st & kValueMask) : 0u;
+                for (int o = 1; o < LB; o <<= 1) v += __shfl_xor(v, o, 64);
+                excl += v;
+                if (grp) break;
+                j -= LB;
             }
-            atomic_store_u32(mine, (kFlagInclusive << kFlagShift) | (excl + total));
         }
+        if (tile > 0 && d < NB && k == 0)
+            atomic_store_u32(lookback + (size_t)tile * NB + d, (kFlagInclusive << kFlagShift) | (excl + s_tot[d]));
+        if (d < NB && k == 0) s_base[d] = excl;
+    }
+    __syncthreads();
+    if (tid < NB) {
         uint32_t gex = 0;
-        for (int q = 0; q < d; ++q) gex += s_g[q];
-        s_base[d] = gex + excl;
+        for (int q = 0; q < tid; ++q) gex += s_g[q];
+        s_base[tid] += gex;
     }
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < kSortItems; ++r) {
+    for (int r = 0; r < ITEMS; ++r) {
         const uint32_t idx = base_idx + r * 64 + lane;
         if (idx < count) {
             const uint32_t d = (keys[r] >> shift) & mask;
@@ -452,6 +498,13 @@ __global__ __launch_bounds__(256) void k_scan_offsets(int n, const uint32_t *__r
 }
 
 // ---------------------------------------------------------------- k_emit
+//
+// Wave-cooperative fan-out: the 64 Gaussians of a wave (consecutive in depth
+// order, so their instance blocks are contiguous) write their instances in
+// chunks of 64 consecutive slots; each lane finds the Gaussian owning its
+// slot by a binary search over the wave's exclusive counts.  Stores are
+// coalesced.  Tile-digit histograms for the following sort are accumulated
+// in LDS.
 
 __global__ __launch_bounds__(256) void k_emit(int n, const uint32_t *__restrict__ order,
                                               const unsigned long long *__restrict__ offsets,
@@ -460,24 +513,70 @@ __global__ __launch_bounds__(256) void k_emit(int n, const uint32_t *__restrict_
                                               int passes, int shift0, int bits0, int shift1, int bits1,
                                               uint32_t *__restrict__ tile_hist) {
     __shared__ uint32_t h[2][256];
-    for (int i = threadIdx.x; i < 512; i += blockDim.x) (&h[0][0])[i] = 0;
+    for (int q = threadIdx.x; q < 512; q += blockDim.x) (&h[0][0])[q] = 0;
     __syncthreads();
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
     const uint32_t g = i < n ? order[i] : 0xffffffffu;
+    int x0 = 0, y0 = 0, w = 1, cnt = 0;
+    unsigned long long base = 0;
     if (g < (uint32_t)n) {
         const uint2 rc = rect[g];
-        const int x0 = rc.x & 0xffff, y0 = rc.x >> 16, x1 = rc.y & 0xffff, y1 = rc.y >> 16;
-        unsigned long long o = offsets[i];
-        const uint32_t m0 = (1u << bits0) - 1u, m1 = (1u << bits1) - 1u;
-        for (int ty = y0; ty < y1; ++ty) {
-            for (int tx = x0; tx < x1; ++tx, ++o) {
-                if (o >= capacity) break;
-                const uint32_t t = (uint32_t)(ty * tiles_x + tx);
-                tkeys[o] = t;
-                tvals[o] = g;
-                atomicAdd(&h[0][(t >> shift0) & m0], 1u);
-                if (passes > 1) atomicAdd(&h[1][(t >> shift1) & m1], 1u);
+        x0 = rc.x & 0xffff;
+        y0 = rc.x >> 16;
+        w = (int)(rc.y & 0xffff) - x0;
+        cnt = w * ((int)(rc.y >> 16) - y0);
+        if (cnt <= 0) { cnt = 0; w = 1; }
+        base = offsets[i];
+    }
+    // inclusive scan of counts over the wave
+    int incl = cnt;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+    }
+    const int excl = incl - cnt;
+    const int total = __shfl(incl, 63, 64);
+    // slot 0 of the wave: the first lane's offset minus its exclusive count (0)
+    const unsigned long long wbase = __shfl(base, 0, 64) - (unsigned long long)__shfl(excl, 0, 64);
+    const uint32_t m0 = (1u << bits0) - 1u, m1 = (1u << bits1) - 1u;
+    const uint64_t lt = lanemask_lt64();
+    for (int jb = 0; jb < total; jb += 64) {
+        const int j = jb + lane;
+        // owner: the largest lane l with excl_l <= j (it has cnt_l > 0 when j < total)
+        int lo = 0;
+#pragma unroll
+        for (int step = 32; step >= 1; step >>= 1) {
+            const int cand = lo + step;
+            const int e = __shfl(excl, cand < 64 ? cand : 63, 64);
+            if (cand < 64 && e <= j) lo = cand;
+        }
+        const int r = j - __shfl(excl, lo, 64);
+        const int ow = __shfl(w, lo, 64);
+        const int ox = __shfl(x0, lo, 64);
+        const int oy = __shfl(y0, lo, 64);
+        const uint32_t og = __shfl(g, lo, 64);
+        const unsigned long long o = wbase + (unsigned long long)j;
+        const bool live = j < total && o < capacity;
+        uint32_t t = 0;
+        if (live) {
+            const int ry = r / ow;
+            t = (uint32_t)((oy + ry) * tiles_x + ox + (r - ry * ow));
+            tkeys[o] = t;
+            tvals[o] = og;
+            atomicAdd(&h[0][(t >> shift0) & m0], 1u);   // consecutive tiles: few conflicts
+        }
+        if (passes > 1) {
+            // the high digit repeats along a tile row: one LDS atomic per distinct value
+            const uint32_t d1 = (t >> shift1) & m1;
+            uint64_t peers = __ballot(live);
+            for (int bb = 0; bb < bits1; ++bb) {
+                const bool bit = (d1 >> bb) & 1u;
+                const uint64_t bl = __ballot(bit);
+                peers &= bit ? bl : ~bl;
             }
+            if (live && (peers & lt) == 0) atomicAdd(&h[1][d1], (uint32_t)__popcll(peers));
         }
     }
     __syncthreads();
@@ -501,6 +600,20 @@ __global__ __launch_bounds__(256) void k_ranges(const DevStatus *__restrict__ st
 }
 
 // ---------------------------------------------------------------- k_blend
+//
+// Per batch of 256 list entries, each thread stages one Gaussian and decides
+// whether it can reach alpha >= 1/255 anywhere in the tile: the quadratic
+// form d^T Sigma'^-1 d is convex, so its minimum over the rectangle of the
+// tile's pixel centres is 0 if the centre lies inside, else the least of the
+// four clamped edge minima.  Entries that cannot reach the threshold at any
+// pixel are skipped by every pixel anyway, so dropping them changes no
+// result; the cut keeps a margin in the quadratic form that covers its
+// binary32 rounding and that of the per-pixel evaluation.  Survivors are compacted into LDS with their list positions, which
+// keeps n_contrib and the evaluation count in list terms.
+
+__device__ __forceinline__ float quad_form(float A, float B, float C, float dx, float dy) {
+    return (A * dx) * dx + (2.0f * B * dx) * dy + (C * dy) * dy;
+}
 
 __global__ __launch_bounds__(kTilePixels) void k_blend(const uint2 *__restrict__ ranges,
                                                        const uint32_t *__restrict__ gids,
@@ -508,27 +621,30 @@ __global__ __launch_bounds__(kTilePixels) void k_blend(const uint2 *__restrict__
                                                        const float4 *__restrict__ recB,
                                                        const float *__restrict__ recC, int width, int height,
                                                        int tiles_x, int n_tiles, const CamK *__restrict__ camd,
-                                                       float *__restrict__ image, float *__restrict__ final_T,
-                                                       int32_t *__restrict__ n_contrib, DevStatus *__restrict__ st,
-                                                       int passes, int n) {
+                                                       DevStatus *__restrict__ st, int passes, int n) {
     __shared__ float4 sA[kTilePixels];
     __shared__ float4 sB[kTilePixels];
     __shared__ float sC[kTilePixels];
-    // XCD-aware tile order: consecutive blocks go to different XCDs, so give
-    // each XCD a contiguous band of tiles (neighbouring tiles share Gaussians).
-    // The grid is 8 * ceil(n_tiles / 8) blocks; block b runs on XCD b % 8.
+    __shared__ float sS[kTilePixels];
+    __shared__ int sI[kTilePixels];
+    __shared__ int s_wcount[kTilePixels / 64];
+    // The grid is 8 * ceil(n_tiles / 8) blocks; block b runs on XCD b % 8, and
+    // each XCD gets a contiguous band of tiles (neighbours share Gaussians).
     const int b = (int)blockIdx.x;
     const int per = (int)gridDim.x / 8;
     const int tile = (b % 8) * per + b / 8;
     if (tile >= n_tiles) return;
     const int tx = tile % tiles_x, ty = tile / tiles_x;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     if (tile == 0 && tid == 0) {
         st->tiles = (uint32_t)n_tiles;
         st->passes = (uint32_t)passes;
     }
     const int px = tx * kTile + (tid & 15), py = ty * kTile + (tid >> 4);
     const bool inside = px < width && py < height;
+    // pixel-centre rectangle of the tile, clipped to the image
+    const float x_lo = (float)(tx * kTile), x_hi = (float)min(tx * kTile + kTile - 1, width - 1);
+    const float y_lo = (float)(ty * kTile), y_hi = (float)min(ty * kTile + kTile - 1, height - 1);
     const uint2 rg = ranges[tile];
     const int start = (int)rg.x, end = (int)rg.y;
     const float fpx = (float)px, fpy = (float)py;
@@ -537,39 +653,82 @@ __global__ __launch_bounds__(kTilePixels) void k_blend(const uint2 *__restrict__
     int last = 0;
     int evals = inside ? end - start : 0;   // list entries this pixel evaluates
     const float a_min = 1.0f / 255.0f;
+    const uint64_t lt = lanemask_lt64();
     for (int b0 = start; b0 < end; b0 += kTilePixels) {
         if (__syncthreads_count(done) == kTilePixels) break;
+        // stage + cull one entry per thread
         const int i = b0 + tid;
+        bool keep = false;
+        float4 A4 = make_float4(0.f, 0.f, 0.f, 0.f), B4 = A4;
+        float C1 = 0.0f, C1s = 0.0f;
         if (i < end) {
             uint32_t g = gids[i];
             if (g >= (uint32_t)n) g = 0;   // only possible if the sort failed (flagged there)
-            sA[tid] = recA[g];
-            sB[tid] = recB[g];
-            sC[tid] = recC[g];
+            A4 = recA[g];
+            B4 = recB[g];
+            C1 = recC[g];
+            const float A = -2.0f * A4.z, C = -2.0f * A4.w, Bc = -B4.x;
+            const float dxl = A4.x - x_hi, dxh = A4.x - x_lo;
+            const float dyl = A4.y - y_hi, dyh = A4.y - y_lo;
+            float qmin = 0.0f;
+            if (!(dxl <= 0.0f && dxh >= 0.0f && dyl <= 0.0f && dyh >= 0.0f)) {
+                const float ea = fminf(fmaxf(-(Bc * dxl) / C, dyl), dyh);
+                const float eb = fminf(fmaxf(-(Bc * dxh) / C, dyl), dyh);
+                const float ec = fminf(fmaxf(-(Bc * dyl) / A, dxl), dxh);
+                const float ed = fminf(fmaxf(-(Bc * dyh) / A, dxl), dxh);
+                qmin = fminf(fminf(quad_form(A, Bc, C, dxl, ea), quad_form(A, Bc, C, dxh, eb)),
+                             fminf(quad_form(A, Bc, C, ec, dyl), quad_form(A, Bc, C, ed, dyh)));
+            }
+            // alpha >= 1/255 needs q <= 2 ln(255 o).  Margin: 1e-3 relative to the
+            // threshold, plus a bound on the binary32 rounding of q at any
+            // pixel of the tile, |dq| <= 2e-6 (A + C) |d|^2_max.
+            const float thr = 2.0f * (__logf(B4.y) + 5.541263545158426f);
+            const float d2 = fmaxf(dxl * dxl, dxh * dxh) + fmaxf(dyl * dyl, dyh * dyh);
+            keep = !(qmin > thr + 1e-3f * (1.0f + fabsf(thr)) + 2e-6f * (A + C) * d2);
+            // per-pixel pre-test: power < -thr/2 - margin implies alpha < 1/255
+            // (o exp(power) < e^-margin / 255), so exp is only evaluated above it
+            C1s = -0.5f * thr - 1e-3f * (1.0f + fabsf(thr));
+        }
+        const uint64_t kb = __ballot(keep);
+        if (lane == 0) s_wcount[wave] = (int)__popcll(kb);
+        __syncthreads();
+        int base = 0, kept = 0;
+#pragma unroll
+        for (int w = 0; w < kTilePixels / 64; ++w) {
+            const int c = s_wcount[w];
+            if (w < wave) base += c;
+            kept += c;
+        }
+        if (keep) {
+            const int pos = base + (int)__popcll(kb & lt);
+            sA[pos] = A4;
+            sB[pos] = B4;
+            sC[pos] = C1;
+            sS[pos] = C1s;
+            sI[pos] = i - start;
         }
         __syncthreads();
-        const int cnt = min(kTilePixels, end - b0);
         if (!done) {
-            for (int j = 0; j < cnt; ++j) {
+            for (int j = 0; j < kept; ++j) {
                 const float4 A = sA[j];
                 const float4 B = sB[j];
                 const float dx = A.x - fpx, dy = A.y - fpy;
                 const float power = ((A.z * dx) * dx + (A.w * dy) * dy) + (B.x * dx) * dy;
-                if (power > 0.0f) continue;
+                if (power > 0.0f || power < sS[j]) continue;
                 const float alpha = fminf(0.99f, B.y * __expf(power));
                 if (alpha < a_min) continue;
                 const float test = T * (1.0f - alpha);
                 if (test < 0.0001f) {
                     done = true;
-                    evals = b0 - start + j + 1;
+                    evals = sI[j] + 1;
                     break;
                 }
                 const float w = alpha * T;
-                cr += B.z * w;
-                cg += B.w * w;
-                cbl += sC[j] * w;
+                cr = __builtin_fmaf(B.z, w, cr);
+                cg = __builtin_fmaf(B.w, w, cg);
+                cbl = __builtin_fmaf(sC[j], w, cbl);
                 T = test;
-                last = b0 - start + j + 1;
+                last = sI[j] + 1;
             }
         }
     }
@@ -578,7 +737,7 @@ __global__ __launch_bounds__(kTilePixels) void k_blend(const uint2 *__restrict__
         unsigned long long e = (unsigned long long)evals;
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) e += __shfl_xor(e, o, 64);
-        if ((tid & 63) == 0) s_ev[tid >> 6] = e;
+        if (lane == 0) s_ev[wave] = e;
         __syncthreads();
         if (tid == 0) {
             unsigned long long sum = 0;
@@ -587,6 +746,9 @@ __global__ __launch_bounds__(kTilePixels) void k_blend(const uint2 *__restrict__
         }
     }
     if (inside) {
+        float *__restrict__ image = camd->image;
+        float *__restrict__ final_T = camd->final_T;
+        int32_t *__restrict__ n_contrib = camd->n_contrib;
         const float bg0 = camd->bg[0], bg1 = camd->bg[1], bg2 = camd->bg[2];
         const size_t pix = (size_t)py * width + px;
         const size_t plane = (size_t)width * height;
@@ -677,7 +839,10 @@ g4d_status render(const g4d_splats *G, const g4d_camera *C, const g4d_workspace 
     if (C->width < 1 || C->height < 1 || C->width > L.w_max || C->height > L.h_max) return G4D_EINVAL;
     if (n > 0 && (!G->means || !G->scales || !G->quats || !G->opacity || !G->sh)) return G4D_EINVAL;
     if (!(C->fx > 0.0f) || !(C->fy > 0.0f) || !(C->near_plane > 0.0f)) return G4D_EINVAL;
-    const CamK cam = make_cam(C);
+    CamK cam = make_cam(C);
+    cam.image = image;
+    cam.final_T = final_T;
+    cam.n_contrib = n_contrib;
     const int tiles = cam.tiles_x * cam.tiles_y;
     const uint32_t cap = (uint32_t)L.cap;
     const TilePassPlan plan = tile_pass_plan(tiles);
@@ -721,13 +886,14 @@ g4d_status render(const g4d_splats *G, const g4d_camera *C, const g4d_workspace 
                            G->quats, G->opacity, G->sh, camd, recA, recB, recC, rect, touched, dgid, depth_hist, st);
         mark(2);
         // 2. depth sort: four 8-bit passes over n keys; values start as the identity
-        const int sblocks = (n + kSortTile - 1) / kSortTile;
+        const int sblocks = (n + kSortTileN - 1) / kSortTileN;
         const uint32_t *kin[4] = {dgid, dk[1], dk[0], dk[1]};
         const uint32_t *vin[4] = {nullptr, dv[1], dv[0], dv[1]};
         uint32_t *kout[4] = {dk[1], dk[0], dk[1], dk[0]};
         uint32_t *vout[4] = {dv[1], dv[0], dv[1], dv[0]};
         for (int p = 0; p < 4; ++p) {
-            hipLaunchKernelGGL(k_sort_pass, dim3(sblocks), dim3(kSortThreads), 0, s, kin[p], vin[p], kout[p], vout[p],
+            hipLaunchKernelGGL(k_sort_pass<kSortItemsN>, dim3(sblocks), dim3(kSortThreads), 0, s, kin[p], vin[p],
+                               kout[p], vout[p],
                                nullptr, (uint32_t)n, 8 * p, 8, depth_hist + 256 * p,
                                lb_depth + (size_t)p * L.nblk_n * 256, &st->tile_counter[p], &st->sort_error);
         }
@@ -748,7 +914,8 @@ g4d_status render(const g4d_splats *G, const g4d_camera *C, const g4d_workspace 
         const int kblocks = (int)((L.cap + kSortTile - 1) / kSortTile);
         int cur = e;
         for (int p = 0; p < plan.passes; ++p) {
-            hipLaunchKernelGGL(k_sort_pass, dim3(kblocks), dim3(kSortThreads), 0, s, tk[cur], tv[cur], tk[cur ^ 1],
+            hipLaunchKernelGGL(k_sort_pass<kSortItems>, dim3(kblocks), dim3(kSortThreads), 0, s, tk[cur], tv[cur],
+                               tk[cur ^ 1],
                                tv[cur ^ 1], &st->k_used, cap, plan.shift[p], plan.bits[p], tile_hist + 256 * p,
                                lb_tile + (size_t)p * L.nblk_k * 256, &st->tile_counter[5 + p], &st->sort_error);
             cur ^= 1;
@@ -765,7 +932,7 @@ g4d_status render(const g4d_splats *G, const g4d_camera *C, const g4d_workspace 
     mark(7);
     // 7. blend (with n == 0 every range is empty and the image is the background)
     hipLaunchKernelGGL(k_blend, dim3(blend_grid), dim3(kTilePixels), 0, s, ranges, tv[0], recA, recB, recC, C->width,
-                       C->height, cam.tiles_x, tiles, camd, image, final_T, n_contrib, st,
+                       C->height, cam.tiles_x, tiles, camd, st,
                        plan.passes, std::max(n, 1));
     mark(8);
     G4D_HIP_CHECK(hipGetLastError());
@@ -850,8 +1017,9 @@ g4d_status render_export(const g4d_workspace *ws, int32_t kind, int32_t n, int64
 // ---------------------------------------------------------------- graphs
 //
 // A render captured into a graph keeps every pointer and launch shape of its
-// workspace and frame size; the view enters only through k_zero's CamK
-// argument.  These helpers find that node and rewrite its parameters.
+// workspace, input set and frame size; the view and the output buffers enter
+// only through k_zero's frame argument.  These helpers find that node and
+// rewrite its parameters.
 
 g4d_status graph_find_camera_node(hipGraph_t g, hipGraphNode_t *out) {
     size_t count = 0;
@@ -872,13 +1040,16 @@ g4d_status graph_find_camera_node(hipGraph_t g, hipGraphNode_t *out) {
     return G4D_EDEVICE;
 }
 
-g4d_status graph_set_camera(hipGraphExec_t exec, hipGraphNode_t node, const g4d_workspace *ws,
-                            const g4d_camera *C) {
+g4d_status graph_set_frame(hipGraphExec_t exec, hipGraphNode_t node, const g4d_workspace *ws,
+                           const g4d_camera *C, float *image, float *final_T, int32_t *n_contrib) {
     WsLayout L;
-    if (!C || !ws_layout(ws, &L)) return G4D_EINVAL;
+    if (!C || !image || !ws_layout(ws, &L)) return G4D_EINVAL;
     uint4 *p = reinterpret_cast<uint4 *>(ws->ptr);
     size_t n16 = L.zero_bytes / 16;
     CamK cam = make_cam(C);
+    cam.image = image;
+    cam.final_T = final_T;
+    cam.n_contrib = n_contrib;
     CamK *camd = at<CamK>(ws, L.cam);
     void *args[4] = {&p, &n16, &cam, &camd};
     hipKernelNodeParams kp{};
@@ -890,6 +1061,12 @@ g4d_status graph_set_camera(hipGraphExec_t exec, hipGraphNode_t node, const g4d_
     kp.extra = nullptr;
     G4D_HIP_CHECK(hipGraphExecKernelNodeSetParams(exec, node, &kp));
     return G4D_OK;
+}
+
+size_t status_offset(const g4d_workspace *ws) {
+    WsLayout L;
+    if (!ws_layout(ws, &L)) return (size_t)-1;
+    return L.status;
 }
 
 }  // namespace g4d

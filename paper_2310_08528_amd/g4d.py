@@ -85,6 +85,18 @@ class ServerStats(ctypes.Structure):
                 ("eager_renders", c_i64), ("overflow_retries", c_i64), ("peak_bytes", c_sz)]
 
 
+class SimConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget", c_sz), ("max_slots", c_i32), ("batch_deform", c_i32), ("n_requests", c_i32),
+                ("arrival_s", c_p), ("service_s", c_p), ("bytes", c_p), ("class_id", c_p), ("shape_class", c_p),
+                ("overlap", c_f64)]
+
+
+class SimResult(ctypes.Structure):
+    _fields_ = [("p50_ms", c_f64), ("p99_ms", c_f64), ("mean_ms", c_f64), ("max_ms", c_f64),
+                ("makespan_s", c_f64), ("peak_bytes", c_sz), ("max_in_flight", c_i32), ("rejected", c_i32),
+                ("batched_launches", c_i64), ("buffer_reuses", c_i64), ("latency_ms", c_p), ("admit_order", c_p)]
+
+
 # symbol -> (restype, argtypes); the full set declared in include/g4d.h
 SIGNATURES = {
     "g4d_deform": (c_i32, [ctypes.POINTER(Gaussians), ctypes.POINTER(Planes), ctypes.POINTER(MLP), c_f32,
@@ -109,6 +121,7 @@ SIGNATURES = {
     "g4d_server_stats_get": (c_i32, [c_p, ctypes.POINTER(ServerStats)]),
     "g4d_server_reset_stats": (c_i32, [c_p]),
     "g4d_server_destroy": (c_i32, [c_p]),
+    "g4d_server_simulate": (c_i32, [ctypes.POINTER(SimConfig), ctypes.POINTER(SimResult)]),
 }
 
 _lib = None
@@ -330,3 +343,84 @@ def set_stage_events(events):
 
 def version() -> str:
     return load().g4d_version().decode()
+
+
+# ------------------------------------------------------------------ serving
+
+class Server:
+    """Continuous-batching request loop (g4d_server_*).  Scenes are copied
+    into server-owned device memory; images go to caller device tensors."""
+
+    def __init__(self, hbm_budget: int, max_slots: int = 8, use_graphs: bool = True, batch_deform: bool = True,
+                 max_width: int = 1352, max_height: int = 1014, instance_factor: float = 64.0):
+        import torch  # noqa: F401  (one HIP runtime per process)
+        self.lib = load()
+        cfg = ServerConfig(int(hbm_budget), int(max_slots), int(bool(use_graphs)), int(bool(batch_deform)),
+                           int(max_width), int(max_height), float(instance_factor))
+        h = c_p()
+        check(self.lib.g4d_server_create(ctypes.byref(cfg), ctypes.byref(h)), "g4d_server_create")
+        self.h = h
+
+    def add_scene(self, G: DeviceGaussians, P: DevicePlanes, M: DeviceMLP) -> int:
+        gs, ps, ms = G.struct(), P.struct(), M.struct()
+        sid = c_i32()
+        check(self.lib.g4d_server_add_scene(self.h, ctypes.byref(gs), ctypes.byref(ps), ctypes.byref(ms),
+                                            ctypes.byref(sid)), "g4d_server_add_scene")
+        return sid.value
+
+    def submit(self, scene: int, cam, t: float, out) -> int:
+        cs = cam if isinstance(cam, Camera) else camera_struct(cam)
+        tk = ctypes.c_uint64()
+        check(self.lib.g4d_server_submit(self.h, int(scene), ctypes.byref(cs), float(t), _ptr(out),
+                                         ctypes.byref(tk)), "g4d_server_submit")
+        return tk.value
+
+    def wait(self, ticket: int) -> float:
+        ms = c_f64()
+        check(self.lib.g4d_server_wait(self.h, ctypes.c_uint64(ticket), ctypes.byref(ms)), "g4d_server_wait")
+        return ms.value
+
+    def drain(self):
+        check(self.lib.g4d_server_drain(self.h), "g4d_server_drain")
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        check(self.lib.g4d_server_stats_get(self.h, ctypes.byref(st)), "g4d_server_stats_get")
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_}
+
+    def reset_stats(self):
+        check(self.lib.g4d_server_reset_stats(self.h), "g4d_server_reset_stats")
+
+    def close(self):
+        if getattr(self, "h", None):
+            check(self.lib.g4d_server_destroy(self.h), "g4d_server_destroy")
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def simulate(arrival_s, service_s, nbytes, class_id, shape_class, hbm_budget, max_slots, batch_deform=True,
+             overlap=0.5):
+    """Run the serving scheduler on a simulated device (no GPU)."""
+    n = len(arrival_s)
+    a = np.ascontiguousarray(arrival_s, dtype=np.float64)
+    sv = np.ascontiguousarray(service_s, dtype=np.float64)
+    by = np.ascontiguousarray(nbytes, dtype=np.uint64)
+    ci = np.ascontiguousarray(class_id, dtype=np.int32)
+    sc = np.ascontiguousarray(shape_class, dtype=np.int32)
+    lat = np.full(n, -2.0)
+    order = np.full(n, -1, dtype=np.int32)
+    cfg = SimConfig(int(hbm_budget), int(max_slots), int(bool(batch_deform)), n,
+                    a.ctypes.data, sv.ctypes.data, by.ctypes.data, ci.ctypes.data, sc.ctypes.data, float(overlap))
+    res = SimResult()
+    res.latency_ms = lat.ctypes.data
+    res.admit_order = order.ctypes.data
+    check(load().g4d_server_simulate(ctypes.byref(cfg), ctypes.byref(res)), "g4d_server_simulate")
+    out = {k: getattr(res, k) for k, _ in SimResult._fields_ if k not in ("latency_ms", "admit_order")}
+    out["latency_ms"] = lat
+    out["admit_order"] = order
+    return out
