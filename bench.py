@@ -29,12 +29,15 @@ sys.path.insert(0, ROOT)
 
 METRIC = "deform+splat frames/s @800², 100k Gaussians; served p50/p99 ms vs plain"
 
-# MI355X published peaks
+# MI355X peaks: published HBM and FP32 vector; the VALU issue peak for single
+# (non-packed, non-fused) binary32 operations derived from the unit counts:
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
+PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 # Algorithmic work per unit (measurement section)
-BLEND_FLOP_PER_EVAL = 14          # binary32 ops per evaluated (pixel, Gaussian) pair
+BLEND_FLOP_PER_EVAL = 15          # binary32 ops per evaluated (pixel, Gaussian) pair
 STAGES = ["clear", "preprocess", "depth_sort", "offsets", "emit", "tile_sort", "ranges", "blend"]
 
 
@@ -125,13 +128,16 @@ def serving_bench(seconds: float, rate: float, budget_gb: float, slots: int, war
         srv = g4d.Server(int(budget_gb * (1 << 30)), max_slots=slots_, use_graphs=graphs, batch_deform=batch,
                          max_width=1352, max_height=1014)
         ids = [srv.add_scene(*d) for d in dev_scenes]
+        log(f"serving ({slots_} slots, graphs={graphs}, batch={batch}): warming {len(ids) * len(res)} classes")
         # warm every (scene, frame size) class once: sizes its capacity, captures its graph
         for si in ids:
             for ri, r in enumerate(res):
                 srv.wait(srv.submit(si, cams[si][ri][0], 0.5, outs[r][0]))
         srv.reset_stats()
+        log("serving: trace")
         t0 = time.perf_counter()
         k = 0
+        next_log = 5.0
         for (ta, si, ci, t, r) in trace:
             delay = t0 + ta - time.perf_counter()
             if delay > 0:
@@ -140,11 +146,15 @@ def serving_bench(seconds: float, rate: float, budget_gb: float, slots: int, war
                 srv.reset_stats()
             k += ta >= warm_s
             srv.submit(si, cams[si][res.index(tuple(r))][ci], t, outs[tuple(r)][k % 48])
+            if ta >= next_log:
+                log(f"serving: t={ta:.0f} s, {k} requests")
+                next_log += 5.0
         srv.drain()
         st = srv.stats()
         srv.close()
         return st
 
+    log("serving: scenes ready")
     served = run(slots, True, True)
     log(f"served: {served}")
     plain = run(1, False, False)
@@ -159,6 +169,8 @@ def serving_bench(seconds: float, rate: float, budget_gb: float, slots: int, war
 
 
 def main():
+    import faulthandler
+    faulthandler.dump_traceback_later(90, repeat=True, file=sys.stderr)
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=400)
@@ -167,6 +179,8 @@ def main():
     ap.add_argument("--cpu-frames", type=int, default=3)
     ap.add_argument("--n", type=int, default=100_000)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 256 MiB device copy (for scaling HBM byte counters)")
     ap.add_argument("--serve-seconds", type=float, default=20.0)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-slots", type=int, default=16)
@@ -235,11 +249,21 @@ def main():
         if r1 or r2:
             raise g4d.G4DError(r1 or r2, "bench step")
 
+    log("warm-up")
     for k in range(args.warmup):
         step(k)
     torch.cuda.synchronize()
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 5 x 256 MiB device-to-device copies")
+        del src, dst
 
     # ---- timed region: K frames; HIP events around the blend kernel only
+    log("timed region")
     K = args.steps
     blend_ev = [(ev.create(), ev.create()) for _ in range(K)]
     blend_arr = [(ctypes.c_void_p * 9)(*([None] * 7 + [a, b])) for a, b in blend_ev]
@@ -254,6 +278,7 @@ def main():
     st = g4d.read_status(ws)
     assert st.overflow == 0 and st.sort_error == 0
 
+    log(f"timed: {fps:.1f} frames/s; stage breakdown")
     # ---- per-stage breakdown (separate pass with events at every boundary)
     n_prof = min(K, 100)
     stage_ev = [[ev.create() for _ in range(9)] for _ in range(n_prof)]
@@ -278,9 +303,10 @@ def main():
     blend_flop = evals_per_frame * BLEND_FLOP_PER_EVAL
     achieved = blend_flop / (blend_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "kernel": "k_blend", "achieved": round(achieved, 3),
-                "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                "peak": round(PEAK_VALU_TOPS, 2), "unit": "TFLOP/s", "frac": round(achieved / PEAK_VALU_TOPS, 4),
                 "traffic": None, "evals_per_frame": int(evals_per_frame),
-                "flop_per_eval": BLEND_FLOP_PER_EVAL, "avg_ms": round(blend_ms, 4)}
+                "flop_per_eval": BLEND_FLOP_PER_EVAL, "avg_ms": round(blend_ms, 4),
+                "frac_of_published_fp32": round(achieved / PEAK_FP32_TFLOPS, 4)}
 
     out = {"metric": METRIC, "value": round(fps, 2), "unit": "frames/s", "n_gpus": 1, "steps": K,
            "warmup": args.warmup, "ms_per_step": round(1e3 * wall / K, 4), "higher_is_better": True,
@@ -291,9 +317,11 @@ def main():
                       "capacity": capacity},
            "stages_ms": {k: round(v, 4) for k, v in stages.items()},
            "roofline": roofline}
+    log("stages done")
     if not args.no_serve:
         out["serving"] = serving_bench(args.serve_seconds, args.serve_rate, args.serve_budget_gb, args.serve_slots)
     if not args.no_cpu_baseline:
+        log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(sc, frames, args.cpu_frames)
     for e in blend_ev:
         ev.destroy(e[0]); ev.destroy(e[1])

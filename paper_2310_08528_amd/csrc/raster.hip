@@ -381,24 +381,61 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_pass(
         if (d < NB && k == 0) s_base[d] = excl;
     }
     __syncthreads();
-    if (tid < NB) {
-        uint32_t gex = 0;
-        for (int q = 0; q < tid; ++q) gex += s_g[q];
-        s_base[tid] += gex;
+    // global exclusive digit prefix (over all keys) and this tile's exclusive
+    // digit prefix, by block scans over the NB digits
+    {
+        const uint32_t g = tid < NB ? s_g[tid] : 0u;
+        const uint32_t t = tid < NB ? s_tot[tid] : 0u;
+        uint32_t gi = g, ti = t;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t gy = __shfl_up(gi, o, 64), ty = __shfl_up(ti, o, 64);
+            if (lane >= o) {
+                gi += gy;
+                ti += ty;
+            }
+        }
+        __shared__ uint32_t s_wg[4], s_wt[4];
+        if (lane == 63) {
+            s_wg[wave] = gi;
+            s_wt[wave] = ti;
+        }
+        __syncthreads();
+        uint32_t go = 0, to = 0;
+        for (int w = 0; w < wave; ++w) {
+            go += s_wg[w];
+            to += s_wt[w];
+        }
+        if (tid < NB) {
+            s_base[tid] += go + gi - g;          // where digit tid starts in the output, for this tile
+            s_tot[tid] = to + ti - t;            // where digit tid starts inside this tile
+        }
     }
     __syncthreads();
+    // Reorder the tile by digit in LDS, then write runs of equal digits with
+    // consecutive threads to consecutive addresses.
+    __shared__ uint32_t s_k[TILE], s_v[TILE];
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
         const uint32_t idx = base_idx + r * 64 + lane;
         if (idx < count) {
             const uint32_t d = (keys[r] >> shift) & mask;
-            const uint32_t pos = s_base[d] + s_wcnt[wave][d] + rank[r];
-            if (pos < count) {
-                kout[pos] = keys[r];
-                vout[pos] = vals[r];
-            } else {
-                atomicOr(err, 4u);   // inconsistent counts: never write out of bounds
-            }
+            const uint32_t lpos = s_tot[d] + s_wcnt[wave][d] + rank[r];
+            s_k[lpos] = keys[r];
+            s_v[lpos] = vals[r];
+        }
+    }
+    __syncthreads();
+    const uint32_t in_tile = min(TILE, count - tile * TILE);
+    for (uint32_t li = tid; li < in_tile; li += kSortThreads) {
+        const uint32_t k = s_k[li];
+        const uint32_t d = (k >> shift) & mask;
+        const uint32_t pos = s_base[d] + (li - s_tot[d]);
+        if (pos < count) {
+            kout[pos] = k;
+            vout[pos] = s_v[li];
+        } else {
+            atomicOr(err, 4u);   // inconsistent counts: never write out of bounds
         }
     }
 }
@@ -503,8 +540,28 @@ __global__ __launch_bounds__(256) void k_scan_offsets(int n, const uint32_t *__r
 // order, so their instance blocks are contiguous) write their instances in
 // chunks of 64 consecutive slots; each lane finds the Gaussian owning its
 // slot by a binary search over the wave's exclusive counts.  Stores are
-// coalesced.  Tile-digit histograms for the following sort are accumulated
-// in LDS.
+// coalesced.  The tile-digit histograms of the following sort passes are
+// counted per tile row of each Gaussian (a row is a run of consecutive tile
+// ids): the high digit takes one LDS add per distinct value, the low digit a
+// range update on a difference array; instances past the capacity are left
+// out, as the sort leaves them out.
+
+__device__ __forceinline__ void range_add_mod(int *diff, int *whole, uint32_t a, uint32_t len, uint32_t M) {
+    // add 1 to bins a, a+1, ..., a+len-1 (mod M) using a difference array
+    const uint32_t full = len / M, rem = len % M;
+    if (full) atomicAdd(whole, (int)full);
+    if (!rem) return;
+    const uint32_t st = a % M;
+    if (st + rem <= M) {
+        atomicAdd(&diff[st], 1);
+        atomicAdd(&diff[st + rem], -1);
+    } else {
+        atomicAdd(&diff[st], 1);
+        atomicAdd(&diff[M], -1);
+        atomicAdd(&diff[0], 1);
+        atomicAdd(&diff[st + rem - M], -1);
+    }
+}
 
 __global__ __launch_bounds__(256) void k_emit(int n, const uint32_t *__restrict__ order,
                                               const unsigned long long *__restrict__ offsets,
@@ -512,8 +569,12 @@ __global__ __launch_bounds__(256) void k_emit(int n, const uint32_t *__restrict_
                                               uint32_t *__restrict__ tkeys, uint32_t *__restrict__ tvals,
                                               int passes, int shift0, int bits0, int shift1, int bits1,
                                               uint32_t *__restrict__ tile_hist) {
-    __shared__ uint32_t h[2][256];
-    for (int q = threadIdx.x; q < 512; q += blockDim.x) (&h[0][0])[q] = 0;
+    __shared__ int s_diff[257];
+    __shared__ int s_whole;
+    __shared__ uint32_t s_h1[256];
+    for (int q = threadIdx.x; q < 257; q += blockDim.x) s_diff[q] = 0;
+    for (int q = threadIdx.x; q < 256; q += blockDim.x) s_h1[q] = 0;
+    if (threadIdx.x == 0) s_whole = 0;
     __syncthreads();
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63;
@@ -529,7 +590,24 @@ __global__ __launch_bounds__(256) void k_emit(int n, const uint32_t *__restrict_
         if (cnt <= 0) { cnt = 0; w = 1; }
         base = offsets[i];
     }
-    // inclusive scan of counts over the wave
+    // ---- digit histograms of this lane's instances (those below capacity)
+    {
+        const uint32_t M0 = 1u << bits0;
+        long long keep = base < capacity ? (long long)min<unsigned long long>((unsigned long long)cnt, capacity - base) : 0;
+        for (int ty = y0; keep > 0; ++ty) {
+            const uint32_t seg = (uint32_t)min<long long>(w, keep);
+            keep -= seg;
+            const uint32_t r0 = (uint32_t)(ty * tiles_x + x0), r1 = r0 + seg;   // tiles [r0, r1)
+            range_add_mod(s_diff, &s_whole, r0 >> shift0, seg, M0);               // shift0 is 0
+            if (passes > 1) {
+                for (uint32_t v = r0 >> shift1; v <= (r1 - 1) >> shift1; ++v) {
+                    const uint32_t lo = max(r0, v << shift1), hi = min(r1, (v + 1) << shift1);
+                    atomicAdd(&s_h1[v & ((1u << bits1) - 1u)], hi - lo);
+                }
+            }
+        }
+    }
+    // ---- coalesced fan-out
     int incl = cnt;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
@@ -540,8 +618,6 @@ __global__ __launch_bounds__(256) void k_emit(int n, const uint32_t *__restrict_
     const int total = __shfl(incl, 63, 64);
     // slot 0 of the wave: the first lane's offset minus its exclusive count (0)
     const unsigned long long wbase = __shfl(base, 0, 64) - (unsigned long long)__shfl(excl, 0, 64);
-    const uint32_t m0 = (1u << bits0) - 1u, m1 = (1u << bits1) - 1u;
-    const uint64_t lt = lanemask_lt64();
     for (int jb = 0; jb < total; jb += 64) {
         const int j = jb + lane;
         // owner: the largest lane l with excl_l <= j (it has cnt_l > 0 when j < total)
@@ -558,31 +634,39 @@ __global__ __launch_bounds__(256) void k_emit(int n, const uint32_t *__restrict_
         const int oy = __shfl(y0, lo, 64);
         const uint32_t og = __shfl(g, lo, 64);
         const unsigned long long o = wbase + (unsigned long long)j;
-        const bool live = j < total && o < capacity;
-        uint32_t t = 0;
-        if (live) {
+        if (j < total && o < capacity) {
             const int ry = r / ow;
-            t = (uint32_t)((oy + ry) * tiles_x + ox + (r - ry * ow));
-            tkeys[o] = t;
+            tkeys[o] = (uint32_t)((oy + ry) * tiles_x + ox + (r - ry * ow));
             tvals[o] = og;
-            atomicAdd(&h[0][(t >> shift0) & m0], 1u);   // consecutive tiles: few conflicts
-        }
-        if (passes > 1) {
-            // the high digit repeats along a tile row: one LDS atomic per distinct value
-            const uint32_t d1 = (t >> shift1) & m1;
-            uint64_t peers = __ballot(live);
-            for (int bb = 0; bb < bits1; ++bb) {
-                const bool bit = (d1 >> bb) & 1u;
-                const uint64_t bl = __ballot(bit);
-                peers &= bit ? bl : ~bl;
-            }
-            if (live && (peers & lt) == 0) atomicAdd(&h[1][d1], (uint32_t)__popcll(peers));
         }
     }
     __syncthreads();
-    for (int q = threadIdx.x; q < 512; q += blockDim.x) {
-        const uint32_t c = (&h[0][0])[q];
-        if (c) atomicAdd(&tile_hist[q], c);
+    // ---- flush: prefix of the difference array gives the low-digit counts
+    if (threadIdx.x < 64) {
+        const uint32_t M0 = 1u << bits0;
+        // M0 <= 256 bins, 4 per lane, serial within the lane then a wave scan
+        int v[4];
+        int acc = 0;
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t bin = threadIdx.x * 4 + q;
+            acc += bin < M0 ? s_diff[bin] : 0;
+            v[q] = acc;
+        }
+        int x = acc;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        const int off = x - acc + s_whole;
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t bin = threadIdx.x * 4 + q;
+            if (bin < M0 && v[q] + off) atomicAdd(&tile_hist[bin], (uint32_t)(v[q] + off));
+        }
+    }
+    if (passes > 1) {
+        for (int q = threadIdx.x; q < (1 << bits1); q += blockDim.x)
+            if (s_h1[q]) atomicAdd(&tile_hist[256 + q], s_h1[q]);
     }
 }
 
@@ -601,18 +685,40 @@ __global__ __launch_bounds__(256) void k_ranges(const DevStatus *__restrict__ st
 
 // ---------------------------------------------------------------- k_blend
 //
-// Per batch of 256 list entries, each thread stages one Gaussian and decides
-// whether it can reach alpha >= 1/255 anywhere in the tile: the quadratic
-// form d^T Sigma'^-1 d is convex, so its minimum over the rectangle of the
-// tile's pixel centres is 0 if the centre lies inside, else the least of the
-// four clamped edge minima.  Entries that cannot reach the threshold at any
-// pixel are skipped by every pixel anyway, so dropping them changes no
-// result; the cut keeps a margin in the quadratic form that covers its
-// binary32 rounding and that of the per-pixel evaluation.  Survivors are compacted into LDS with their list positions, which
-// keeps n_contrib and the evaluation count in list terms.
+// One 256-thread block per 16x16 tile; wave w owns the 8x8 quadrant
+// (w & 1, w >> 1), lane l the pixel (l & 7, l >> 3) inside it.  Per batch of
+// 256 list entries each thread stages one Gaussian and decides, for each of
+// the four quadrants, whether it can reach alpha >= 1/255 at any pixel
+// there: the quadratic form d^T Sigma'^-1 d is convex, so its minimum over
+// the rectangle of pixel centres is 0 if the centre lies inside, else the
+// least of the four clamped edge minima.  An entry that cannot reach the
+// threshold in a quadrant is skipped by every pixel of it anyway, so leaving
+// it out of that quadrant's list changes no result; the cut keeps a margin
+// covering the binary32 rounding of both the cut and the per-pixel value.
+// Each quadrant's list (list order kept, list positions stored) is compacted
+// into LDS; the wave then composites it with a branch-free body and leaves
+// once all its pixels are done.
 
 __device__ __forceinline__ float quad_form(float A, float B, float C, float dx, float dy) {
     return (A * dx) * dx + (2.0f * B * dx) * dy + (C * dy) * dy;
+}
+
+// Can a Gaussian (centre u, v; conic A, B, C; cut threshold thr on the
+// quadratic form) reach the threshold inside [x_lo, x_hi] x [y_lo, y_hi]?
+__device__ __forceinline__ bool rect_may_reach(float u, float v, float A, float B, float C, float thr, float x_lo,
+                                               float x_hi, float y_lo, float y_hi) {
+    if (x_hi < x_lo || y_hi < y_lo) return false;   // quadrant outside the image
+    const float dxl = u - x_hi, dxh = u - x_lo;
+    const float dyl = v - y_hi, dyh = v - y_lo;
+    if (dxl <= 0.0f && dxh >= 0.0f && dyl <= 0.0f && dyh >= 0.0f) return true;
+    const float ea = fminf(fmaxf(-(B * dxl) / C, dyl), dyh);
+    const float eb = fminf(fmaxf(-(B * dxh) / C, dyl), dyh);
+    const float ec = fminf(fmaxf(-(B * dyl) / A, dxl), dxh);
+    const float ed = fminf(fmaxf(-(B * dyh) / A, dxl), dxh);
+    const float qmin = fminf(fminf(quad_form(A, B, C, dxl, ea), quad_form(A, B, C, dxh, eb)),
+                             fminf(quad_form(A, B, C, ec, dyl), quad_form(A, B, C, ed, dyh)));
+    const float d2 = fmaxf(dxl * dxl, dxh * dxh) + fmaxf(dyl * dyl, dyh * dyh);
+    return !(qmin > thr + 1e-3f * (1.0f + fabsf(thr)) + 2e-6f * (A + C) * d2);
 }
 
 __global__ __launch_bounds__(kTilePixels) void k_blend(const uint2 *__restrict__ ranges,
@@ -622,12 +728,11 @@ __global__ __launch_bounds__(kTilePixels) void k_blend(const uint2 *__restrict__
                                                        const float *__restrict__ recC, int width, int height,
                                                        int tiles_x, int n_tiles, const CamK *__restrict__ camd,
                                                        DevStatus *__restrict__ st, int passes, int n) {
-    __shared__ float4 sA[kTilePixels];
-    __shared__ float4 sB[kTilePixels];
-    __shared__ float sC[kTilePixels];
-    __shared__ float sS[kTilePixels];
-    __shared__ int sI[kTilePixels];
-    __shared__ int s_wcount[kTilePixels / 64];
+    constexpr int NW = kTilePixels / 64;                   // waves = quadrants
+    __shared__ float4 sA[NW][kTilePixels];
+    __shared__ float4 sB[NW][kTilePixels];
+    __shared__ float2 sCI[NW][kTilePixels];                // (blue, list position as bits)
+    __shared__ int s_cnt[NW][NW];                          // [staging wave][quadrant]
     // The grid is 8 * ceil(n_tiles / 8) blocks; block b runs on XCD b % 8, and
     // each XCD gets a contiguous band of tiles (neighbours share Gaussians).
     const int b = (int)blockIdx.x;
@@ -640,11 +745,9 @@ __global__ __launch_bounds__(kTilePixels) void k_blend(const uint2 *__restrict__
         st->tiles = (uint32_t)n_tiles;
         st->passes = (uint32_t)passes;
     }
-    const int px = tx * kTile + (tid & 15), py = ty * kTile + (tid >> 4);
+    const int qx0 = tx * kTile + (wave & 1) * 8, qy0 = ty * kTile + (wave >> 1) * 8;
+    const int px = qx0 + (lane & 7), py = qy0 + (lane >> 3);
     const bool inside = px < width && py < height;
-    // pixel-centre rectangle of the tile, clipped to the image
-    const float x_lo = (float)(tx * kTile), x_hi = (float)min(tx * kTile + kTile - 1, width - 1);
-    const float y_lo = (float)(ty * kTile), y_hi = (float)min(ty * kTile + kTile - 1, height - 1);
     const uint2 rg = ranges[tile];
     const int start = (int)rg.x, end = (int)rg.y;
     const float fpx = (float)px, fpy = (float)py;
@@ -656,84 +759,87 @@ __global__ __launch_bounds__(kTilePixels) void k_blend(const uint2 *__restrict__
     const uint64_t lt = lanemask_lt64();
     for (int b0 = start; b0 < end; b0 += kTilePixels) {
         if (__syncthreads_count(done) == kTilePixels) break;
-        // stage + cull one entry per thread
+        // ---- stage one entry per thread; quadrant masks
         const int i = b0 + tid;
-        bool keep = false;
+        uint32_t qmask = 0;
         float4 A4 = make_float4(0.f, 0.f, 0.f, 0.f), B4 = A4;
-        float C1 = 0.0f, C1s = 0.0f;
+        float C1 = 0.0f;
         if (i < end) {
             uint32_t g = gids[i];
             if (g >= (uint32_t)n) g = 0;   // only possible if the sort failed (flagged there)
             A4 = recA[g];
             B4 = recB[g];
             C1 = recC[g];
+            // conic from the stored halves: A = -2 ha, C = -2 hc, B = -nb
             const float A = -2.0f * A4.z, C = -2.0f * A4.w, Bc = -B4.x;
-            const float dxl = A4.x - x_hi, dxh = A4.x - x_lo;
-            const float dyl = A4.y - y_hi, dyh = A4.y - y_lo;
-            float qmin = 0.0f;
-            if (!(dxl <= 0.0f && dxh >= 0.0f && dyl <= 0.0f && dyh >= 0.0f)) {
-                const float ea = fminf(fmaxf(-(Bc * dxl) / C, dyl), dyh);
-                const float eb = fminf(fmaxf(-(Bc * dxh) / C, dyl), dyh);
-                const float ec = fminf(fmaxf(-(Bc * dyl) / A, dxl), dxh);
-                const float ed = fminf(fmaxf(-(Bc * dyh) / A, dxl), dxh);
-                qmin = fminf(fminf(quad_form(A, Bc, C, dxl, ea), quad_form(A, Bc, C, dxh, eb)),
-                             fminf(quad_form(A, Bc, C, ec, dyl), quad_form(A, Bc, C, ed, dyh)));
-            }
-            // alpha >= 1/255 needs q <= 2 ln(255 o).  Margin: 1e-3 relative to the
-            // threshold, plus a bound on the binary32 rounding of q at any
-            // pixel of the tile, |dq| <= 2e-6 (A + C) |d|^2_max.
+            // alpha >= 1/255 needs q <= 2 ln(255 o)
             const float thr = 2.0f * (__logf(B4.y) + 5.541263545158426f);
-            const float d2 = fmaxf(dxl * dxl, dxh * dxh) + fmaxf(dyl * dyl, dyh * dyh);
-            keep = !(qmin > thr + 1e-3f * (1.0f + fabsf(thr)) + 2e-6f * (A + C) * d2);
-            // per-pixel pre-test: power < -thr/2 - margin implies alpha < 1/255
-            // (o exp(power) < e^-margin / 255), so exp is only evaluated above it
-            C1s = -0.5f * thr - 1e-3f * (1.0f + fabsf(thr));
-        }
-        const uint64_t kb = __ballot(keep);
-        if (lane == 0) s_wcount[wave] = (int)__popcll(kb);
-        __syncthreads();
-        int base = 0, kept = 0;
 #pragma unroll
-        for (int w = 0; w < kTilePixels / 64; ++w) {
-            const int c = s_wcount[w];
-            if (w < wave) base += c;
-            kept += c;
+            for (int q = 0; q < NW; ++q) {
+                const float x_lo = (float)(tx * kTile + (q & 1) * 8);
+                const float y_lo = (float)(ty * kTile + (q >> 1) * 8);
+                const float x_hi = fminf(x_lo + 7.0f, (float)(width - 1));
+                const float y_hi = fminf(y_lo + 7.0f, (float)(height - 1));
+                if (rect_may_reach(A4.x, A4.y, A, Bc, C, thr, x_lo, x_hi, y_lo, y_hi)) qmask |= 1u << q;
+            }
         }
-        if (keep) {
-            const int pos = base + (int)__popcll(kb & lt);
-            sA[pos] = A4;
-            sB[pos] = B4;
-            sC[pos] = C1;
-            sS[pos] = C1s;
-            sI[pos] = i - start;
+        uint64_t bal[NW];
+#pragma unroll
+        for (int q = 0; q < NW; ++q) bal[q] = __ballot((qmask >> q) & 1u);
+        if (lane == 0) {
+#pragma unroll
+            for (int q = 0; q < NW; ++q) s_cnt[wave][q] = (int)__popcll(bal[q]);
         }
         __syncthreads();
-        if (!done) {
+        int kept = 0;      // entries in this wave's own quadrant list
+#pragma unroll
+        for (int q = 0; q < NW; ++q) {
+            int base = 0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                const int c = s_cnt[w][q];
+                if (w < wave) base += c;
+                if (q == wave) kept += c;
+            }
+            if ((qmask >> q) & 1u) {
+                const int pos = base + (int)__popcll(bal[q] & lt);
+                sA[q][pos] = A4;
+                sB[q][pos] = B4;
+                sCI[q][pos] = make_float2(C1, __int_as_float(i - start));
+            }
+        }
+        __syncthreads();
+        // ---- composite this wave's list (branch-free body)
+        if (!__all(done)) {
+            const float4 *__restrict__ LA = sA[wave];
+            const float4 *__restrict__ LB = sB[wave];
+            const float2 *__restrict__ LC = sCI[wave];
             for (int j = 0; j < kept; ++j) {
-                const float4 A = sA[j];
-                const float4 B = sB[j];
+                const float4 A = LA[j];
+                const float4 B = LB[j];
+                const float2 CI = LC[j];
                 const float dx = A.x - fpx, dy = A.y - fpy;
                 const float power = ((A.z * dx) * dx + (A.w * dy) * dy) + (B.x * dx) * dy;
-                if (power > 0.0f || power < sS[j]) continue;
                 const float alpha = fminf(0.99f, B.y * __expf(power));
-                if (alpha < a_min) continue;
                 const float test = T * (1.0f - alpha);
-                if (test < 0.0001f) {
-                    done = true;
-                    evals = sI[j] + 1;
-                    break;
-                }
-                const float w = alpha * T;
+                const bool valid = !done && !(power > 0.0f) && !(alpha < a_min);
+                const bool stop = valid && test < 0.0001f;
+                const bool add = valid && !stop;
+                const float w = add ? alpha * T : 0.0f;
                 cr = __builtin_fmaf(B.z, w, cr);
                 cg = __builtin_fmaf(B.w, w, cg);
-                cbl = __builtin_fmaf(sC[j], w, cbl);
-                T = test;
-                last = sI[j] + 1;
+                cbl = __builtin_fmaf(CI.x, w, cbl);
+                T = add ? test : T;
+                const int pos1 = __float_as_int(CI.y) + 1;
+                last = add ? pos1 : last;
+                evals = stop ? pos1 : evals;
+                done = done || stop;
+                if (__all(done)) break;
             }
         }
     }
     {
-        __shared__ unsigned long long s_ev[kTilePixels / 64];
+        __shared__ unsigned long long s_ev[NW];
         unsigned long long e = (unsigned long long)evals;
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) e += __shfl_xor(e, o, 64);
@@ -741,7 +847,7 @@ __global__ __launch_bounds__(kTilePixels) void k_blend(const uint2 *__restrict__
         __syncthreads();
         if (tid == 0) {
             unsigned long long sum = 0;
-            for (int w = 0; w < kTilePixels / 64; ++w) sum += s_ev[w];
+            for (int w = 0; w < NW; ++w) sum += s_ev[w];
             if (sum) atomicAdd(&st->blend_evals, sum);
         }
     }

@@ -248,3 +248,46 @@ def test_full_size_config2_one_frame(dev):
     host, _ = gpu_deform(sc, t)
     s = oracle.to_splats32(host, sc.gaussians.sh, 3)
     _check_render(s, cam, "C2 full frame", capacity=8 << 20)
+
+
+# ------------------------------------------------------- large config, BF16 MLP
+
+def _bf16_report(sc, t):
+    host32, _ = gpu_deform(sc, t, precision=g4d.MLP_F32)
+    host16, _ = gpu_deform(sc, t, precision=g4d.MLP_BF16)
+    d64 = oracle.deform(sc.gaussians, sc.planes, sc.mlp, t)
+    emu = oracle.deform(sc.gaussians, sc.planes, sc.mlp, t, bf16_emulate=True)
+    rep = {}
+    for k in ("means", "scales", "quats"):
+        ref = getattr(d64, k)
+        e16 = np.abs(getattr(host16, k) - ref) / (1 + np.abs(ref))
+        e32 = np.abs(getattr(host32, k) - ref) / (1 + np.abs(ref))
+        eem = np.abs(getattr(host16, k) - getattr(emu, k)) / (1 + np.abs(getattr(emu, k)))
+        rep[k] = (float(e32.max()), float(e16.max()), float(e16.mean()), float(eem.max()), float(np.median(eem)))
+    for k, v in rep.items():
+        log(f"   {k}: fp32 max {v[0]:.2e} | bf16 vs fp64 max {v[1]:.2e} mean {v[2]:.2e} | "
+            f"bf16 vs bf16-emulation max {v[3]:.2e} median {v[4]:.2e}")
+    return host32, host16, rep
+
+
+def test_deform_large_config_fp32_and_bf16(dev):
+    sc = synth.config4(plane_dist="uniform", n=30_000)
+    log(f"[deform large] n={sc.gaussians.n} planes 64/128/256 t150, MLP 96-128-10")
+    host32, host16, rep = _bf16_report(sc, 0.43)
+    tol = def_tol(sc.planes)
+    for k, v in rep.items():
+        assert v[0] <= tol, (k, v[0], tol)
+        # BF16 inputs carry 8 significant bits; accumulation stays FP32
+        assert v[1] <= 0.05 and v[2] <= 5e-3, (k, v)
+        # against the BF16 emulation only rare rounding-boundary flips of f_h remain
+        assert v[4] <= 1e-5, (k, v)
+
+
+def test_full_size_large_config_bf16_frame(dev):
+    """300k Gaussians, 1352x1014, BF16 MLP: the GPU's deformed set renders with
+    bit-exact keys and the image within tolerance of the oracle."""
+    sc = synth.config4()
+    cam, t = sc.cameras[5], float(sc.timestamps[123])
+    host16, _ = gpu_deform(sc, t, precision=g4d.MLP_BF16)
+    s = oracle.to_splats32(host16, sc.gaussians.sh, 3)
+    _check_render(s, cam, "large config BF16 frame", capacity=32 << 20)
