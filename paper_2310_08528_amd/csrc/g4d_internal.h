@@ -15,7 +15,7 @@ namespace g4d {
 constexpr int kTile = G4D_TILE;              // 16x16 pixel tiles
 constexpr int kTilePixels = kTile * kTile;   // one blend block per tile
 
-// Radix-sort tiling: 256 threads x 16 items per block.
+// Radix-sort tiling: 256 threads x kSortItems keys per block.
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortThreads * kSortItems;   // 4096 keys per block (instances)
@@ -60,10 +60,11 @@ struct WsLayout {
     int32_t nblk_n;      // sort blocks over n
     int32_t nblk_k;      // sort blocks over capacity
     int32_t nscan;       // scan blocks over n
-    size_t status, depth_hist, tile_hist, lb_depth, lb_tile, lb_scan, ranges;
+    size_t status, depth_hist, lb_depth, lb_scan, ranges;
     size_t zero_bytes;
     size_t cam;
     size_t recA, recB, recC, rect, touched, dgid, dk0, dk1, dv0, dv1, offsets, tk0, tk1, tv0, tv1;
+    size_t tcnt, tdtot;  // instance sort: per-pass digit counts [256][nblk_k] and digit totals [256]
     size_t total;
 };
 
@@ -82,9 +83,7 @@ inline bool make_layout(int32_t n, int32_t w, int32_t h, int64_t cap, WsLayout *
     auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes, 256); return r; };
     L->status = take(sizeof(DevStatus));
     L->depth_hist = take(4 * 256 * 4);
-    L->tile_hist = take(2 * 256 * 4);
     L->lb_depth = take((size_t)4 * L->nblk_n * 256 * 4);
-    L->lb_tile = take((size_t)2 * L->nblk_k * 256 * 4);
     L->lb_scan = take((size_t)L->nscan * 8);
     L->ranges = take((size_t)L->tiles_max * 8);
     L->zero_bytes = o;
@@ -104,6 +103,8 @@ inline bool make_layout(int32_t n, int32_t w, int32_t h, int64_t cap, WsLayout *
     L->tk1 = take((size_t)cap * 4);
     L->tv0 = take((size_t)cap * 4);
     L->tv1 = take((size_t)cap * 4);
+    L->tcnt = take((size_t)2 * 256 * L->nblk_k * 4);
+    L->tdtot = take((size_t)2 * 256 * 4);
     L->total = o;
     return true;
 }

@@ -80,18 +80,13 @@ __global__ void k_zero(uint4 *__restrict__ p, size_t n16, CamK cam, CamK *__rest
 #define SH_C0 0.28209479177387814f
 #define SH_C1 0.4886025119029199f
 
-__device__ __forceinline__ float3 sh_colour(int deg, const float *__restrict__ sh, int n, int g, float x, float y,
-                                            float z) {
-    float3 c;
-    const size_t cs = (size_t)n;          // channel stride
-    const size_t ks = (size_t)3 * n;      // coefficient stride
-    auto coef = [&](int k, int ch) { return sh[(size_t)k * ks + ch * cs + g]; };
-    float r = SH_C0 * coef(0, 0), gg = SH_C0 * coef(0, 1), b = SH_C0 * coef(0, 2);
+__device__ __forceinline__ float3 sh_colour(int deg, const float (&c)[16][3], float x, float y, float z) {
+    float r = SH_C0 * c[0][0], gg = SH_C0 * c[0][1], b = SH_C0 * c[0][2];
     if (deg >= 1) {
         const float y1 = -SH_C1 * y, y2 = SH_C1 * z, y3 = -SH_C1 * x;
-        r += y1 * coef(1, 0) + y2 * coef(2, 0) + y3 * coef(3, 0);
-        gg += y1 * coef(1, 1) + y2 * coef(2, 1) + y3 * coef(3, 1);
-        b += y1 * coef(1, 2) + y2 * coef(2, 2) + y3 * coef(3, 2);
+        r += y1 * c[1][0] + y2 * c[2][0] + y3 * c[3][0];
+        gg += y1 * c[1][1] + y2 * c[2][1] + y3 * c[3][1];
+        b += y1 * c[1][2] + y2 * c[2][2] + y3 * c[3][2];
         if (deg >= 2) {
             const float xx = x * x, yy = y * y, zz = z * z, xy = x * y, yz = y * z, xz = x * z;
             const float Y[5] = {1.0925484305920792f * xy, -1.0925484305920792f * yz,
@@ -99,9 +94,9 @@ __device__ __forceinline__ float3 sh_colour(int deg, const float *__restrict__ s
                                 0.5462742152960396f * (xx - yy)};
 #pragma unroll
             for (int k = 0; k < 5; ++k) {
-                r += Y[k] * coef(4 + k, 0);
-                gg += Y[k] * coef(4 + k, 1);
-                b += Y[k] * coef(4 + k, 2);
+                r += Y[k] * c[4 + k][0];
+                gg += Y[k] * c[4 + k][1];
+                b += Y[k] * c[4 + k][2];
             }
             if (deg >= 3) {
                 const float Z[7] = {-0.5900435899266435f * y * (3.0f * xx - yy),
@@ -113,17 +108,18 @@ __device__ __forceinline__ float3 sh_colour(int deg, const float *__restrict__ s
                                     -0.5900435899266435f * x * (xx - 3.0f * yy)};
 #pragma unroll
                 for (int k = 0; k < 7; ++k) {
-                    r += Z[k] * coef(9 + k, 0);
-                    gg += Z[k] * coef(9 + k, 1);
-                    b += Z[k] * coef(9 + k, 2);
+                    r += Z[k] * c[9 + k][0];
+                    gg += Z[k] * c[9 + k][1];
+                    b += Z[k] * c[9 + k][2];
                 }
             }
         }
     }
-    c.x = fmaxf(r + 0.5f, 0.0f);
-    c.y = fmaxf(gg + 0.5f, 0.0f);
-    c.z = fmaxf(b + 0.5f, 0.0f);
-    return c;
+    float3 out;
+    out.x = fmaxf(r + 0.5f, 0.0f);
+    out.y = fmaxf(gg + 0.5f, 0.0f);
+    out.z = fmaxf(b + 0.5f, 0.0f);
+    return out;
 }
 
 __global__ __launch_bounds__(256) void k_preprocess(int n, int sh_degree, const float *__restrict__ means,
@@ -157,6 +153,15 @@ __global__ __launch_bounds__(256) void k_preprocess(int n, int sh_degree, const 
         const float py = ((V[4] * mx + V[5] * my) + V[6] * mz) + V[7];
         const float pz = ((V[8] * mx + V[9] * my) + V[10] * mz) + V[11];
         if (finite && pz > cam.near_plane) {
+            // SH coefficients, loaded before the projection so that their
+            // latency overlaps it
+            const int ncoef = (sh_degree + 1) * (sh_degree + 1);
+            float coef[16][3];
+#pragma unroll
+            for (int k = 0; k < 16; ++k)
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch)
+                    coef[k][ch] = k < ncoef ? sh[((size_t)k * 3 + ch) * n + g] : 0.0f;
             // Eq. 2: Sigma = R S S^T R^T
             const float xx = qx * qx, yy = qy * qy, zz = qz * qz;
             const float xy = qx * qy, xz = qx * qz, yz = qy * qz;
@@ -222,7 +227,7 @@ __global__ __launch_bounds__(256) void k_preprocess(int n, int sh_degree, const 
                         float dx = mx - cam.campos[0], dy = my - cam.campos[1], dz = mz - cam.campos[2];
                         const float il = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
                         dx *= il; dy *= il; dz *= il;
-                        const float3 col = sh_colour(sh_degree, sh, n, g, dx, dy, dz);
+                        const float3 col = sh_colour(sh_degree, coef, dx, dy, dz);
                         A = make_float4(u, v, -0.5f * cA, -0.5f * cC);
                         B = make_float4(-cB, opac[g], col.x, col.y);
                         Cb = col.z;
@@ -264,7 +269,10 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_pass(
     const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
     uint32_t *__restrict__ vout, const uint32_t *__restrict__ d_count, uint32_t count_max, int shift, int bits,
     const uint32_t *__restrict__ ghist, uint32_t *__restrict__ lookback, uint32_t *__restrict__ ticket,
-    uint32_t *__restrict__ err) {
+    uint32_t *__restrict__ err, const uint32_t *__restrict__ skip) {
+    // an overflowed frame is invalid: its instance sort is skipped (every
+    // later read stays in bounds)
+    if (skip && *skip) return;
     __shared__ uint32_t s_wcnt[4][256];
     __shared__ uint32_t s_base[256];
     __shared__ uint32_t s_g[256];
@@ -302,13 +310,27 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_pass(
     uint32_t keys[ITEMS], vals[ITEMS], rank[ITEMS];
     const uint32_t base_idx = tile * TILE + wave * (ITEMS * 64);
     const uint64_t lt = lanemask_lt64();
+    // issue every load of the tile before ranking (independent of each other)
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) {
+        const uint32_t idx = base_idx + r * 64 + lane;
+        keys[r] = idx < count ? kin[idx] : 0u;
+    }
+    if (vin) {
+#pragma unroll
+        for (int r = 0; r < ITEMS; ++r) {
+            const uint32_t idx = base_idx + r * 64 + lane;
+            vals[r] = idx < count ? vin[idx] : 0u;
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < ITEMS; ++r) vals[r] = base_idx + r * 64 + lane;
+    }
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
         const uint32_t idx = base_idx + r * 64 + lane;
         const bool valid = idx < count;
-        const uint32_t k = valid ? kin[idx] : 0u;
-        keys[r] = k;
-        vals[r] = valid ? (vin ? vin[idx] : idx) : 0u;
+        const uint32_t k = keys[r];
         const uint32_t d = (k >> shift) & mask;
         uint64_t peers = __ballot(valid);
         for (int b = 0; b < bits; ++b) {
@@ -340,40 +362,53 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_pass(
                          ((tile == 0 ? kFlagInclusive : kFlagAggregate) << kFlagShift) | total);
     }
     __syncthreads();
-    // Windowed look-back: LB = 256 / NB consecutive threads per digit read LB
-    // predecessors at once; the nearest inclusive prefix ends the walk.
+    // Windowed look-back: LB = 256 / NB consecutive threads per digit; thread
+    // k of a digit reads predecessors at distances k, k + LB, k + 2 LB, k + 3 LB
+    // (four independent loads), so a step covers 4 LB predecessors; the
+    // nearest inclusive prefix ends the walk.
     {
         const int LB = min(kSortThreads / NB, 64);   // a group never spans two waves
+        constexpr int M = 4;
         const int d = tid / LB, k = tid % LB;
         uint32_t excl = 0;
         if (tile > 0 && d < NB) {
             int j = (int)tile - 1;
             while (true) {
-                const int jj = j - k;
-                uint32_t st = (kFlagInclusive << kFlagShift);   // before tile 0: inclusive zero
-                if (jj >= 0) {
-                    const uint32_t *p = lookback + (size_t)jj * NB + d;
-                    st = atomic_load_u32(p);
+                uint32_t stv[M];
+#pragma unroll
+                for (int m = 0; m < M; ++m) {
+                    const int jj = j - k - LB * m;
+                    stv[m] = (kFlagInclusive << kFlagShift);   // before tile 0: inclusive zero
+                    if (jj >= 0) stv[m] = atomic_load_u32(lookback + (size_t)jj * NB + d);
+                }
+#pragma unroll
+                for (int m = 0; m < M; ++m) {
+                    const int jj = j - k - LB * m;
                     uint32_t spins = 0;
-                    while ((st >> kFlagShift) == 0u && spins < kSpinLimit) {
+                    while ((stv[m] >> kFlagShift) == 0u && spins < kSpinLimit) {
                         __builtin_amdgcn_s_sleep(1);
-                        st = atomic_load_u32(p);
+                        stv[m] = atomic_load_u32(lookback + (size_t)jj * NB + d);
                         ++spins;
                     }
-                    if ((st >> kFlagShift) == 0u) {
+                    if ((stv[m] >> kFlagShift) == 0u) {
                         atomicOr(err, 1u);
-                        st = (kFlagInclusive << kFlagShift);
+                        stv[m] = (kFlagInclusive << kFlagShift);
                     }
                 }
-                const bool inc = (st >> kFlagShift) == kFlagInclusive;
-                const uint64_t bal = __ballot(inc);
-                const uint32_t grp = (uint32_t)(bal >> (lane - k)) & ((1u << LB) - 1u);
-                const int kfirst = grp ? __builtin_ctz(grp) : LB;
-                uint32_t v = (k <= kfirst) ? (st & kValueMask) : 0u;
+                // nearest inclusive entry of this thread, then of the group
+                int near = 1 << 30;
+#pragma unroll
+                for (int m = M - 1; m >= 0; --m)
+                    if ((stv[m] >> kFlagShift) == kFlagInclusive) near = k + LB * m;
+                for (int o = 1; o < LB; o <<= 1) near = min(near, __shfl_xor(near, o, 64));
+                uint32_t v = 0;
+#pragma unroll
+                for (int m = 0; m < M; ++m)
+                    if (k + LB * m <= near) v += stv[m] & kValueMask;
                 for (int o = 1; o < LB; o <<= 1) v += __shfl_xor(v, o, 64);
                 excl += v;
-                if (grp) break;
-                j -= LB;
+                if (near < (1 << 30)) break;
+                j -= LB * M;
             }
         }
         if (tile > 0 && d < NB && k == 0)
@@ -410,6 +445,8 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_pass(
             s_base[tid] += go + gi - g;          // where digit tid starts in the output, for this tile
             s_tot[tid] = to + ti - t;            // where digit tid starts inside this tile
         }
+        // the digit counts must account for every key exactly
+        if (tid == NB - 1 && tile == 0 && go + gi != count) atomicOr(err, 8u);
     }
     __syncthreads();
     // Reorder the tile by digit in LDS, then write runs of equal digits with
@@ -466,15 +503,17 @@ __global__ __launch_bounds__(256) void k_scan_offsets(int n, const uint32_t *__r
     const uint32_t ntiles = ((uint32_t)n + kScanTile - 1) / kScanTile;
     if (tile >= ntiles) return;
     const uint32_t base = tile * kScanTile + tid * 16;
-    uint32_t v[16];
+    uint32_t v[16], gs[16];
     unsigned long long sum = 0;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
         const uint32_t i = base + r;
-        const uint32_t g = i < (uint32_t)n ? order[i] : 0xffffffffu;
-        v[r] = g < (uint32_t)n ? touched[g] : 0u;
-        sum += v[r];
+        gs[r] = i < (uint32_t)n ? order[i] : 0xffffffffu;
     }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = gs[r] < (uint32_t)n ? touched[gs[r]] : 0u;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) sum += v[r];
     // wave inclusive scan of per-thread sums
     unsigned long long x = sum;
 #pragma unroll
@@ -536,137 +575,289 @@ __global__ __launch_bounds__(256) void k_scan_offsets(int n, const uint32_t *__r
 
 // ---------------------------------------------------------------- k_emit
 //
-// Wave-cooperative fan-out: the 64 Gaussians of a wave (consecutive in depth
-// order, so their instance blocks are contiguous) write their instances in
-// chunks of 64 consecutive slots; each lane finds the Gaussian owning its
-// slot by a binary search over the wave's exclusive counts.  Stores are
-// coalesced.  The tile-digit histograms of the following sort passes are
-// counted per tile row of each Gaussian (a row is a run of consecutive tile
-// ids): the high digit takes one LDS add per distinct value, the low digit a
-// range update on a difference array; instances past the capacity are left
-// out, as the sort leaves them out.
+// Load-balanced fan-out: wave w writes instance slots [1024 w, 1024 (w+1)),
+// whatever Gaussians they belong to.  It finds the Gaussian (in depth order)
+// owning its first slot with a 64-way cooperative search over the offsets,
+// then walks batches of 64 consecutive Gaussians; within a batch each lane
+// finds the owner of its slot by a binary search over the batch's offsets
+// (shuffles).  Stores are coalesced.  (Nearby Gaussians, first in depth
+// order, cover thousands of tiles, so balancing by Gaussian would not do.)
 
-__device__ __forceinline__ void range_add_mod(int *diff, int *whole, uint32_t a, uint32_t len, uint32_t M) {
-    // add 1 to bins a, a+1, ..., a+len-1 (mod M) using a difference array
-    const uint32_t full = len / M, rem = len % M;
-    if (full) atomicAdd(whole, (int)full);
-    if (!rem) return;
-    const uint32_t st = a % M;
-    if (st + rem <= M) {
-        atomicAdd(&diff[st], 1);
-        atomicAdd(&diff[st + rem], -1);
-    } else {
-        atomicAdd(&diff[st], 1);
-        atomicAdd(&diff[M], -1);
-        atomicAdd(&diff[0], 1);
-        atomicAdd(&diff[st + rem - M], -1);
+constexpr int kEmitSlots = 1024;   // instance slots per wave
+
+// The work of one wave: slots [1024 w, 1024 (w+1)) below K, counting the
+// low tile digit of each instance (consecutive slots of a Gaussian are
+// consecutive tiles of a row, so the lanes hit different LDS words).
+__device__ __forceinline__ void emit_wave(int n, const uint32_t *__restrict__ order,
+                                          const unsigned long long *__restrict__ offsets,
+                                          const uint2 *__restrict__ rect, int tiles_x,
+                                          const DevStatus *__restrict__ st, uint32_t *__restrict__ tkeys,
+                                          uint32_t *__restrict__ tvals, int bits0, uint32_t *h0) {
+    const int lane = threadIdx.x & 63;
+    const unsigned long long K = st->k_used;
+    const unsigned long long s0 = ((unsigned long long)blockIdx.x * 4 + (threadIdx.x >> 6)) * kEmitSlots;
+    if (s0 >= K || n <= 0) return;   // wave-uniform
+    const unsigned long long s1 = min(s0 + (unsigned long long)kEmitSlots, K);
+    // last Gaussian i with offsets[i] <= s0 (offsets[0] == 0)
+    int lo = 0, hi = n;
+    while (hi - lo > 64) {
+        const int step = (hi - lo + 63) / 64;
+        const int p = lo + lane * step;
+        const bool ok = p < hi && offsets[p] <= s0;
+        const int c = (int)__popcll(__ballot(ok));   // lanes 0..c-1 (lane 0 always)
+        lo = lo + (c - 1) * step;
+        hi = min(hi, lo + step);
+    }
+    {
+        const bool ok = lo + lane < hi && offsets[lo + lane] <= s0;
+        lo = lo + (int)__popcll(__ballot(ok)) - 1;
+    }
+    unsigned long long cur = s0;
+    for (int ib = lo; cur < s1 && ib < n; ib += 64) {
+        const int i = ib + lane;
+        uint32_t g = 0xffffffffu;
+        int x0 = 0, y0 = 0, w = 1, rel = 0x7fffffff;
+        if (i < n) {
+            g = order[i];
+            if (g < (uint32_t)n) {
+                const uint2 rc = rect[g];
+                x0 = rc.x & 0xffff;
+                y0 = rc.x >> 16;
+                w = max((int)(rc.y & 0xffff) - x0, 1);
+            }
+            rel = (int)((long long)offsets[i] - (long long)s0);   // |rel| < 2^30
+        }
+        // the batch covers slots up to the next batch's first offset
+        const int next = ib + 64 < n ? (int)((long long)offsets[ib + 64] - (long long)s0) : (int)(K - s0);
+        const unsigned long long bend = min(s1, s0 + (unsigned long long)max(next, 0));
+        for (unsigned long long c0 = cur; c0 < bend; c0 += 64) {
+            const int j = (int)(c0 - s0) + lane;
+            int ow = 0;
+#pragma unroll
+            for (int step = 32; step >= 1; step >>= 1) {
+                const int cand = ow + step;
+                const int e = __shfl(rel, cand < 64 ? cand : 63, 64);
+                if (cand < 64 && e <= j) ow = cand;
+            }
+            const int r = j - __shfl(rel, ow, 64);
+            const int ww = __shfl(w, ow, 64);
+            const int ox = __shfl(x0, ow, 64);
+            const int oy = __shfl(y0, ow, 64);
+            const uint32_t og = __shfl(g, ow, 64);
+            const unsigned long long o = s0 + (unsigned long long)j;
+            const bool live = o < bend;
+            uint32_t t = 0xffffffffu;
+            if (live) {
+                const int ry = r / ww;
+                t = (uint32_t)((oy + ry) * tiles_x + ox + (r - ry * ww));
+                tkeys[o] = t;
+                tvals[o] = og;
+                atomicAdd(&h0[t & ((1u << bits0) - 1u)], 1u);
+            }
+        }
+        cur = bend;
     }
 }
 
+static_assert(4 * kEmitSlots == kSortTile, "an emit block must cover exactly one sort tile");
+
 __global__ __launch_bounds__(256) void k_emit(int n, const uint32_t *__restrict__ order,
                                               const unsigned long long *__restrict__ offsets,
-                                              const uint2 *__restrict__ rect, int tiles_x, uint32_t capacity,
-                                              uint32_t *__restrict__ tkeys, uint32_t *__restrict__ tvals,
-                                              int passes, int shift0, int bits0, int shift1, int bits1,
-                                              uint32_t *__restrict__ tile_hist) {
-    __shared__ int s_diff[257];
-    __shared__ int s_whole;
-    __shared__ uint32_t s_h1[256];
-    for (int q = threadIdx.x; q < 257; q += blockDim.x) s_diff[q] = 0;
-    for (int q = threadIdx.x; q < 256; q += blockDim.x) s_h1[q] = 0;
-    if (threadIdx.x == 0) s_whole = 0;
+                                              const uint2 *__restrict__ rect, int tiles_x,
+                                              const DevStatus *__restrict__ st, uint32_t *__restrict__ tkeys,
+                                              uint32_t *__restrict__ tvals, int bits0,
+                                              uint32_t *__restrict__ cnt, int cnt_stride) {
+    __shared__ uint32_t h0[256];
+    for (int q = threadIdx.x; q < 256; q += blockDim.x) h0[q] = 0;
     __syncthreads();
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int lane = threadIdx.x & 63;
-    const uint32_t g = i < n ? order[i] : 0xffffffffu;
-    int x0 = 0, y0 = 0, w = 1, cnt = 0;
-    unsigned long long base = 0;
-    if (g < (uint32_t)n) {
-        const uint2 rc = rect[g];
-        x0 = rc.x & 0xffff;
-        y0 = rc.x >> 16;
-        w = (int)(rc.y & 0xffff) - x0;
-        cnt = w * ((int)(rc.y >> 16) - y0);
-        if (cnt <= 0) { cnt = 0; w = 1; }
-        base = offsets[i];
+    emit_wave(n, order, offsets, rect, tiles_x, st, tkeys, tvals, bits0, h0);
+    __syncthreads();
+    // this block's digit counts for the first instance-sort pass (its slots
+    // are exactly sort tile blockIdx.x)
+    for (int q = threadIdx.x; q < (1 << bits0); q += blockDim.x) cnt[(size_t)q * cnt_stride + blockIdx.x] = h0[q];
+}
+
+// ---------------------------------------------------------------- instance sort
+//
+// Reduce-then-scan LSD passes over the K instances by tile digit: per-tile
+// digit counts (the first pass's from k_emit, later ones from k_sort_up), a
+// per-digit exclusive scan over the tiles (k_spine), then k_sort_down ranks
+// each tile stably and scatters it.  No block waits on another.
+
+// counts of `bits`-wide digits at `shift` in sort tile blockIdx.x
+__global__ __launch_bounds__(kSortThreads) void k_sort_up(const uint32_t *__restrict__ kin,
+                                                          const DevStatus *__restrict__ st, uint32_t cap,
+                                                          int shift, int bits, uint32_t *__restrict__ cnt,
+                                                          int cnt_stride) {
+    if (st->overflow) return;
+    __shared__ uint32_t h[256];
+    const int NB = 1 << bits;
+    const uint32_t count = min(st->k_used, cap);
+    const uint32_t tile = blockIdx.x;
+    if (tile * (uint32_t)kSortTile >= count) return;
+    for (int q = threadIdx.x; q < NB; q += blockDim.x) h[q] = 0;
+    __syncthreads();
+    uint32_t k[kSortItems];
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        const uint32_t idx = tile * kSortTile + r * kSortThreads + threadIdx.x;
+        k[r] = idx < count ? kin[idx] : 0xffffffffu;
     }
-    // ---- digit histograms of this lane's instances (those below capacity)
-    {
-        const uint32_t M0 = 1u << bits0;
-        long long keep = base < capacity ? (long long)min<unsigned long long>((unsigned long long)cnt, capacity - base) : 0;
-        for (int ty = y0; keep > 0; ++ty) {
-            const uint32_t seg = (uint32_t)min<long long>(w, keep);
-            keep -= seg;
-            const uint32_t r0 = (uint32_t)(ty * tiles_x + x0), r1 = r0 + seg;   // tiles [r0, r1)
-            range_add_mod(s_diff, &s_whole, r0 >> shift0, seg, M0);               // shift0 is 0
-            if (passes > 1) {
-                for (uint32_t v = r0 >> shift1; v <= (r1 - 1) >> shift1; ++v) {
-                    const uint32_t lo = max(r0, v << shift1), hi = min(r1, (v + 1) << shift1);
-                    atomicAdd(&s_h1[v & ((1u << bits1) - 1u)], hi - lo);
-                }
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r)
+        if (k[r] != 0xffffffffu) atomicAdd(&h[(k[r] >> shift) & (uint32_t)(NB - 1)], 1u);
+    __syncthreads();
+    for (int q = threadIdx.x; q < NB; q += blockDim.x) cnt[(size_t)q * cnt_stride + tile] = h[q];
+}
+
+// per digit (one wave each): exclusive scan of its counts over the live
+// tiles, in place, and the digit's total
+__global__ __launch_bounds__(256) void k_spine(uint32_t *__restrict__ cnt, int cnt_stride, int NB,
+                                               const DevStatus *__restrict__ st, uint32_t cap,
+                                               uint32_t *__restrict__ dtot) {
+    if (st->overflow) return;
+    const int lane = threadIdx.x & 63;
+    const int d = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (d >= NB) return;   // wave-uniform
+    const uint32_t count = min(st->k_used, cap);
+    const int nlive = (int)((count + kSortTile - 1) / kSortTile);
+    uint32_t *row = cnt + (size_t)d * cnt_stride;
+    uint32_t carry = 0;
+    constexpr int R = 16;   // 1024 tiles per segment, all loads in flight
+    for (int s0 = 0; s0 < nlive; s0 += 64 * R) {
+        uint32_t v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int idx = s0 + r * 64 + lane;
+            v[r] = idx < nlive ? row[idx] : 0u;
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            uint32_t x = v[r];
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t y = __shfl_up(x, o, 64);
+                if (lane >= o) x += y;
             }
+            const int idx = s0 + r * 64 + lane;
+            if (idx < nlive) row[idx] = carry + x - v[r];
+            carry += __shfl(x, 63, 64);
         }
     }
-    // ---- coalesced fan-out
-    int incl = cnt;
+    if (lane == 0) dtot[d] = carry;
+}
+
+template <int ITEMS>
+__global__ __launch_bounds__(kSortThreads) void k_sort_down(
+    const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
+    uint32_t *__restrict__ vout, const DevStatus *__restrict__ st, uint32_t cap, int shift, int bits,
+    const uint32_t *__restrict__ cnt, int cnt_stride, const uint32_t *__restrict__ dtot,
+    uint32_t *__restrict__ err) {
+    if (st->overflow) return;   // an overflowed frame is invalid; reads below stay in bounds
+    constexpr uint32_t TILE = kSortThreads * ITEMS;
+    __shared__ uint32_t s_wcnt[4][256];
+    __shared__ uint32_t s_base[256];
+    __shared__ uint32_t s_tot[256];
+    __shared__ uint32_t s_wg[4], s_wt[4];
+    __shared__ uint32_t s_k[TILE], s_v[TILE];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int NB = 1 << bits;
+    const uint32_t mask = (uint32_t)NB - 1u;
+    const uint32_t count = min(st->k_used, cap);
+    const uint32_t tile = blockIdx.x;
+    if (tile * TILE >= count) return;
+    for (int i = tid; i < 4 * 256; i += kSortThreads) (&s_wcnt[0][0])[i] = 0;
+    __syncthreads();
+    uint32_t keys[ITEMS], vals[ITEMS], rank[ITEMS];
+    const uint32_t base_idx = tile * TILE + wave * (ITEMS * 64);
+    const uint64_t lt = lanemask_lt64();
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) {
+        const uint32_t idx = base_idx + r * 64 + lane;
+        keys[r] = idx < count ? kin[idx] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) {
+        const uint32_t idx = base_idx + r * 64 + lane;
+        vals[r] = idx < count ? vin[idx] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) {
+        const uint32_t idx = base_idx + r * 64 + lane;
+        const bool valid = idx < count;
+        const uint32_t d = (keys[r] >> shift) & mask;
+        uint64_t peers = __ballot(valid);
+        for (int b = 0; b < bits; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bb = __ballot(bit);
+            peers &= bit ? bb : ~bb;
+        }
+        uint32_t old = 0;
+        if (valid) old = s_wcnt[wave][d];
+        if (valid && (peers & lt) == 0) s_wcnt[wave][d] = old + (uint32_t)__popcll(peers);
+        rank[r] = old + (uint32_t)__popcll(peers & lt);
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    // per digit: wave prefixes and tile total; then the block scans of the
+    // digit totals (global) and of this tile's totals
+    uint32_t g = 0, t = 0;
+    if (tid < NB) {
+        const uint32_t t0 = s_wcnt[0][tid], t1 = s_wcnt[1][tid], t2 = s_wcnt[2][tid], t3 = s_wcnt[3][tid];
+        t = t0 + t1 + t2 + t3;
+        s_wcnt[0][tid] = 0;
+        s_wcnt[1][tid] = t0;
+        s_wcnt[2][tid] = t0 + t1;
+        s_wcnt[3][tid] = t0 + t1 + t2;
+        g = dtot[tid];
+    }
+    uint32_t gi = g, ti = t;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
-        const int y = __shfl_up(incl, o, 64);
-        if (lane >= o) incl += y;
-    }
-    const int excl = incl - cnt;
-    const int total = __shfl(incl, 63, 64);
-    // slot 0 of the wave: the first lane's offset minus its exclusive count (0)
-    const unsigned long long wbase = __shfl(base, 0, 64) - (unsigned long long)__shfl(excl, 0, 64);
-    for (int jb = 0; jb < total; jb += 64) {
-        const int j = jb + lane;
-        // owner: the largest lane l with excl_l <= j (it has cnt_l > 0 when j < total)
-        int lo = 0;
-#pragma unroll
-        for (int step = 32; step >= 1; step >>= 1) {
-            const int cand = lo + step;
-            const int e = __shfl(excl, cand < 64 ? cand : 63, 64);
-            if (cand < 64 && e <= j) lo = cand;
+        const uint32_t gy = __shfl_up(gi, o, 64), ty = __shfl_up(ti, o, 64);
+        if (lane >= o) {
+            gi += gy;
+            ti += ty;
         }
-        const int r = j - __shfl(excl, lo, 64);
-        const int ow = __shfl(w, lo, 64);
-        const int ox = __shfl(x0, lo, 64);
-        const int oy = __shfl(y0, lo, 64);
-        const uint32_t og = __shfl(g, lo, 64);
-        const unsigned long long o = wbase + (unsigned long long)j;
-        if (j < total && o < capacity) {
-            const int ry = r / ow;
-            tkeys[o] = (uint32_t)((oy + ry) * tiles_x + ox + (r - ry * ow));
-            tvals[o] = og;
+    }
+    if (lane == 63) {
+        s_wg[wave] = gi;
+        s_wt[wave] = ti;
+    }
+    __syncthreads();
+    uint32_t go = 0, to = 0;
+    for (int w = 0; w < wave; ++w) {
+        go += s_wg[w];
+        to += s_wt[w];
+    }
+    if (tid < NB) {
+        s_base[tid] = go + gi - g + cnt[(size_t)tid * cnt_stride + tile];   // output start of (digit, tile)
+        s_tot[tid] = to + ti - t;                                           // start inside the tile
+    }
+    if (tid == NB - 1 && tile == 0 && go + gi != count) atomicOr(err, 8u);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) {
+        const uint32_t idx = base_idx + r * 64 + lane;
+        if (idx < count) {
+            const uint32_t d = (keys[r] >> shift) & mask;
+            const uint32_t lpos = s_tot[d] + s_wcnt[wave][d] + rank[r];
+            s_k[lpos] = keys[r];
+            s_v[lpos] = vals[r];
         }
     }
     __syncthreads();
-    // ---- flush: prefix of the difference array gives the low-digit counts
-    if (threadIdx.x < 64) {
-        const uint32_t M0 = 1u << bits0;
-        // M0 <= 256 bins, 4 per lane, serial within the lane then a wave scan
-        int v[4];
-        int acc = 0;
-        for (int q = 0; q < 4; ++q) {
-            const uint32_t bin = threadIdx.x * 4 + q;
-            acc += bin < M0 ? s_diff[bin] : 0;
-            v[q] = acc;
+    const uint32_t in_tile = min(TILE, count - tile * TILE);
+    for (uint32_t li = tid; li < in_tile; li += kSortThreads) {
+        const uint32_t k = s_k[li];
+        const uint32_t d = (k >> shift) & mask;
+        const uint32_t pos = s_base[d] + (li - s_tot[d]);
+        if (pos < count) {
+            kout[pos] = k;
+            vout[pos] = s_v[li];
+        } else {
+            atomicOr(err, 4u);   // inconsistent counts: never write out of bounds
         }
-        int x = acc;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const int y = __shfl_up(x, o, 64);
-            if (lane >= o) x += y;
-        }
-        const int off = x - acc + s_whole;
-        for (int q = 0; q < 4; ++q) {
-            const uint32_t bin = threadIdx.x * 4 + q;
-            if (bin < M0 && v[q] + off) atomicAdd(&tile_hist[bin], (uint32_t)(v[q] + off));
-        }
-    }
-    if (passes > 1) {
-        for (int q = threadIdx.x; q < (1 << bits1); q += blockDim.x)
-            if (s_h1[q]) atomicAdd(&tile_hist[256 + q], s_h1[q]);
     }
 }
 
@@ -695,9 +886,10 @@ __global__ __launch_bounds__(256) void k_ranges(const DevStatus *__restrict__ st
 // threshold in a quadrant is skipped by every pixel of it anyway, so leaving
 // it out of that quadrant's list changes no result; the cut keeps a margin
 // covering the binary32 rounding of both the cut and the per-pixel value.
-// Each quadrant's list (list order kept, list positions stored) is compacted
-// into LDS; the wave then composites it with a branch-free body and leaves
-// once all its pixels are done.
+// The batch is staged once in LDS and each quadrant gets a list of the
+// staged slots it keeps (list order kept, list positions stored); the wave
+// then composites its list with a branch-free body and leaves once all its
+// pixels are done.
 
 __device__ __forceinline__ float quad_form(float A, float B, float C, float dx, float dy) {
     return (A * dx) * dx + (2.0f * B * dx) * dy + (C * dy) * dy;
@@ -729,9 +921,10 @@ __global__ __launch_bounds__(kTilePixels) void k_blend(const uint2 *__restrict__
                                                        int tiles_x, int n_tiles, const CamK *__restrict__ camd,
                                                        DevStatus *__restrict__ st, int passes, int n) {
     constexpr int NW = kTilePixels / 64;                   // waves = quadrants
-    __shared__ float4 sA[NW][kTilePixels];
-    __shared__ float4 sB[NW][kTilePixels];
-    __shared__ float2 sCI[NW][kTilePixels];                // (blue, list position as bits)
+    __shared__ float4 sA[kTilePixels];                     // staged batch
+    __shared__ float4 sB[kTilePixels];
+    __shared__ float2 sCI[kTilePixels];                    // (blue, list position as bits)
+    __shared__ uint8_t sL[NW][kTilePixels];                // per-quadrant lists of staged slots
     __shared__ int s_cnt[NW][NW];                          // [staging wave][quadrant]
     // The grid is 8 * ceil(n_tiles / 8) blocks; block b runs on XCD b % 8, and
     // each XCD gets a contiguous band of tiles (neighbours share Gaussians).
@@ -790,6 +983,11 @@ __global__ __launch_bounds__(kTilePixels) void k_blend(const uint2 *__restrict__
 #pragma unroll
             for (int q = 0; q < NW; ++q) s_cnt[wave][q] = (int)__popcll(bal[q]);
         }
+        if (qmask) {
+            sA[tid] = A4;
+            sB[tid] = B4;
+            sCI[tid] = make_float2(C1, __int_as_float(i - start));
+        }
         __syncthreads();
         int kept = 0;      // entries in this wave's own quadrant list
 #pragma unroll
@@ -801,23 +999,17 @@ __global__ __launch_bounds__(kTilePixels) void k_blend(const uint2 *__restrict__
                 if (w < wave) base += c;
                 if (q == wave) kept += c;
             }
-            if ((qmask >> q) & 1u) {
-                const int pos = base + (int)__popcll(bal[q] & lt);
-                sA[q][pos] = A4;
-                sB[q][pos] = B4;
-                sCI[q][pos] = make_float2(C1, __int_as_float(i - start));
-            }
+            if ((qmask >> q) & 1u) sL[q][base + (int)__popcll(bal[q] & lt)] = (uint8_t)tid;
         }
         __syncthreads();
         // ---- composite this wave's list (branch-free body)
         if (!__all(done)) {
-            const float4 *__restrict__ LA = sA[wave];
-            const float4 *__restrict__ LB = sB[wave];
-            const float2 *__restrict__ LC = sCI[wave];
+            const uint8_t *__restrict__ LL = sL[wave];
             for (int j = 0; j < kept; ++j) {
-                const float4 A = LA[j];
-                const float4 B = LB[j];
-                const float2 CI = LC[j];
+                const int e = LL[j];
+                const float4 A = sA[e];
+                const float4 B = sB[e];
+                const float2 CI = sCI[e];
                 const float dx = A.x - fpx, dy = A.y - fpy;
                 const float power = ((A.z * dx) * dx + (A.w * dy) * dy) + (B.x * dx) * dy;
                 const float alpha = fminf(0.99f, B.y * __expf(power));
@@ -956,9 +1148,7 @@ g4d_status render(const g4d_splats *G, const g4d_camera *C, const g4d_workspace 
     DevStatus *st = at<DevStatus>(ws, L.status);
     CamK *camd = at<CamK>(ws, L.cam);
     uint32_t *depth_hist = at<uint32_t>(ws, L.depth_hist);
-    uint32_t *tile_hist = at<uint32_t>(ws, L.tile_hist);
     uint32_t *lb_depth = at<uint32_t>(ws, L.lb_depth);
-    uint32_t *lb_tile = at<uint32_t>(ws, L.lb_tile);
     unsigned long long *lb_scan = at<unsigned long long>(ws, L.lb_scan);
     uint2 *ranges = at<uint2>(ws, L.ranges);
     float4 *recA = at<float4>(ws, L.recA);
@@ -1001,7 +1191,8 @@ g4d_status render(const g4d_splats *G, const g4d_camera *C, const g4d_workspace 
             hipLaunchKernelGGL(k_sort_pass<kSortItemsN>, dim3(sblocks), dim3(kSortThreads), 0, s, kin[p], vin[p],
                                kout[p], vout[p],
                                nullptr, (uint32_t)n, 8 * p, 8, depth_hist + 256 * p,
-                               lb_depth + (size_t)p * L.nblk_n * 256, &st->tile_counter[p], &st->sort_error);
+                               lb_depth + (size_t)p * L.nblk_n * 256, &st->tile_counter[p], &st->sort_error,
+                               nullptr);
         }
         mark(3);
         const uint32_t *order = dv[0];
@@ -1012,18 +1203,26 @@ g4d_status render(const g4d_splats *G, const g4d_camera *C, const g4d_workspace 
         mark(4);
         // 4. emit instances (first tile-sort buffer chosen so the result lands in tk0/tv0)
         const int e = plan.passes == 1 ? 1 : 0;
-        hipLaunchKernelGGL(k_emit, dim3(nb_n), dim3(256), 0, s, n, order, offsets, rect, cam.tiles_x, cap, tk[e],
-                           tv[e], plan.passes, plan.shift[0], plan.bits[0], plan.shift[1],
-                           plan.passes > 1 ? plan.bits[1] : 1, tile_hist);
+        uint32_t *tcnt = at<uint32_t>(ws, L.tcnt);
+        uint32_t *tdtot = at<uint32_t>(ws, L.tdtot);
+        const int cstride = L.nblk_k;
+        const int kblocks = L.nblk_k;
+        hipLaunchKernelGGL(k_emit, dim3(kblocks), dim3(256), 0, s, n, order, offsets, rect, cam.tiles_x, st, tk[e],
+                           tv[e], plan.bits[0], tcnt, cstride);
         mark(5);
-        // 5. tile sort over K instances (device count), grid sized by capacity
-        const int kblocks = (int)((L.cap + kSortTile - 1) / kSortTile);
+        // 5. instance sort by tile digits (reduce-then-scan passes)
         int cur = e;
         for (int p = 0; p < plan.passes; ++p) {
-            hipLaunchKernelGGL(k_sort_pass<kSortItems>, dim3(kblocks), dim3(kSortThreads), 0, s, tk[cur], tv[cur],
-                               tk[cur ^ 1],
-                               tv[cur ^ 1], &st->k_used, cap, plan.shift[p], plan.bits[p], tile_hist + 256 * p,
-                               lb_tile + (size_t)p * L.nblk_k * 256, &st->tile_counter[5 + p], &st->sort_error);
+            uint32_t *pc = tcnt + (size_t)p * 256 * cstride;
+            uint32_t *pt = tdtot + 256 * p;
+            const int NB = 1 << plan.bits[p];
+            if (p > 0)
+                hipLaunchKernelGGL(k_sort_up, dim3(kblocks), dim3(kSortThreads), 0, s, tk[cur], st, cap,
+                                   plan.shift[p], plan.bits[p], pc, cstride);
+            hipLaunchKernelGGL(k_spine, dim3((NB + 3) / 4), dim3(256), 0, s, pc, cstride, NB, st, cap, pt);
+            hipLaunchKernelGGL(k_sort_down<kSortItems>, dim3(kblocks), dim3(kSortThreads), 0, s, tk[cur], tv[cur],
+                               tk[cur ^ 1], tv[cur ^ 1], st, cap, plan.shift[p], plan.bits[p], pc, cstride, pt,
+                               &st->sort_error);
             cur ^= 1;
         }
         mark(6);
