@@ -515,7 +515,8 @@ void orc_tile_ranges(int64_t k, const uint64_t *keys, int n_tiles, int64_t *rang
 /* Decisions are taken in binary32 (values f32 from orc_project); the   */
 /* colour and T are accumulated in FP64 from the FP64 values.  flag[p]  */
 /* counts binary32 decisions within `margin` (relative) of their        */
-/* threshold; such pixels are excluded from element-wise comparison.    */
+/* threshold (for the sign of power: relative to the magnitude of its   */
+/* terms); such pixels are excluded from element-wise comparison.       */
 /* ------------------------------------------------------------------ */
 void orc_blend(int width, int height, const int64_t *ranges, const uint32_t *vals,
                const float *opacity, const float *f32v /* [n][8] */, const double *f64v /* [n][8] */,
@@ -546,6 +547,10 @@ void orc_blend(int width, int height, const int64_t *ranges, const uint32_t *val
                 float p2 = (v32[7] * dy) * dy;
                 float p3 = (v32[6] * dx) * dy;
                 float power32 = -0.5f * (p1 + p2) - p3;
+                /* the form is positive definite, so power <= 0 exactly; its   */
+                /* sign test only resolves rounding: flag when it is that close */
+                float mag = 0.5f * (fabsf(p1) + fabsf(p2)) + fabsf(p3);
+                if (fabsf(power32) < (float)margin * mag) ++fl;
                 if (power32 > 0.0f) continue;
                 float alpha32 = fminf(0.99f, opacity[g] * expf(power32));
                 if (fabsf(alpha32 - a_min) <= (float)margin * a_min) ++fl;

@@ -921,10 +921,12 @@ __global__ __launch_bounds__(kTilePixels) void k_blend(const uint2 *__restrict__
                                                        int tiles_x, int n_tiles, const CamK *__restrict__ camd,
                                                        DevStatus *__restrict__ st, int passes, int n) {
     constexpr int NW = kTilePixels / 64;                   // waves = quadrants
-    __shared__ float4 sA[kTilePixels];                     // staged batch
-    __shared__ float4 sB[kTilePixels];
-    __shared__ float2 sCI[kTilePixels];                    // (blue, list position as bits)
-    __shared__ uint8_t sL[NW][kTilePixels];                // per-quadrant lists of staged slots
+    // staged batch: per slot three float4 = (u, v, -A/2, -C/2), (-B, log2 o, r, g),
+    // (b, list position + 1 as bits, -, -); 48 bytes, addressed by byte offset
+    // slot kTilePixels is a blank record (log2 o = -inf, so alpha = 0) that pads
+    // each list to a multiple of four entries
+    __shared__ float4 sR[(kTilePixels + 1) * 3];
+    __shared__ __align__(8) uint16_t sL[NW][kTilePixels];  // per-quadrant lists of slot byte offsets
     __shared__ int s_cnt[NW][NW];                          // [staging wave][quadrant]
     // The grid is 8 * ceil(n_tiles / 8) blocks; block b runs on XCD b % 8, and
     // each XCD gets a contiguous band of tiles (neighbours share Gaussians).
@@ -941,6 +943,9 @@ __global__ __launch_bounds__(kTilePixels) void k_blend(const uint2 *__restrict__
     const int qx0 = tx * kTile + (wave & 1) * 8, qy0 = ty * kTile + (wave >> 1) * 8;
     const int px = qx0 + (lane & 7), py = qy0 + (lane >> 3);
     const bool inside = px < width && py < height;
+    const size_t pix = inside ? (size_t)py * width + px : 0;
+    if (tid < 3)
+        sR[3 * kTilePixels + tid] = tid == 1 ? make_float4(0.0f, -INFINITY, 0.0f, 0.0f) : make_float4(0.f, 0.f, 0.f, 0.f);
     const uint2 rg = ranges[tile];
     const int start = (int)rg.x, end = (int)rg.y;
     const float fpx = (float)px, fpy = (float)py;
@@ -950,6 +955,7 @@ __global__ __launch_bounds__(kTilePixels) void k_blend(const uint2 *__restrict__
     int evals = inside ? end - start : 0;   // list entries this pixel evaluates
     const float a_min = 1.0f / 255.0f;
     const uint64_t lt = lanemask_lt64();
+    const char *rbase = reinterpret_cast<const char *>(sR);
     for (int b0 = start; b0 < end; b0 += kTilePixels) {
         if (__syncthreads_count(done) == kTilePixels) break;
         // ---- stage one entry per thread; quadrant masks
@@ -984,9 +990,9 @@ __global__ __launch_bounds__(kTilePixels) void k_blend(const uint2 *__restrict__
             for (int q = 0; q < NW; ++q) s_cnt[wave][q] = (int)__popcll(bal[q]);
         }
         if (qmask) {
-            sA[tid] = A4;
-            sB[tid] = B4;
-            sCI[tid] = make_float2(C1, __int_as_float(i - start));
+            sR[3 * tid] = A4;
+            sR[3 * tid + 1] = make_float4(B4.x, __log2f(B4.y), B4.z, B4.w);
+            sR[3 * tid + 2] = make_float4(C1, __int_as_float(i - start + 1), 0.0f, 0.0f);
         }
         __syncthreads();
         int kept = 0;      // entries in this wave's own quadrant list
@@ -999,34 +1005,45 @@ __global__ __launch_bounds__(kTilePixels) void k_blend(const uint2 *__restrict__
                 if (w < wave) base += c;
                 if (q == wave) kept += c;
             }
-            if ((qmask >> q) & 1u) sL[q][base + (int)__popcll(bal[q] & lt)] = (uint8_t)tid;
+            if ((qmask >> q) & 1u) sL[q][base + (int)__popcll(bal[q] & lt)] = (uint16_t)(tid * 48);
         }
+        kept = __builtin_amdgcn_readfirstlane(kept);
+        const int kept4 = (kept + 3) & ~3;
+        if (lane < kept4 - kept) sL[wave][kept + lane] = (uint16_t)(kTilePixels * 48);
         __syncthreads();
         // ---- composite this wave's list (branch-free body)
         if (!__all(done)) {
-            const uint8_t *__restrict__ LL = sL[wave];
-            for (int j = 0; j < kept; ++j) {
-                const int e = LL[j];
-                const float4 A = sA[e];
-                const float4 B = sB[e];
-                const float2 CI = sCI[e];
-                const float dx = A.x - fpx, dy = A.y - fpy;
-                const float power = ((A.z * dx) * dx + (A.w * dy) * dy) + (B.x * dx) * dy;
-                const float alpha = fminf(0.99f, B.y * __expf(power));
-                const float test = T * (1.0f - alpha);
-                const bool valid = !done && !(power > 0.0f) && !(alpha < a_min);
-                const bool stop = valid && test < 0.0001f;
-                const bool add = valid && !stop;
-                const float w = add ? alpha * T : 0.0f;
-                cr = __builtin_fmaf(B.z, w, cr);
-                cg = __builtin_fmaf(B.w, w, cg);
-                cbl = __builtin_fmaf(CI.x, w, cbl);
-                T = add ? test : T;
-                const int pos1 = __float_as_int(CI.y) + 1;
-                last = add ? pos1 : last;
-                evals = stop ? pos1 : evals;
-                done = done || stop;
-                if (__all(done)) break;
+            const uint16_t *__restrict__ LL = sL[wave];
+            for (int j = 0; j < kept4; j += 4) {
+                const uint2 offs = *reinterpret_cast<const uint2 *>(LL + j);
+                const uint32_t off4[4] = {offs.x & 0xffffu, offs.x >> 16, offs.y & 0xffffu, offs.y >> 16};
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const char *rec = rbase + off4[u];
+                    const float4 R0 = *reinterpret_cast<const float4 *>(rec);
+                    const float4 R1 = *reinterpret_cast<const float4 *>(rec + 16);
+                    const float2 R2 = *reinterpret_cast<const float2 *>(rec + 32);
+                    const float dx = R0.x - fpx, dy = R0.y - fpy;
+                    // -(A dx^2 + C dy^2)/2 - B dx dy in a fixed binary32 sequence
+                    const float power =
+                        __builtin_fmaf(R0.z * dx, dx, __builtin_fmaf(R0.w * dy, dy, (R1.x * dx) * dy));
+                    const float alpha =
+                        fminf(0.99f, __builtin_amdgcn_exp2f(__builtin_fmaf(power, 1.44269504f, R1.y)));
+                    const float test = __builtin_fmaf(-alpha, T, T);   // T (1 - alpha), one rounding
+                    const bool valid = !done & !(power > 0.0f) & !(alpha < a_min);
+                    const bool stop = valid & (test < 0.0001f);
+                    const bool add = valid ^ stop;
+                    const float w = add ? alpha * T : 0.0f;
+                    cr = __builtin_fmaf(R1.z, w, cr);
+                    cg = __builtin_fmaf(R1.w, w, cg);
+                    cbl = __builtin_fmaf(R2.x, w, cbl);
+                    T = add ? test : T;
+                    const int pos1 = __float_as_int(R2.y);
+                    last = add ? pos1 : last;
+                    evals = stop ? pos1 : evals;
+                    done = done | stop;
+                }
+                if (__builtin_amdgcn_ballot_w64(!done) == 0) break;
             }
         }
     }
@@ -1048,7 +1065,6 @@ __global__ __launch_bounds__(kTilePixels) void k_blend(const uint2 *__restrict__
         float *__restrict__ final_T = camd->final_T;
         int32_t *__restrict__ n_contrib = camd->n_contrib;
         const float bg0 = camd->bg[0], bg1 = camd->bg[1], bg2 = camd->bg[2];
-        const size_t pix = (size_t)py * width + px;
         const size_t plane = (size_t)width * height;
         image[pix] = cr + T * bg0;
         image[plane + pix] = cg + T * bg1;
