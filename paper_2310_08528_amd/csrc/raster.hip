@@ -8,8 +8,11 @@
 //   k_sort_pass x4  stable LSD radix sort of (depth bits, index) over Gaussians
 //   k_scan_offsets  exclusive scan of tiles-per-Gaussian in depth order -> K
 //   k_emit        one (tile id, Gaussian) instance per touched tile, in depth order
-//   k_sort_pass x1-2  stable LSD radix sort of the instances by tile id
+//                 (and counts the first tile digit per sort tile)
+//   k_sort_up / k_spine / k_sort_down  x1-2  stable LSD radix sort of the
+//                 instances by tile id (reduce-then-scan passes)
 //   k_ranges      [start, end) of every tile in the sorted list
+//   k_tile_order  blend order of the tiles, longest list first
 //   k_blend       one 256-thread block per 16x16 tile: front-to-back compositing
 //                 (Eq. 1, Eq. 4) over LDS-staged batches with early exit
 //
@@ -866,47 +869,95 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_down(
 __global__ __launch_bounds__(256) void k_ranges(const DevStatus *__restrict__ st, const uint32_t *__restrict__ tkeys,
                                                 uint2 *__restrict__ ranges, uint32_t n_tiles) {
     const uint32_t K = st->k_used;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < K; i += gridDim.x * blockDim.x) {
-        const uint32_t t = tkeys[i];
-        if (t >= n_tiles) continue;   // only possible if the sort failed (flagged there)
-        if (i == 0 || tkeys[i - 1] != t) ranges[t].x = i;
-        if (i == K - 1 || tkeys[i + 1] != t) ranges[t].y = i + 1;
+    const uint32_t nq = (K + 3) / 4;
+    constexpr uint32_t kNone = 0xffffffffu;
+    for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += gridDim.x * blockDim.x) {
+        const uint32_t i0 = 4 * q;
+        uint32_t k[4];
+        if (i0 + 4 <= K) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(tkeys + i0);
+            k[0] = v.x; k[1] = v.y; k[2] = v.z; k[3] = v.w;
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) k[j] = i0 + j < K ? tkeys[i0 + j] : kNone;
+        }
+        const uint32_t prev = i0 > 0 ? tkeys[i0 - 1] : kNone;
+        const uint32_t next = i0 + 4 < K ? tkeys[i0 + 4] : kNone;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t t = k[j];
+            if (i0 + j >= K || t >= n_tiles) continue;   // t >= n_tiles only if the sort failed (flagged there)
+            const uint32_t before = j > 0 ? k[j - 1] : prev;
+            const uint32_t after = j < 3 ? k[j + 1] : next;
+            if (before != t) ranges[t].x = i0 + j;
+            if (after != t) ranges[t].y = i0 + j + 1;
+        }
     }
+}
+
+// ---------------------------------------------------------------- k_tile_order
+//
+// Blend order of the tiles: by list length, longest first, in power-of-two
+// classes (order inside a class is arbitrary; each tile's result does not
+// depend on it).  Blocks are dispatched in index order and spread round-robin
+// over the XCDs, so the longest tiles start first and land on different XCDs.
+
+__global__ __launch_bounds__(1024) void k_tile_order(const uint2 *__restrict__ ranges, int n_tiles,
+                                                     uint32_t *__restrict__ order) {
+    __shared__ uint32_t hist[33];
+    const int tid = threadIdx.x;
+    if (tid < 33) hist[tid] = 0;
+    __syncthreads();
+    auto cls = [](uint2 r) -> int { const uint32_t len = r.y > r.x ? r.y - r.x : 0u; return 32 - __clz(len); };
+    for (int t = tid; t < n_tiles; t += 1024) atomicAdd(&hist[cls(ranges[t])], 1u);
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t pos = 0;
+        for (int c = 32; c >= 0; --c) {
+            const uint32_t h = hist[c];
+            hist[c] = pos;
+            pos += h;
+        }
+    }
+    __syncthreads();
+    for (int t = tid; t < n_tiles; t += 1024) order[atomicAdd(&hist[cls(ranges[t])], 1u)] = (uint32_t)t;
 }
 
 // ---------------------------------------------------------------- k_blend
 //
 // One 256-thread block per 16x16 tile; wave w owns the 8x8 quadrant
-// (w & 1, w >> 1), lane l the pixel (l & 7, l >> 3) inside it.  Per batch of
-// 256 list entries each thread stages one Gaussian and decides, for each of
-// the four quadrants, whether it can reach alpha >= 1/255 at any pixel
-// there: the quadratic form d^T Sigma'^-1 d is convex, so its minimum over
-// the rectangle of pixel centres is 0 if the centre lies inside, else the
-// least of the four clamped edge minima.  An entry that cannot reach the
-// threshold in a quadrant is skipped by every pixel of it anyway, so leaving
-// it out of that quadrant's list changes no result; the cut keeps a margin
-// covering the binary32 rounding of both the cut and the per-pixel value.
-// The batch is staged once in LDS and each quadrant gets a list of the
-// staged slots it keeps (list order kept, list positions stored); the wave
-// then composites its list with a branch-free body and leaves once all its
-// pixels are done.
+// (w & 1, w >> 1), lane l the pixel (l & 7, l >> 3) inside it.  The four
+// waves run independently (no block barrier until the end).  Per step a wave
+// takes the next 64 list entries, one per lane, and decides whether each can
+// reach alpha >= 1/255 at any pixel of its quadrant: the quadratic form
+// d^T Sigma'^-1 d is convex, so its minimum over the rectangle of pixel
+// centres is 0 if the centre lies inside, else the least of the four clamped
+// edge minima.  An entry that cannot reach the threshold in the quadrant is
+// skipped by every pixel of it anyway, so leaving it out changes no result;
+// the cut keeps a margin covering the binary32 rounding of both the cut and
+// the per-pixel value.  The kept entries are packed in list order into the
+// wave's LDS slots (list positions stored) and composited with a branch-free
+// body; the wave leaves once all its pixels are done.
 
 __device__ __forceinline__ float quad_form(float A, float B, float C, float dx, float dy) {
     return (A * dx) * dx + (2.0f * B * dx) * dy + (C * dy) * dy;
 }
 
-// Can a Gaussian (centre u, v; conic A, B, C; cut threshold thr on the
-// quadratic form) reach the threshold inside [x_lo, x_hi] x [y_lo, y_hi]?
-__device__ __forceinline__ bool rect_may_reach(float u, float v, float A, float B, float C, float thr, float x_lo,
-                                               float x_hi, float y_lo, float y_hi) {
+// Can a Gaussian (centre u, v; conic A, B, C with reciprocals iA ~ 1/A,
+// iC ~ 1/C; cut threshold thr on the quadratic form) reach the threshold
+// inside [x_lo, x_hi] x [y_lo, y_hi]?  The edge minimisers are located with
+// hardware reciprocals: a misplaced minimiser only raises the edge value by
+// a second-order amount (C de^2 for an error de), far inside the margin.
+__device__ __forceinline__ bool rect_may_reach(float u, float v, float A, float B, float C, float iA, float iC,
+                                               float thr, float x_lo, float x_hi, float y_lo, float y_hi) {
     if (x_hi < x_lo || y_hi < y_lo) return false;   // quadrant outside the image
     const float dxl = u - x_hi, dxh = u - x_lo;
     const float dyl = v - y_hi, dyh = v - y_lo;
     if (dxl <= 0.0f && dxh >= 0.0f && dyl <= 0.0f && dyh >= 0.0f) return true;
-    const float ea = fminf(fmaxf(-(B * dxl) / C, dyl), dyh);
-    const float eb = fminf(fmaxf(-(B * dxh) / C, dyl), dyh);
-    const float ec = fminf(fmaxf(-(B * dyl) / A, dxl), dxh);
-    const float ed = fminf(fmaxf(-(B * dyh) / A, dxl), dxh);
+    const float ea = fminf(fmaxf(-(B * dxl) * iC, dyl), dyh);
+    const float eb = fminf(fmaxf(-(B * dxh) * iC, dyl), dyh);
+    const float ec = fminf(fmaxf(-(B * dyl) * iA, dxl), dxh);
+    const float ed = fminf(fmaxf(-(B * dyh) * iA, dxl), dxh);
     const float qmin = fminf(fminf(quad_form(A, B, C, dxl, ea), quad_form(A, B, C, dxh, eb)),
                              fminf(quad_form(A, B, C, ec, dyl), quad_form(A, B, C, ed, dyh)));
     const float d2 = fmaxf(dxl * dxl, dxh * dxh) + fmaxf(dyl * dyl, dyh * dyh);
@@ -914,29 +965,24 @@ __device__ __forceinline__ bool rect_may_reach(float u, float v, float A, float 
 }
 
 __global__ __launch_bounds__(kTilePixels) void k_blend(const uint2 *__restrict__ ranges,
+                                                       const uint32_t *__restrict__ order,
                                                        const uint32_t *__restrict__ gids,
                                                        const float4 *__restrict__ recA,
                                                        const float4 *__restrict__ recB,
                                                        const float *__restrict__ recC, int width, int height,
                                                        int tiles_x, int n_tiles, const CamK *__restrict__ camd,
                                                        DevStatus *__restrict__ st, int passes, int n) {
-    constexpr int NW = kTilePixels / 64;                   // waves = quadrants
-    // staged batch: per slot three float4 = (u, v, -A/2, -C/2), (-B, log2 o, r, g),
-    // (b, list position + 1 as bits, -, -); 48 bytes, addressed by byte offset
-    // slot kTilePixels is a blank record (log2 o = -inf, so alpha = 0) that pads
-    // each list to a multiple of four entries
-    __shared__ float4 sR[(kTilePixels + 1) * 3];
-    __shared__ __align__(8) uint16_t sL[NW][kTilePixels];  // per-quadrant lists of slot byte offsets
-    __shared__ int s_cnt[NW][NW];                          // [staging wave][quadrant]
-    // The grid is 8 * ceil(n_tiles / 8) blocks; block b runs on XCD b % 8, and
-    // each XCD gets a contiguous band of tiles (neighbours share Gaussians).
+    constexpr int NW = kTilePixels / 64;   // waves = quadrants
+    // per wave: 64 record slots + one blank (log2 o = -inf, so alpha = 0) that
+    // pads a step to a multiple of four entries; a slot is three float4 =
+    // (u, v, -A/2, -C/2), (-B, log2 o, r, g), (b, list position + 1 as bits, -, -)
+    __shared__ float4 sR[NW][65 * 3];
     const int b = (int)blockIdx.x;
-    const int per = (int)gridDim.x / 8;
-    const int tile = (b % 8) * per + b / 8;
-    if (tile >= n_tiles) return;
+    if (b >= n_tiles) return;
+    const int tile = (int)order[b];   // block b blends tile order[b]: the longest lists start first
     const int tx = tile % tiles_x, ty = tile / tiles_x;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    if (tile == 0 && tid == 0) {
+    if (b == 0 && tid == 0) {
         st->tiles = (uint32_t)n_tiles;
         st->passes = (uint32_t)passes;
     }
@@ -944,108 +990,110 @@ __global__ __launch_bounds__(kTilePixels) void k_blend(const uint2 *__restrict__
     const int px = qx0 + (lane & 7), py = qy0 + (lane >> 3);
     const bool inside = px < width && py < height;
     const size_t pix = inside ? (size_t)py * width + px : 0;
-    if (tid < 3)
-        sR[3 * kTilePixels + tid] = tid == 1 ? make_float4(0.0f, -INFINITY, 0.0f, 0.0f) : make_float4(0.f, 0.f, 0.f, 0.f);
     const uint2 rg = ranges[tile];
     const int start = (int)rg.x, end = (int)rg.y;
     const float fpx = (float)px, fpy = (float)py;
+    // this quadrant's rectangle of pixel centres, clipped to the image
+    const float x_lo = (float)qx0, y_lo = (float)qy0;
+    const float x_hi = fminf(x_lo + 7.0f, (float)(width - 1));
+    const float y_hi = fminf(y_lo + 7.0f, (float)(height - 1));
     float T = 1.0f, cr = 0.0f, cg = 0.0f, cbl = 0.0f;
     bool done = !inside;
     int last = 0;
     int evals = inside ? end - start : 0;   // list entries this pixel evaluates
     const float a_min = 1.0f / 255.0f;
     const uint64_t lt = lanemask_lt64();
-    const char *rbase = reinterpret_cast<const char *>(sR);
-    for (int b0 = start; b0 < end; b0 += kTilePixels) {
-        if (__syncthreads_count(done) == kTilePixels) break;
-        // ---- stage one entry per thread; quadrant masks
-        const int i = b0 + tid;
-        uint32_t qmask = 0;
-        float4 A4 = make_float4(0.f, 0.f, 0.f, 0.f), B4 = A4;
-        float C1 = 0.0f;
+    float4 *__restrict__ R = sR[wave];
+    const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    const float4 blank1 = make_float4(0.f, -INFINITY, 0.f, 0.f);
+    // Software pipeline over the steps: while step k is culled and
+    // composited, the records of step k + 1 and the ids of step k + 2 are in
+    // flight (ids are checked where they are used, so no wait follows their
+    // load; g >= n only if the sort failed, which is flagged there).
+    auto load_gid = [&](int i) -> uint32_t { return i < end ? gids[i] : 0u; };
+    auto safe = [&](uint32_t g) -> uint32_t { return g < (uint32_t)n ? g : 0u; };
+    float4 nA = zero4, nB = zero4;
+    float nC = 0.0f;
+    if (start + lane < end) {
+        const uint32_t g = safe(load_gid(start + lane));
+        nA = recA[g];
+        nB = recB[g];
+        nC = recC[g];
+    }
+    uint32_t g_next = load_gid(start + 64 + lane);
+    for (int b0 = start; b0 < end; b0 += 64) {
+        if (__builtin_amdgcn_ballot_w64(!done) == 0) break;
+        const int i = b0 + lane;
+        const float4 A4 = nA, B4 = nB;
+        const float C1 = nC;
+        if (i + 64 < end) {
+            const uint32_t g = safe(g_next);
+            nA = recA[g];
+            nB = recB[g];
+            nC = recC[g];
+        }
+        g_next = load_gid(i + 128);
+        bool keep = false;
         if (i < end) {
-            uint32_t g = gids[i];
-            if (g >= (uint32_t)n) g = 0;   // only possible if the sort failed (flagged there)
-            A4 = recA[g];
-            B4 = recB[g];
-            C1 = recC[g];
             // conic from the stored halves: A = -2 ha, C = -2 hc, B = -nb
             const float A = -2.0f * A4.z, C = -2.0f * A4.w, Bc = -B4.x;
+            const float iA = __builtin_amdgcn_rcpf(A), iC = __builtin_amdgcn_rcpf(C);
             // alpha >= 1/255 needs q <= 2 ln(255 o)
             const float thr = 2.0f * (__logf(B4.y) + 5.541263545158426f);
-#pragma unroll
-            for (int q = 0; q < NW; ++q) {
-                const float x_lo = (float)(tx * kTile + (q & 1) * 8);
-                const float y_lo = (float)(ty * kTile + (q >> 1) * 8);
-                const float x_hi = fminf(x_lo + 7.0f, (float)(width - 1));
-                const float y_hi = fminf(y_lo + 7.0f, (float)(height - 1));
-                if (rect_may_reach(A4.x, A4.y, A, Bc, C, thr, x_lo, x_hi, y_lo, y_hi)) qmask |= 1u << q;
-            }
+            keep = rect_may_reach(A4.x, A4.y, A, Bc, C, iA, iC, thr, x_lo, x_hi, y_lo, y_hi);
         }
-        uint64_t bal[NW];
-#pragma unroll
-        for (int q = 0; q < NW; ++q) bal[q] = __ballot((qmask >> q) & 1u);
-        if (lane == 0) {
-#pragma unroll
-            for (int q = 0; q < NW; ++q) s_cnt[wave][q] = (int)__popcll(bal[q]);
-        }
-        if (qmask) {
-            sR[3 * tid] = A4;
-            sR[3 * tid + 1] = make_float4(B4.x, __log2f(B4.y), B4.z, B4.w);
-            sR[3 * tid + 2] = make_float4(C1, __int_as_float(i - start + 1), 0.0f, 0.0f);
-        }
-        __syncthreads();
-        int kept = 0;      // entries in this wave's own quadrant list
-#pragma unroll
-        for (int q = 0; q < NW; ++q) {
-            int base = 0;
-#pragma unroll
-            for (int w = 0; w < NW; ++w) {
-                const int c = s_cnt[w][q];
-                if (w < wave) base += c;
-                if (q == wave) kept += c;
-            }
-            if ((qmask >> q) & 1u) sL[q][base + (int)__popcll(bal[q] & lt)] = (uint16_t)(tid * 48);
-        }
-        kept = __builtin_amdgcn_readfirstlane(kept);
+        const uint64_t km = __builtin_amdgcn_ballot_w64(keep);
+        const int kept = (int)__popcll(km);
         const int kept4 = (kept + 3) & ~3;
-        if (lane < kept4 - kept) sL[wave][kept + lane] = (uint16_t)(kTilePixels * 48);
-        __syncthreads();
-        // ---- composite this wave's list (branch-free body)
-        if (!__all(done)) {
-            const uint16_t *__restrict__ LL = sL[wave];
-            for (int j = 0; j < kept4; j += 4) {
-                const uint2 offs = *reinterpret_cast<const uint2 *>(LL + j);
-                const uint32_t off4[4] = {offs.x & 0xffffu, offs.x >> 16, offs.y & 0xffffu, offs.y >> 16};
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const char *rec = rbase + off4[u];
-                    const float4 R0 = *reinterpret_cast<const float4 *>(rec);
-                    const float4 R1 = *reinterpret_cast<const float4 *>(rec + 16);
-                    const float2 R2 = *reinterpret_cast<const float2 *>(rec + 32);
-                    const float dx = R0.x - fpx, dy = R0.y - fpy;
-                    // -(A dx^2 + C dy^2)/2 - B dx dy in a fixed binary32 sequence
-                    const float power =
-                        __builtin_fmaf(R0.z * dx, dx, __builtin_fmaf(R0.w * dy, dy, (R1.x * dx) * dy));
-                    const float alpha =
-                        fminf(0.99f, __builtin_amdgcn_exp2f(__builtin_fmaf(power, 1.44269504f, R1.y)));
-                    const float test = __builtin_fmaf(-alpha, T, T);   // T (1 - alpha), one rounding
-                    const bool valid = !done & !(power > 0.0f) & !(alpha < a_min);
-                    const bool stop = valid & (test < 0.0001f);
-                    const bool add = valid ^ stop;
-                    const float w = add ? alpha * T : 0.0f;
-                    cr = __builtin_fmaf(R1.z, w, cr);
-                    cg = __builtin_fmaf(R1.w, w, cg);
-                    cbl = __builtin_fmaf(R2.x, w, cbl);
-                    T = add ? test : T;
-                    const int pos1 = __float_as_int(R2.y);
-                    last = add ? pos1 : last;
-                    evals = stop ? pos1 : evals;
-                    done = done | stop;
-                }
-                if (__builtin_amdgcn_ballot_w64(!done) == 0) break;
-            }
+        if (kept == 0) continue;
+        // pack the kept entries in list order; blank records pad to kept4
+        if (keep) {
+            const int slot = (int)__popcll(km & lt);
+            R[3 * slot] = A4;
+            R[3 * slot + 1] = make_float4(B4.x, __log2f(B4.y), B4.z, B4.w);
+            R[3 * slot + 2] = make_float4(C1, __int_as_float(i - start + 1), 0.0f, 0.0f);
         }
+        if (lane >= kept && lane < kept4) {
+            R[3 * lane] = zero4;
+            R[3 * lane + 1] = blank1;
+            R[3 * lane + 2] = zero4;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // ---- composite the packed entries (branch-free body)
+        for (int j = 0; j < kept4; j += 4) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const float4 R0 = R[3 * (j + u)];
+                const float4 R1 = R[3 * (j + u) + 1];
+                const float2 R2 = *reinterpret_cast<const float2 *>(&R[3 * (j + u) + 2]);
+                const float dx = R0.x - fpx, dy = R0.y - fpy;
+                // -(A dx^2 + C dy^2)/2 - B dx dy = dx (-A/2 dx - B dy) + (-C/2 dy) dy
+                const float power = __builtin_fmaf(dx, __builtin_fmaf(R0.z, dx, R1.x * dy), (R0.w * dy) * dy);
+                const float alpha = fminf(0.99f, __builtin_amdgcn_exp2f(__builtin_fmaf(power, 1.44269504f, R1.y)));
+                const float test = __builtin_fmaf(-alpha, T, T);   // T (1 - alpha), one rounding
+                const bool valid = !done & !(power > 0.0f) & !(alpha < a_min);
+                const bool stop = valid & (test < 0.0001f);
+                const bool add = valid ^ stop;
+                // the weight alpha T is the drop in transmittance
+                const float Tn = add ? test : T;
+                const float w = T - Tn;
+                cr = __builtin_fmaf(R1.z, w, cr);
+                cg = __builtin_fmaf(R1.w, w, cg);
+                cbl = __builtin_fmaf(R2.x, w, cbl);
+                T = Tn;
+                const int pos1 = __float_as_int(R2.y);
+                last = add ? pos1 : last;
+                evals = stop ? pos1 : evals;
+                done = done | stop;
+            }
+            if (__builtin_amdgcn_ballot_w64(!done) == 0) break;
+        }
+        // the next step rewrites the slots: finish this step's reads first
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     {
         __shared__ unsigned long long s_ev[NW];
@@ -1190,7 +1238,7 @@ g4d_status render(const g4d_splats *G, const g4d_camera *C, const g4d_workspace 
         hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, s, reinterpret_cast<uint4 *>(ws->ptr), n16, cam, camd);
     }
     mark(1);
-    const int blend_grid = 8 * ((tiles + 7) / 8);
+    uint32_t *order = at<uint32_t>(ws, L.order);
     if (n > 0) {
         const int nb_n = (n + 255) / 256;
         // 1. preprocess
@@ -1250,9 +1298,10 @@ g4d_status render(const g4d_splats *G, const g4d_camera *C, const g4d_workspace 
     } else {
         for (int i = 2; i <= 6; ++i) mark(i);
     }
+    hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, s, ranges, tiles, order);
     mark(7);
     // 7. blend (with n == 0 every range is empty and the image is the background)
-    hipLaunchKernelGGL(k_blend, dim3(blend_grid), dim3(kTilePixels), 0, s, ranges, tv[0], recA, recB, recC, C->width,
+    hipLaunchKernelGGL(k_blend, dim3(tiles), dim3(kTilePixels), 0, s, ranges, order, tv[0], recA, recB, recC, C->width,
                        C->height, cam.tiles_x, tiles, camd, st,
                        plan.passes, std::max(n, 1));
     mark(8);
