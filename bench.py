@@ -16,6 +16,7 @@ oracle timed on a bounded sample on this host.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import ctypes
 import json
 import os
@@ -168,6 +169,23 @@ def serving_bench(seconds: float, rate: float, budget_gb: float, slots: int, war
             "peak_request_bytes": int(served["peak_bytes"])}
 
 
+def blend_traffic():
+    """HBM bytes per blend launch from the committed counter summary, or None
+    when the blend kernel's source has changed since the counters were taken."""
+    root = os.path.dirname(os.path.abspath(__file__))
+    try:
+        md = open(os.path.join(root, "profiles", "k_blend_traffic_100k_800x800.md")).read()
+        data = json.loads(md.split("```json", 1)[1].split("```", 1)[0])
+        src = open(os.path.join(root, "paper_2310_08528_amd", "csrc", "raster.hip")).read()
+        a = src.index("// ---------------------------------------------------------------- k_blend")
+        b = src.index("// ---------------------------------------------------------------- k_export")
+    except (OSError, ValueError, IndexError):
+        return None
+    if hashlib.sha256(src[a:b].encode()).hexdigest() != data.get("kernel_source_sha256"):
+        return None
+    return int(data["traffic_bytes_per_launch"])
+
+
 def main():
     import faulthandler
     faulthandler.dump_traceback_later(90, repeat=True, file=sys.stderr)
@@ -176,7 +194,7 @@ def main():
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-frames", type=int, default=3)
+    ap.add_argument("--cpu-frames", type=int, default=20)
     ap.add_argument("--n", type=int, default=100_000)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -300,11 +318,13 @@ def main():
     evals_per_frame = evals_tot / n_prof
 
     # ---- roofline of the dominant kernel (the blend: VALU-bound)
+    traffic = blend_traffic()
     blend_flop = evals_per_frame * BLEND_FLOP_PER_EVAL
     achieved = blend_flop / (blend_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "kernel": "k_blend", "achieved": round(achieved, 3),
                 "peak": round(PEAK_VALU_TOPS, 2), "unit": "TFLOP/s", "frac": round(achieved / PEAK_VALU_TOPS, 4),
-                "traffic": None, "evals_per_frame": int(evals_per_frame),
+                "traffic": traffic, "traffic_unit": "bytes/launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+                "evals_per_frame": int(evals_per_frame),
                 "flop_per_eval": BLEND_FLOP_PER_EVAL, "avg_ms": round(blend_ms, 4),
                 "frac_of_published_fp32": round(achieved / PEAK_FP32_TFLOPS, 4)}
 

@@ -36,6 +36,7 @@ struct DeformJob {
 
 struct DeformBatch {
     int n_jobs;
+    int n_blocks;   // blocks of work (the grid is padded to a multiple of 8)
     DeformJob job[G4D_MAX_BATCH_JOBS];
 };
 
@@ -101,12 +102,18 @@ __global__ __launch_bounds__(kThreads) void k_deform(DeformBatch batch) {
     float *s_b1 = s_delta + kGB * 17;
     float *s_b2 = s_b1 + HID;
 
+    // Block b runs on XCD b % 8; each XCD takes a contiguous run of the
+    // work blocks, so spatially ordered Gaussians keep each XCD's share of
+    // the feature planes compact in its own L2.
+    const int per = (int)gridDim.x / 8;
+    const int wb = ((int)blockIdx.x % 8) * per + (int)blockIdx.x / 8;
+    if (wb >= batch.n_blocks) return;
     // job of this block
     int j = 0;
     for (int q = 1; q < batch.n_jobs; ++q)
-        if ((int)blockIdx.x >= batch.job[q].block_begin) j = q;
+        if (wb >= batch.job[q].block_begin) j = q;
     const DeformJob &job = batch.job[j];
-    const int g0 = ((int)blockIdx.x - job.block_begin) * kGB;
+    const int g0 = (wb - job.block_begin) * kGB;
     const int n = job.n;
     const int tid = threadIdx.x;
     const bool features_only = job.out_features != nullptr;
@@ -391,6 +398,7 @@ g4d_status launch(DeformBatch &B, const KernelEntry *ke, hipStream_t s) {
         blocks += (B.job[j].n + kGB - 1) / kGB;
     }
     if (blocks == 0) return G4D_OK;
+    B.n_blocks = blocks;
     static bool attr_done[sizeof(kDeformKernels) / sizeof(kDeformKernels[0])] = {};
     size_t idx = (size_t)(ke - kDeformKernels);
     if (!attr_done[idx]) {
@@ -398,7 +406,7 @@ g4d_status launch(DeformBatch &B, const KernelEntry *ke, hipStream_t s) {
                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)ke->smem));
         attr_done[idx] = true;
     }
-    hipLaunchKernelGGL(ke->fn, dim3(blocks), dim3(kThreads), ke->smem, s, B);
+    hipLaunchKernelGGL(ke->fn, dim3(8 * ((blocks + 7) / 8)), dim3(kThreads), ke->smem, s, B);
     G4D_HIP_CHECK(hipGetLastError());
     return G4D_OK;
 }
