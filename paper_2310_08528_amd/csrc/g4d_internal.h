@@ -41,6 +41,8 @@ struct DevStatus {
     uint32_t passes;
     uint32_t tile_counter[16];       // onesweep tile tickets, one per sort pass / scan
     unsigned long long blend_evals;  // (pixel, Gaussian) pairs evaluated by the blend
+    uint32_t pack_bits;              // instances packed as (tile << pack_bits) | index; 0: two arrays
+    uint32_t reserved;
 };
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }

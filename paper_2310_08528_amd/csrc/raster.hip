@@ -595,7 +595,7 @@ __device__ __forceinline__ void emit_wave(int n, const uint32_t *__restrict__ or
                                           const unsigned long long *__restrict__ offsets,
                                           const uint2 *__restrict__ rect, int tiles_x,
                                           const DevStatus *__restrict__ st, uint32_t *__restrict__ tkeys,
-                                          uint32_t *__restrict__ tvals, int bits0, uint32_t *h0) {
+                                          uint32_t *__restrict__ tvals, int pack_bits, int bits0, uint32_t *h0) {
     const int lane = threadIdx.x & 63;
     const unsigned long long K = st->k_used;
     const unsigned long long s0 = ((unsigned long long)blockIdx.x * 4 + (threadIdx.x >> 6)) * kEmitSlots;
@@ -653,8 +653,12 @@ __device__ __forceinline__ void emit_wave(int n, const uint32_t *__restrict__ or
             if (live) {
                 const int ry = r / ww;
                 t = (uint32_t)((oy + ry) * tiles_x + ox + (r - ry * ww));
-                tkeys[o] = t;
-                tvals[o] = og;
+                if (pack_bits) {
+                    tkeys[o] = (t << pack_bits) | og;
+                } else {
+                    tkeys[o] = t;
+                    tvals[o] = og;
+                }
                 atomicAdd(&h0[t & ((1u << bits0) - 1u)], 1u);
             }
         }
@@ -668,12 +672,12 @@ __global__ __launch_bounds__(256) void k_emit(int n, const uint32_t *__restrict_
                                               const unsigned long long *__restrict__ offsets,
                                               const uint2 *__restrict__ rect, int tiles_x,
                                               const DevStatus *__restrict__ st, uint32_t *__restrict__ tkeys,
-                                              uint32_t *__restrict__ tvals, int bits0,
+                                              uint32_t *__restrict__ tvals, int pack_bits, int bits0,
                                               uint32_t *__restrict__ cnt, int cnt_stride) {
     __shared__ uint32_t h0[256];
     for (int q = threadIdx.x; q < 256; q += blockDim.x) h0[q] = 0;
     __syncthreads();
-    emit_wave(n, order, offsets, rect, tiles_x, st, tkeys, tvals, bits0, h0);
+    emit_wave(n, order, offsets, rect, tiles_x, st, tkeys, tvals, pack_bits, bits0, h0);
     __syncthreads();
     // this block's digit counts for the first instance-sort pass (its slots
     // are exactly sort tile blockIdx.x)
@@ -713,44 +717,56 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_up(const uint32_t *__rest
     for (int q = threadIdx.x; q < NB; q += blockDim.x) cnt[(size_t)q * cnt_stride + tile] = h[q];
 }
 
-// per digit (one wave each): exclusive scan of its counts over the live
-// tiles, in place, and the digit's total
+// per digit (one block each): exclusive scan of its counts over the live
+// tiles, in place, and the digit's total.  Each thread sums a run of 16
+// counts, the block scans the 256 run sums, and the runs are rewritten.
 __global__ __launch_bounds__(256) void k_spine(uint32_t *__restrict__ cnt, int cnt_stride, int NB,
                                                const DevStatus *__restrict__ st, uint32_t cap,
                                                uint32_t *__restrict__ dtot) {
     if (st->overflow) return;
-    const int lane = threadIdx.x & 63;
-    const int d = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (d >= NB) return;   // wave-uniform
+    const int d = blockIdx.x;
+    if (d >= NB) return;
+    __shared__ uint32_t s_w[4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t count = min(st->k_used, cap);
     const int nlive = (int)((count + kSortTile - 1) / kSortTile);
     uint32_t *row = cnt + (size_t)d * cnt_stride;
+    constexpr int R = 16;
     uint32_t carry = 0;
-    constexpr int R = 16;   // 1024 tiles per segment, all loads in flight
-    for (int s0 = 0; s0 < nlive; s0 += 64 * R) {
+    for (int s0 = 0; s0 < nlive; s0 += 256 * R) {
+        const int b = s0 + tid * R;
         uint32_t v[R];
+        uint32_t sum = 0;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const int idx = s0 + r * 64 + lane;
-            v[r] = idx < nlive ? row[idx] : 0u;
+            v[r] = b + r < nlive ? row[b + r] : 0u;
+            sum += v[r];
         }
+        uint32_t x = sum;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) s_w[wave] = x;
+        __syncthreads();
+        uint32_t before = carry;
+        for (int w = 0; w < wave; ++w) before += s_w[w];
+        const uint32_t seg_total = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+        uint32_t run = before + x - sum;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            uint32_t x = v[r];
-#pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const uint32_t y = __shfl_up(x, o, 64);
-                if (lane >= o) x += y;
-            }
-            const int idx = s0 + r * 64 + lane;
-            if (idx < nlive) row[idx] = carry + x - v[r];
-            carry += __shfl(x, 63, 64);
+            if (b + r < nlive) row[b + r] = run;
+            run += v[r];
         }
+        carry += seg_total;
+        __syncthreads();   // s_w is rewritten by the next segment
     }
-    if (lane == 0) dtot[d] = carry;
+    if (tid == 0) dtot[d] = carry;
 }
 
-template <int ITEMS>
+// PACKED: an instance is one word (tile << pack_bits) | index; no value array
+template <int ITEMS, bool PACKED>
 __global__ __launch_bounds__(kSortThreads) void k_sort_down(
     const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
     uint32_t *__restrict__ vout, const DevStatus *__restrict__ st, uint32_t cap, int shift, int bits,
@@ -762,7 +778,8 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_down(
     __shared__ uint32_t s_base[256];
     __shared__ uint32_t s_tot[256];
     __shared__ uint32_t s_wg[4], s_wt[4];
-    __shared__ uint32_t s_k[TILE], s_v[TILE];
+    __shared__ uint32_t s_k[TILE];
+    __shared__ uint32_t s_v[PACKED ? 1 : TILE];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int NB = 1 << bits;
     const uint32_t mask = (uint32_t)NB - 1u;
@@ -782,7 +799,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_down(
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
         const uint32_t idx = base_idx + r * 64 + lane;
-        vals[r] = idx < count ? vin[idx] : 0u;
+        vals[r] = !PACKED && idx < count ? vin[idx] : 0u;
     }
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
@@ -846,7 +863,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_down(
             const uint32_t d = (keys[r] >> shift) & mask;
             const uint32_t lpos = s_tot[d] + s_wcnt[wave][d] + rank[r];
             s_k[lpos] = keys[r];
-            s_v[lpos] = vals[r];
+            if constexpr (!PACKED) s_v[lpos] = vals[r];
         }
     }
     __syncthreads();
@@ -857,7 +874,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_down(
         const uint32_t pos = s_base[d] + (li - s_tot[d]);
         if (pos < count) {
             kout[pos] = k;
-            vout[pos] = s_v[li];
+            if constexpr (!PACKED) vout[pos] = s_v[li];
         } else {
             atomicOr(err, 4u);   // inconsistent counts: never write out of bounds
         }
@@ -867,7 +884,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_down(
 // ---------------------------------------------------------------- k_ranges
 
 __global__ __launch_bounds__(256) void k_ranges(const DevStatus *__restrict__ st, const uint32_t *__restrict__ tkeys,
-                                                uint2 *__restrict__ ranges, uint32_t n_tiles) {
+                                                uint2 *__restrict__ ranges, uint32_t n_tiles, int kshift) {
     const uint32_t K = st->k_used;
     const uint32_t nq = (K + 3) / 4;
     constexpr uint32_t kNone = 0xffffffffu;
@@ -876,13 +893,13 @@ __global__ __launch_bounds__(256) void k_ranges(const DevStatus *__restrict__ st
         uint32_t k[4];
         if (i0 + 4 <= K) {
             const uint4 v = *reinterpret_cast<const uint4 *>(tkeys + i0);
-            k[0] = v.x; k[1] = v.y; k[2] = v.z; k[3] = v.w;
+            k[0] = v.x >> kshift; k[1] = v.y >> kshift; k[2] = v.z >> kshift; k[3] = v.w >> kshift;
         } else {
 #pragma unroll
-            for (int j = 0; j < 4; ++j) k[j] = i0 + j < K ? tkeys[i0 + j] : kNone;
+            for (int j = 0; j < 4; ++j) k[j] = i0 + j < K ? tkeys[i0 + j] >> kshift : kNone;
         }
-        const uint32_t prev = i0 > 0 ? tkeys[i0 - 1] : kNone;
-        const uint32_t next = i0 + 4 < K ? tkeys[i0 + 4] : kNone;
+        const uint32_t prev = i0 > 0 ? tkeys[i0 - 1] >> kshift : kNone;
+        const uint32_t next = i0 + 4 < K ? tkeys[i0 + 4] >> kshift : kNone;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const uint32_t t = k[j];
@@ -966,7 +983,7 @@ __device__ __forceinline__ bool rect_may_reach(float u, float v, float A, float 
 
 __global__ __launch_bounds__(kTilePixels) void k_blend(const uint2 *__restrict__ ranges,
                                                        const uint32_t *__restrict__ order,
-                                                       const uint32_t *__restrict__ gids,
+                                                       const uint32_t *__restrict__ gids, uint32_t gmask,
                                                        const float4 *__restrict__ recA,
                                                        const float4 *__restrict__ recB,
                                                        const float *__restrict__ recC, int width, int height,
@@ -985,6 +1002,7 @@ __global__ __launch_bounds__(kTilePixels) void k_blend(const uint2 *__restrict__
     if (b == 0 && tid == 0) {
         st->tiles = (uint32_t)n_tiles;
         st->passes = (uint32_t)passes;
+        st->pack_bits = gmask == 0xffffffffu ? 0u : (uint32_t)__popc(gmask);
     }
     const int qx0 = tx * kTile + (wave & 1) * 8, qy0 = ty * kTile + (wave >> 1) * 8;
     const int px = qx0 + (lane & 7), py = qy0 + (lane >> 3);
@@ -1011,7 +1029,10 @@ __global__ __launch_bounds__(kTilePixels) void k_blend(const uint2 *__restrict__
     // flight (ids are checked where they are used, so no wait follows their
     // load; g >= n only if the sort failed, which is flagged there).
     auto load_gid = [&](int i) -> uint32_t { return i < end ? gids[i] : 0u; };
-    auto safe = [&](uint32_t g) -> uint32_t { return g < (uint32_t)n ? g : 0u; };
+    auto safe = [&](uint32_t w) -> uint32_t {
+        const uint32_t g = w & gmask;
+        return g < (uint32_t)n ? g : 0u;
+    };
     float4 nA = zero4, nB = zero4;
     float nC = 0.0f;
     if (start + lane < end) {
@@ -1128,8 +1149,19 @@ __global__ void k_export_keys(const DevStatus *__restrict__ st, const uint32_t *
                               const uint32_t *__restrict__ tvals, const uint32_t *__restrict__ dkeys_by_gid,
                               unsigned long long *__restrict__ out, uint32_t k) {
     const uint32_t K = min(st->k_used, k);
+    const uint32_t pb = st->pack_bits;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < K; i += gridDim.x * blockDim.x) {
+        const uint32_t t = pb ? tkeys[i] >> pb : tkeys[i];
+        const uint32_t g = pb ? tkeys[i] & ((1u << pb) - 1u) : tvals[i];
+        out[i] = ((unsigned long long)t << 32) | dkeys_by_gid[g];
+    }
+}
+__global__ void k_export_gids(const DevStatus *__restrict__ st, const uint32_t *__restrict__ tkeys,
+                              const uint32_t *__restrict__ tvals, uint32_t *__restrict__ out, uint32_t k) {
+    const uint32_t K = min(st->k_used, k);
+    const uint32_t pb = st->pack_bits;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < K; i += gridDim.x * blockDim.x)
-        out[i] = ((unsigned long long)tkeys[i] << 32) | dkeys_by_gid[tvals[i]];
+        out[i] = pb ? tkeys[i] & ((1u << pb) - 1u) : tvals[i];
 }
 
 __global__ void k_export_splat2d(int n, const float4 *__restrict__ recA, const float4 *__restrict__ recB,
@@ -1208,6 +1240,14 @@ g4d_status render(const g4d_splats *G, const g4d_camera *C, const g4d_workspace 
     const int tiles = cam.tiles_x * cam.tiles_y;
     const uint32_t cap = (uint32_t)L.cap;
     const TilePassPlan plan = tile_pass_plan(tiles);
+    // An instance is packed into one word (tile << gbits) | index when the
+    // tile ids and the Gaussian indices fit in 32 bits together; otherwise
+    // tile ids and indices travel in two arrays.
+    int gbits = 1, tbits = 0;
+    while (gbits < 32 && (1u << gbits) < (uint32_t)n) ++gbits;
+    while ((1 << tbits) < tiles) ++tbits;
+    const bool packed = n > 0 && gbits + tbits <= 32;
+    const int kshift = packed ? gbits : 0;
 
     DevStatus *st = at<DevStatus>(ws, L.status);
     CamK *camd = at<CamK>(ws, L.cam);
@@ -1272,7 +1312,7 @@ g4d_status render(const g4d_splats *G, const g4d_camera *C, const g4d_workspace 
         const int cstride = L.nblk_k;
         const int kblocks = L.nblk_k;
         hipLaunchKernelGGL(k_emit, dim3(kblocks), dim3(256), 0, s, n, order, offsets, rect, cam.tiles_x, st, tk[e],
-                           tv[e], plan.bits[0], tcnt, cstride);
+                           tv[e], packed ? gbits : 0, plan.bits[0], tcnt, cstride);
         mark(5);
         // 5. instance sort by tile digits (reduce-then-scan passes)
         int cur = e;
@@ -1282,18 +1322,23 @@ g4d_status render(const g4d_splats *G, const g4d_camera *C, const g4d_workspace 
             const int NB = 1 << plan.bits[p];
             if (p > 0)
                 hipLaunchKernelGGL(k_sort_up, dim3(kblocks), dim3(kSortThreads), 0, s, tk[cur], st, cap,
-                                   plan.shift[p], plan.bits[p], pc, cstride);
-            hipLaunchKernelGGL(k_spine, dim3((NB + 3) / 4), dim3(256), 0, s, pc, cstride, NB, st, cap, pt);
-            hipLaunchKernelGGL(k_sort_down<kSortItems>, dim3(kblocks), dim3(kSortThreads), 0, s, tk[cur], tv[cur],
-                               tk[cur ^ 1], tv[cur ^ 1], st, cap, plan.shift[p], plan.bits[p], pc, cstride, pt,
-                               &st->sort_error);
+                                   kshift + plan.shift[p], plan.bits[p], pc, cstride);
+            hipLaunchKernelGGL(k_spine, dim3(NB), dim3(256), 0, s, pc, cstride, NB, st, cap, pt);
+            if (packed)
+                hipLaunchKernelGGL((k_sort_down<kSortItems, true>), dim3(kblocks), dim3(kSortThreads), 0, s, tk[cur],
+                                   tv[cur], tk[cur ^ 1], tv[cur ^ 1], st, cap, kshift + plan.shift[p], plan.bits[p],
+                                   pc, cstride, pt, &st->sort_error);
+            else
+                hipLaunchKernelGGL((k_sort_down<kSortItems, false>), dim3(kblocks), dim3(kSortThreads), 0, s, tk[cur],
+                                   tv[cur], tk[cur ^ 1], tv[cur ^ 1], st, cap, plan.shift[p], plan.bits[p], pc,
+                                   cstride, pt, &st->sort_error);
             cur ^= 1;
         }
         mark(6);
         // 6. ranges
         {
             const int rblocks = (int)std::min<int64_t>((L.cap + 255) / 256, 4096);
-            hipLaunchKernelGGL(k_ranges, dim3(rblocks), dim3(256), 0, s, st, tk[0], ranges, (uint32_t)tiles);
+            hipLaunchKernelGGL(k_ranges, dim3(rblocks), dim3(256), 0, s, st, tk[0], ranges, (uint32_t)tiles, kshift);
         }
     } else {
         for (int i = 2; i <= 6; ++i) mark(i);
@@ -1301,7 +1346,8 @@ g4d_status render(const g4d_splats *G, const g4d_camera *C, const g4d_workspace 
     hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, s, ranges, tiles, order);
     mark(7);
     // 7. blend (with n == 0 every range is empty and the image is the background)
-    hipLaunchKernelGGL(k_blend, dim3(tiles), dim3(kTilePixels), 0, s, ranges, order, tv[0], recA, recB, recC, C->width,
+    hipLaunchKernelGGL(k_blend, dim3(tiles), dim3(kTilePixels), 0, s, ranges, order, packed ? tk[0] : tv[0],
+                       packed ? (1u << gbits) - 1u : 0xffffffffu, recA, recB, recC, C->width,
                        C->height, cam.tiles_x, tiles, camd, st,
                        plan.passes, std::max(n, 1));
     mark(8);
@@ -1342,8 +1388,8 @@ g4d_status render_export(const g4d_workspace *ws, int32_t kind, int32_t n, int64
         case G4D_EXPORT_SORTED_GIDS: {
             if (k > L.cap || bytes < (size_t)k * 4) return G4D_EINVAL;
             if (k == 0) return G4D_OK;
-            hipLaunchKernelGGL(k_copy_u32, dim3(256), dim3(256), 0, s, at<uint32_t>(ws, L.tv0),
-                               static_cast<uint32_t *>(dst), st, (uint32_t)k, 1);
+            hipLaunchKernelGGL(k_export_gids, dim3(256), dim3(256), 0, s, st, at<uint32_t>(ws, L.tk0),
+                               at<uint32_t>(ws, L.tv0), static_cast<uint32_t *>(dst), (uint32_t)k);
             break;
         }
         case G4D_EXPORT_RECT: {

@@ -250,6 +250,14 @@ def test_full_size_config2_one_frame(dev):
     _check_render(s, cam, "C2 full frame", capacity=8 << 20)
 
 
+def test_render_two_array_instances(dev):
+    """An instance is one 32-bit word (tile << b) | index when tile ids and
+    Gaussian indices fit together; here 140k indices (18 bits) and 16640
+    tiles (15 bits) do not, so the instances travel as two arrays."""
+    sc = synth.tiny_scene(11, n=140_000, width=4096, height=1040, sh_degree=1, log_scale_mean=-4.5)
+    _check_render(scene_splats(sc), sc.cameras[0], "two-array instances 4096x1040", capacity=8 << 20)
+
+
 # ------------------------------------------------------- large config, BF16 MLP
 
 def _bf16_report(sc, t):
