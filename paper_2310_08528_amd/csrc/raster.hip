@@ -505,16 +505,22 @@ __global__ __launch_bounds__(256) void k_scan_offsets(int n, const uint32_t *__r
     const uint32_t tile = s_tile;
     const uint32_t ntiles = ((uint32_t)n + kScanTile - 1) / kScanTile;
     if (tile >= ntiles) return;
+    // 16 consecutive items per thread (64-byte aligned: whole-vector loads)
     const uint32_t base = tile * kScanTile + tid * 16;
     uint32_t v[16], gs[16];
-    unsigned long long sum = 0;
+    if (base + 16 <= (uint32_t)n) {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const uint32_t i = base + r;
-        gs[r] = i < (uint32_t)n ? order[i] : 0xffffffffu;
+        for (int r = 0; r < 4; ++r) {
+            const uint4 q = *reinterpret_cast<const uint4 *>(order + base + 4 * r);
+            gs[4 * r] = q.x; gs[4 * r + 1] = q.y; gs[4 * r + 2] = q.z; gs[4 * r + 3] = q.w;
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) gs[r] = base + r < (uint32_t)n ? order[base + r] : 0xffffffffu;
     }
 #pragma unroll
     for (int r = 0; r < 16; ++r) v[r] = gs[r] < (uint32_t)n ? touched[gs[r]] : 0u;
+    unsigned long long sum = 0;
 #pragma unroll
     for (int r = 0; r < 16; ++r) sum += v[r];
     // wave inclusive scan of per-thread sums
@@ -531,48 +537,70 @@ __global__ __launch_bounds__(256) void k_scan_offsets(int n, const uint32_t *__r
         if (w < wave) wpre += s_w[w];
         btotal += s_w[w];
     }
-    if (tid == 0) {
-        unsigned long long excl = 0;
+    // decoupled look-back, one wave reading up to 64 predecessors at once:
+    // sum the aggregates back to the nearest inclusive prefix
+    if (wave == 0) {
         unsigned long long *mine = lookback + tile;
+        unsigned long long excl = 0;
         if (tile == 0) {
-            atomic_store_u64(mine, kF64Inc | btotal);
+            if (lane == 0) atomic_store_u64(mine, kF64Inc | btotal);
         } else {
-            atomic_store_u64(mine, kF64Agg | btotal);
-            int j = (int)tile - 1;
-            while (j >= 0) {
-                const unsigned long long *p = lookback + j;
-                unsigned long long s = atomic_load_u64(p);
-                uint32_t spins = 0;
-                while ((s >> 62) == 0ull && spins < kSpinLimit) {
+            if (lane == 0) atomic_store_u64(mine, kF64Agg | btotal);
+            int j = (int)tile - 1;   // nearest predecessor not yet summed
+            uint32_t spins = 0;
+            while (true) {
+                const int idx = j - lane;
+                const unsigned long long sv = idx >= 0 ? atomic_load_u64(lookback + idx) : kF64Inc;
+                const uint64_t inc = __ballot((sv & kF64Inc) != 0ull);
+                const uint64_t none = __ballot((sv >> 62) == 0ull);
+                const int first_inc = inc ? __ffsll((long long)inc) - 1 : 64;
+                const uint64_t need = first_inc < 63 ? (2ull << first_inc) - 1ull : ~0ull;
+                if (none & need) {
+                    if (++spins >= kSpinLimit) {
+                        if (lane == 0) atomicOr(&st->sort_error, 2u);
+                        break;
+                    }
                     __builtin_amdgcn_s_sleep(1);
-                    s = atomic_load_u64(p);
-                    ++spins;
+                    continue;
                 }
-                if ((s >> 62) == 0ull) {
-                    atomicOr(&st->sort_error, 2u);
-                    break;
-                }
-                excl += s & kV64Mask;
-                if ((s & kF64Inc) != 0ull) break;
-                --j;
+                unsigned long long part = lane <= first_inc ? (sv & kV64Mask) : 0ull;
+#pragma unroll
+                for (int o = 32; o >= 1; o >>= 1) part += __shfl_xor(part, o, 64);
+                excl += part;
+                if (first_inc < 64) break;
+                j -= 64;
             }
-            atomic_store_u64(mine, kF64Inc | (excl + btotal));
+            if (lane == 0) atomic_store_u64(mine, kF64Inc | (excl + btotal));
         }
-        s_prefix = excl;
-        if (tile == ntiles - 1) {
-            const unsigned long long K = excl + btotal;
-            st->k_total = K;
-            st->k_used = (uint32_t)(K < capacity ? K : capacity);
-            st->overflow = K > capacity ? 1u : 0u;
+        if (lane == 0) {
+            s_prefix = excl;
+            if (tile == ntiles - 1) {
+                const unsigned long long K = excl + btotal;
+                st->k_total = K;
+                st->k_used = (uint32_t)(K < capacity ? K : capacity);
+                st->overflow = K > capacity ? 1u : 0u;
+            }
         }
     }
     __syncthreads();
     unsigned long long run = s_prefix + wpre + (x - sum);
+    if (base + 16 <= (uint32_t)n) {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const uint32_t i = base + r;
-        if (i < (uint32_t)n) offsets[i] = run;
-        run += v[r];
+        for (int r = 0; r < 8; ++r) {
+            ulonglong2 q;
+            q.x = run;
+            run += v[2 * r];
+            q.y = run;
+            run += v[2 * r + 1];
+            *reinterpret_cast<ulonglong2 *>(offsets + base + 2 * r) = q;
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const uint32_t i = base + r;
+            if (i < (uint32_t)n) offsets[i] = run;
+            run += v[r];
+        }
     }
 }
 
