@@ -125,7 +125,10 @@ __device__ __forceinline__ float3 sh_colour(int deg, const float (&c)[16][3], fl
     return out;
 }
 
-__global__ __launch_bounds__(256) void k_preprocess(int n, int sh_degree, const float *__restrict__ means,
+// 1024 threads per block: the per-block depth-digit histograms are folded
+// into the device-wide ones with device-scope atomics, whose count (and
+// contention on the few live top-digit bins) falls with the block count.
+__global__ __launch_bounds__(1024) void k_preprocess(int n, int sh_degree, const float *__restrict__ means,
                                                     const float *__restrict__ scales,
                                                     const float *__restrict__ quats,
                                                     const float *__restrict__ opac, const float *__restrict__ sh,
@@ -135,7 +138,9 @@ __global__ __launch_bounds__(256) void k_preprocess(int n, int sh_degree, const 
                                                     uint32_t *__restrict__ touched, uint32_t *__restrict__ dkeys,
                                                     uint32_t *__restrict__ depth_hist, DevStatus *__restrict__ st) {
     __shared__ uint32_t h[4][256];
+    __shared__ uint32_t s_vis;
     for (int i = threadIdx.x; i < 4 * 256; i += blockDim.x) (&h[0][0])[i] = 0;
+    if (threadIdx.x == 0) s_vis = 0;
     __syncthreads();
     const CamK cam = *camd;
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
@@ -250,12 +255,13 @@ __global__ __launch_bounds__(256) void k_preprocess(int n, int sh_degree, const 
         atomicAdd(&h[3][key >> 24], 1u);
     }
     const uint64_t vb = __ballot(vis);
-    if (__lane_id() == 0 && vb) atomicAdd(&st->visible, (uint32_t)__popcll(vb));
+    if (__lane_id() == 0 && vb) atomicAdd(&s_vis, (uint32_t)__popcll(vb));
     __syncthreads();
     for (int i = threadIdx.x; i < 4 * 256; i += blockDim.x) {
         const uint32_t c = (&h[0][0])[i];
         if (c) atomicAdd(&depth_hist[i], c);
     }
+    if (threadIdx.x == 0 && s_vis) atomicAdd(&st->visible, s_vis);
 }
 
 // ---------------------------------------------------------------- k_sort_pass
@@ -287,6 +293,8 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_pass(
     const uint32_t mask = (uint32_t)NB - 1u;
     uint32_t count = count_max;
     if (d_count) count = min(*d_count, count_max);
+    // the digit histogram is read while the ticket is taken
+    const uint32_t gh = tid < NB ? ghist[tid] : 0u;
     if (tid == 0) {
         s_tile = atomicAdd(ticket, 1u);
         s_trivial = 0;
@@ -294,8 +302,8 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_pass(
     for (int i = tid; i < 4 * 256; i += kSortThreads) (&s_wcnt[0][0])[i] = 0;
     __syncthreads();
     if (tid < NB) {
-        s_g[tid] = ghist[tid];
-        if (s_g[tid] == count) s_trivial = 1;   // every key has this digit
+        s_g[tid] = gh;
+        if (gh == count) s_trivial = 1;   // every key has this digit
     }
     __syncthreads();
     const uint32_t tile = s_tile;
@@ -1308,9 +1316,9 @@ g4d_status render(const g4d_splats *G, const g4d_camera *C, const g4d_workspace 
     mark(1);
     uint32_t *order = at<uint32_t>(ws, L.order);
     if (n > 0) {
-        const int nb_n = (n + 255) / 256;
+        const int nb_n = (n + 1023) / 1024;
         // 1. preprocess
-        hipLaunchKernelGGL(k_preprocess, dim3(nb_n), dim3(256), 0, s, n, G->sh_degree, G->means, G->scales,
+        hipLaunchKernelGGL(k_preprocess, dim3(nb_n), dim3(1024), 0, s, n, G->sh_degree, G->means, G->scales,
                            G->quats, G->opacity, G->sh, camd, recA, recB, recC, rect, touched, dgid, depth_hist, st);
         mark(2);
         // 2. depth sort: four 8-bit passes over n keys; values start as the identity
