@@ -40,7 +40,6 @@ struct DevStatus {
     uint32_t tiles;
     uint32_t passes;
     uint32_t tile_counter[16];       // onesweep tile tickets, one per sort pass / scan
-    unsigned long long blend_evals;  // (pixel, Gaussian) pairs evaluated by the blend
     uint32_t pack_bits;              // instances packed as (tile << pack_bits) | index; 0: two arrays
     uint32_t reserved;
 };
@@ -68,6 +67,7 @@ struct WsLayout {
     size_t recA, recB, recC, rect, touched, dgid, dk0, dk1, dv0, dv1, offsets, tk0, tk1, tv0, tv1;
     size_t tcnt, tdtot;  // instance sort: per-pass digit counts [256][nblk_k] and digit totals [256]
     size_t order;        // blend order of the tiles (longest list first)
+    size_t evals;        // per tile: (pixel, Gaussian) pairs the blend evaluated (u64)
     size_t total;
 };
 
@@ -109,6 +109,7 @@ inline bool make_layout(int32_t n, int32_t w, int32_t h, int64_t cap, WsLayout *
     L->tcnt = take((size_t)2 * 256 * L->nblk_k * 4);
     L->tdtot = take((size_t)2 * 256 * 4);
     L->order = take((size_t)L->tiles_max * 4);
+    L->evals = take((size_t)L->tiles_max * 8);
     L->total = o;
     return true;
 }

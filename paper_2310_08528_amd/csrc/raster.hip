@@ -1024,7 +1024,9 @@ __global__ __launch_bounds__(kTilePixels) void k_blend(const uint2 *__restrict__
                                                        const float4 *__restrict__ recB,
                                                        const float *__restrict__ recC, int width, int height,
                                                        int tiles_x, int n_tiles, const CamK *__restrict__ camd,
-                                                       DevStatus *__restrict__ st, int passes, int n) {
+                                                       DevStatus *__restrict__ st,
+                                                       unsigned long long *__restrict__ tile_evals, int passes,
+                                                       int n) {
     constexpr int NW = kTilePixels / 64;   // waves = quadrants
     // per wave: 64 record slots + one blank (log2 o = -inf, so alpha = 0) that
     // pads a step to a multiple of four entries; a slot is three float4 =
@@ -1162,7 +1164,7 @@ __global__ __launch_bounds__(kTilePixels) void k_blend(const uint2 *__restrict__
         if (tid == 0) {
             unsigned long long sum = 0;
             for (int w = 0; w < NW; ++w) sum += s_ev[w];
-            if (sum) atomicAdd(&st->blend_evals, sum);
+            tile_evals[tile] = sum;   // summed on the host by read_status (no contended atomic)
         }
     }
     if (inside) {
@@ -1384,7 +1386,7 @@ g4d_status render(const g4d_splats *G, const g4d_camera *C, const g4d_workspace 
     // 7. blend (with n == 0 every range is empty and the image is the background)
     hipLaunchKernelGGL(k_blend, dim3(tiles), dim3(kTilePixels), 0, s, ranges, order, packed ? tk[0] : tv[0],
                        packed ? (1u << gbits) - 1u : 0xffffffffu, recA, recB, recC, C->width,
-                       C->height, cam.tiles_x, tiles, camd, st,
+                       C->height, cam.tiles_x, tiles, camd, st, at<unsigned long long>(ws, L.evals),
                        plan.passes, std::max(n, 1));
     mark(8);
     G4D_HIP_CHECK(hipGetLastError());
@@ -1402,7 +1404,16 @@ g4d_status read_status(const g4d_workspace *ws, g4d_device_status *out, hipStrea
     out->sort_error = (int32_t)h.sort_error;
     out->visible = (int32_t)h.visible;
     out->tiles = (int32_t)h.tiles;
-    out->blend_evals = (int64_t)h.blend_evals;
+    // blend work: one count per tile of the last frame
+    int64_t evals = 0;
+    if (h.tiles > 0 && (int64_t)h.tiles <= (int64_t)L.tiles_max) {
+        std::vector<unsigned long long> te(h.tiles);
+        G4D_HIP_CHECK(hipMemcpyAsync(te.data(), at<unsigned long long>(ws, L.evals), te.size() * 8,
+                                     hipMemcpyDeviceToHost, s));
+        G4D_HIP_CHECK(hipStreamSynchronize(s));
+        for (unsigned long long v : te) evals += (int64_t)v;
+    }
+    out->blend_evals = evals;
     return G4D_OK;
 }
 
