@@ -118,37 +118,38 @@ __global__ __launch_bounds__(kThreads) void k_deform(DeformBatch batch) {
     const int tid = threadIdx.x;
     const bool features_only = job.out_features != nullptr;
 
-    // ---- stage decoder weights (rows of W1; heads padded to 16 rows)
+    // ---- decoder weights (rows of W1; heads padded to 16 rows): the loads
+    // are issued here and stay in flight through the encoder's gathers; the
+    // LDS stores follow the encoder (registers are free here: LDS, not VGPRs,
+    // limits the blocks per CU).
+    constexpr int N1 = (HID * KP + kThreads - 1) / kThreads;
+    constexpr int N2 = (16 * HID + kThreads - 1) / kThreads;
+    float v1[N1], v2[N2];
+    float vb1 = 0.0f, vb2 = 0.0f;
     if (!features_only) {
-        for (int i = tid; i < HID * KP; i += kThreads) {
-            int r = i / KP, c = i - r * KP;
-            float v = c < K ? job.w1[r * K + c] : 0.0f;
-            if constexpr (BF16) s_w1[r * S::W1_LD + c] = f32_to_bf16_rne(v);
-            else s_w1[r * S::W1_LD + c] = v;
+#pragma unroll
+        for (int q = 0; q < N1; ++q) {
+            const int i = tid + q * kThreads;
+            const int r = i / KP, c = i - r * KP;
+            v1[q] = (i < HID * KP && c < K) ? job.w1[r * K + c] : 0.0f;
         }
-        for (int i = tid; i < 16 * HID; i += kThreads) {
-            int r = i / HID, c = i - r * HID;
-            float v = 0.0f;
-            if (r < 3) v = job.wx[r * HID + c];
-            else if (r < 7) v = job.wr[(r - 3) * HID + c];
-            else if (r < 10) v = job.ws[(r - 7) * HID + c];
-            if constexpr (BF16) s_w2[r * S::W2_LD + c] = f32_to_bf16_rne(v);
-            else s_w2[r * S::W2_LD + c] = v;
+#pragma unroll
+        for (int q = 0; q < N2; ++q) {
+            const int i = tid + q * kThreads;
+            const int r = i / HID, c = i - r * HID;
+            const float *src = r < 3 ? job.wx + r * HID : (r < 7 ? job.wr + (r - 3) * HID : job.ws + (r - 7) * HID);
+            v2[q] = (i < 16 * HID && r < 10) ? src[c] : 0.0f;
         }
-        for (int i = tid; i < HID; i += kThreads) s_b1[i] = job.b1[i];
-        if (tid < 16) {
-            float v = 0.0f;
-            if (tid < 3) v = job.bx[tid];
-            else if (tid < 7) v = job.br[tid - 3];
-            else if (tid < 10) v = job.bs[tid - 7];
-            s_b2[tid] = v;
-        }
+        vb1 = tid < HID ? job.b1[tid] : 0.0f;
+        if (tid < 3) vb2 = job.bx[tid];
+        else if (tid < 7) vb2 = job.br[tid - 3];
+        else if (tid < 10) vb2 = job.bs[tid - 7];
     }
 
     // ---- A. encoder: f_h for 64 Gaussians
     constexpr int LPG = F / 4;                 // lanes per Gaussian
     constexpr int GPP = kThreads / LPG;        // Gaussians per pass
-#pragma unroll 1
+#pragma unroll
     for (int pass = 0; pass < kGB / GPP; ++pass) {
         const int gl = pass * GPP + tid / LPG;
         const int c4 = tid % LPG;
@@ -202,6 +203,28 @@ __global__ __launch_bounds__(kThreads) void k_deform(DeformBatch batch) {
         }
     }
     if (features_only) return;
+    {
+#pragma unroll
+        for (int q = 0; q < N1; ++q) {
+            const int i = tid + q * kThreads;
+            if (i < HID * KP) {
+                const int r = i / KP, c = i - r * KP;
+                if constexpr (BF16) s_w1[r * S::W1_LD + c] = f32_to_bf16_rne(v1[q]);
+                else s_w1[r * S::W1_LD + c] = v1[q];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < N2; ++q) {
+            const int i = tid + q * kThreads;
+            if (i < 16 * HID) {
+                const int r = i / HID, c = i - r * HID;
+                if constexpr (BF16) s_w2[r * S::W2_LD + c] = f32_to_bf16_rne(v2[q]);
+                else s_w2[r * S::W2_LD + c] = v2[q];
+            }
+        }
+        if (tid < HID) s_b1[tid] = vb1;
+        if (tid < 16) s_b2[tid] = vb2;
+    }
     if constexpr (BF16 && KP > K) {
         // zero the padding columns K..KP of f_h
         for (int i = tid; i < kGB * (KP - K); i += kThreads) {
