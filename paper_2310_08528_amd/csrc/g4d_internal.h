@@ -17,8 +17,8 @@ constexpr int kTilePixels = kTile * kTile;   // one blend block per tile
 
 // Radix-sort tiling: 256 threads x kSortItems keys per block.
 constexpr int kSortThreads = 256;
-constexpr int kSortItems = 16;
-constexpr int kSortTile = kSortThreads * kSortItems;   // 4096 keys per block (instances)
+constexpr int kSortItems = 8;
+constexpr int kSortTile = kSortThreads * kSortItems;   // 2048 keys per block (instances)
 constexpr int kSortItemsN = 4;
 constexpr int kSortTileN = kSortThreads * kSortItemsN; // 1024 keys per block (per-Gaussian depth)
 constexpr int kScanTile = 256 * 16;                    // 4096 values per scan block

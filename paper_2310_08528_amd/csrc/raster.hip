@@ -614,7 +614,7 @@ __global__ __launch_bounds__(256) void k_scan_offsets(int n, const uint32_t *__r
 
 // ---------------------------------------------------------------- k_emit
 //
-// Load-balanced fan-out: wave w writes instance slots [1024 w, 1024 (w+1)),
+// Load-balanced fan-out: wave w writes instance slots [512 w, 512 (w+1)),
 // whatever Gaussians they belong to.  It finds the Gaussian (in depth order)
 // owning its first slot with a 64-way cooperative search over the offsets,
 // then walks batches of 64 consecutive Gaussians; within a batch each lane
@@ -622,9 +622,9 @@ __global__ __launch_bounds__(256) void k_scan_offsets(int n, const uint32_t *__r
 // (shuffles).  Stores are coalesced.  (Nearby Gaussians, first in depth
 // order, cover thousands of tiles, so balancing by Gaussian would not do.)
 
-constexpr int kEmitSlots = 1024;   // instance slots per wave
+constexpr int kEmitSlots = 512;    // instance slots per wave
 
-// The work of one wave: slots [1024 w, 1024 (w+1)) below K, counting the
+// The work of one wave: slots [512 w, 512 (w+1)) below K, counting the
 // low tile digit of each instance (consecutive slots of a Gaussian are
 // consecutive tiles of a row, so the lanes hit different LDS words).
 __device__ __forceinline__ void emit_wave(int n, const uint32_t *__restrict__ order,
