@@ -1017,6 +1017,8 @@ __device__ __forceinline__ bool rect_may_reach(float u, float v, float A, float 
     return !(qmin > thr + 1e-3f * (1.0f + fabsf(thr)) + 2e-6f * (A + C) * d2);
 }
 
+constexpr int kBlendUnroll = 8;   // entries composited per step of the loop (power of two, <= 64)
+
 __global__ __launch_bounds__(kTilePixels) void k_blend(const uint2 *__restrict__ ranges,
                                                        const uint32_t *__restrict__ order,
                                                        const uint32_t *__restrict__ gids, uint32_t gmask,
@@ -1028,10 +1030,10 @@ __global__ __launch_bounds__(kTilePixels) void k_blend(const uint2 *__restrict__
                                                        unsigned long long *__restrict__ tile_evals, int passes,
                                                        int n) {
     constexpr int NW = kTilePixels / 64;   // waves = quadrants
-    // per wave: 64 record slots + one blank (log2 o = -inf, so alpha = 0) that
-    // pads a step to a multiple of four entries; a slot is three float4 =
+    // per wave: 64 record slots; blank records (log2 o = -inf, so alpha = 0)
+    // pad a step to a multiple of the unroll; a slot is three float4 =
     // (u, v, -A/2, -C/2), (-B, log2 o, r, g), (b, list position + 1 as bits, -, -)
-    __shared__ float4 sR[NW][65 * 3];
+    __shared__ float4 sR[NW][64 * 3];
     const int b = (int)blockIdx.x;
     if (b >= n_tiles) return;
     const int tile = (int)order[b];   // block b blends tile order[b]: the longest lists start first
@@ -1103,9 +1105,10 @@ __global__ __launch_bounds__(kTilePixels) void k_blend(const uint2 *__restrict__
         }
         const uint64_t km = __builtin_amdgcn_ballot_w64(keep);
         const int kept = (int)__popcll(km);
-        const int kept4 = (kept + 3) & ~3;
+        const int kept4 = (kept + kBlendUnroll - 1) & ~(kBlendUnroll - 1);
         if (kept == 0) continue;
-        // pack the kept entries in list order; blank records pad to kept4
+        // pack the kept entries in list order; blank records pad to a multiple
+        // of the unroll
         if (keep) {
             const int slot = (int)__popcll(km & lt);
             R[3 * slot] = A4;
@@ -1121,9 +1124,9 @@ __global__ __launch_bounds__(kTilePixels) void k_blend(const uint2 *__restrict__
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         // ---- composite the packed entries (branch-free body)
-        for (int j = 0; j < kept4; j += 4) {
+        for (int j = 0; j < kept4; j += kBlendUnroll) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < kBlendUnroll; ++u) {
                 const float4 R0 = R[3 * (j + u)];
                 const float4 R1 = R[3 * (j + u) + 1];
                 const float2 R2 = *reinterpret_cast<const float2 *>(&R[3 * (j + u) + 2]);
