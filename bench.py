@@ -169,6 +169,90 @@ def serving_bench(seconds: float, rate: float, budget_gb: float, slots: int, war
             "peak_request_bytes": int(served["peak_bytes"])}
 
 
+def time_scene(sc, precision, steps, warmup, n_frames=None):
+    """frames/s and per-stage ms of deform + render over a scene's frame
+    sequence (camera k mod cameras, timestamp k mod timestamps)."""
+    import torch
+    from paper_2310_08528_amd import g4d
+    dev = "cuda:0"
+    ev = HipEvents()
+    nc, nt = len(sc.cameras), len(sc.timestamps)
+    nf = n_frames or max(nc, nt)
+    frames = [(k % nc, float(sc.timestamps[k % nt])) for k in range(nf)]
+    G = g4d.DeviceGaussians(sc.gaussians, dev)
+    P = g4d.DevicePlanes(sc.planes, dev)
+    M = g4d.DeviceMLP(sc.mlp, dev, precision)
+    S = g4d.DeviceSplats(G.n, G.sh_degree, G.sh, dev)
+    cams = [g4d.camera_struct(c) for c in sc.cameras]
+    W, H = sc.cameras[0].width, sc.cameras[0].height
+    img = torch.empty((3, H, W), dtype=torch.float32, device=dev)
+    capacity = 64 * G.n + 4096
+    ws = g4d.RenderWorkspace(G.n, W, H, capacity, dev)
+    kmax = 0
+    for (ci, t) in frames:
+        g4d.deform(G, P, M, t, S)
+        g4d.render(S, cams[ci], ws, img)
+        st = g4d.read_status(ws)
+        kmax = max(kmax, int(st.instances))
+        if st.overflow:
+            del ws
+            capacity = int(kmax * 1.25) + 4096
+            ws = g4d.RenderWorkspace(G.n, W, H, capacity, dev)
+    for k in range(warmup):
+        ci, t = frames[k % nf]
+        g4d.deform(G, P, M, t, S)
+        g4d.render(S, cams[ci], ws, img)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        ci, t = frames[k % nf]
+        g4d.deform(G, P, M, t, S)
+        g4d.render(S, cams[ci], ws, img)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = g4d.read_status(ws)
+    assert st.overflow == 0 and st.sort_error == 0
+    sp = torch.cuda.current_stream().cuda_stream
+    n_prof = min(steps, 50)
+    stage_ev = [[ev.create() for _ in range(9)] for _ in range(n_prof)]
+    dfm_ev = [(ev.create(), ev.create()) for _ in range(n_prof)]
+    for k in range(n_prof):
+        ci, t = frames[k % nf]
+        ev.record(dfm_ev[k][0], sp)
+        g4d.deform(G, P, M, t, S)
+        ev.record(dfm_ev[k][1], sp)
+        g4d.set_stage_events(stage_ev[k])
+        g4d.render(S, cams[ci], ws, img)
+        g4d.set_stage_events(None)
+    torch.cuda.synchronize()
+    stages = {"deform": float(np.mean([ev.elapsed(a, b) for a, b in dfm_ev]))}
+    for i, name in enumerate(STAGES):
+        stages[name] = float(np.mean([ev.elapsed(e[i], e[i + 1]) for e in stage_ev]))
+    return {"gaussians": G.n, "width": W, "height": H, "frames": nf, "steps": steps,
+            "frames_per_s": round(steps / wall, 2), "ms_per_frame": round(1e3 * wall / steps, 4),
+            "stages_ms": {k: round(v, 4) for k, v in stages.items()}, "instances_max": kmax}
+
+
+def extra_measurements(steps, warmup):
+    """The large configuration (300k Gaussians, planes 64/128/256 x t150,
+    MLP 96-128-10, 1352x1014) with the FP32 and the BF16-input MFMA MLP, and
+    the 100k workload's generator swept over N at 800x800."""
+    from paper_2310_08528_amd import g4d, synth
+    out = {}
+    log("extra: large configuration")
+    sc4 = synth.config4()
+    out["large"] = {"workload": "300k Gaussians (box + cluster, SH3), HexPlane 64/128/256 x t150 F32, "
+                                "MLP 96-128-10, 1352x1014, 20 ring cameras x 300 timestamps",
+                    "fp32_mlp": time_scene(sc4, g4d.MLP_F32, steps, warmup, n_frames=300),
+                    "bf16_mlp": time_scene(sc4, g4d.MLP_BF16, steps, warmup, n_frames=300)}
+    del sc4
+    out["sweep_n"] = {}
+    for n in (10_000, 30_000, 100_000, 300_000):
+        log(f"extra: N = {n}")
+        out["sweep_n"][str(n)] = time_scene(synth.config2(n=n), g4d.MLP_F32, steps, warmup)
+    return out
+
+
 def blend_traffic():
     """HBM bytes per blend launch from the committed counter summary, or None
     when the blend kernel's source has changed since the counters were taken."""
@@ -186,6 +270,20 @@ def blend_traffic():
     return int(data["traffic_bytes_per_launch"])
 
 
+def rasterizer_traffic():
+    """HBM bytes of every rasterizer kernel of one frame, from the committed
+    counter summary, or None when the rasterizer source has changed."""
+    try:
+        md = open(os.path.join(ROOT, "profiles", "k_blend_traffic_100k_800x800.md")).read()
+        data = json.loads(md.split("```json", 1)[1].split("```", 1)[0])
+        src = open(os.path.join(ROOT, "paper_2310_08528_amd", "csrc", "raster.hip")).read()
+    except (OSError, ValueError, IndexError):
+        return None
+    if hashlib.sha256(src.encode()).hexdigest() != data.get("raster_source_sha256"):
+        return None
+    return int(data["rasterizer_bytes_per_frame"])
+
+
 def main():
     import faulthandler
     faulthandler.dump_traceback_later(90, repeat=True, file=sys.stderr)
@@ -199,6 +297,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (for scaling HBM byte counters)")
+    ap.add_argument("--extra", action="store_true",
+                    help="also time the large configuration (FP32 and BF16 MLP) and a sweep over N")
     ap.add_argument("--serve-seconds", type=float, default=20.0)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-slots", type=int, default=16)
@@ -328,6 +428,14 @@ def main():
                 "flop_per_eval": BLEND_FLOP_PER_EVAL, "avg_ms": round(blend_ms, 4),
                 "frac_of_published_fp32": round(achieved / PEAK_FP32_TFLOPS, 4)}
 
+    # the rasterizer as a whole (counter bytes over its live time per frame)
+    rbytes = rasterizer_traffic()
+    r_ms = sum(stages[k] for k in STAGES)
+    raster_hbm = {"bytes_per_frame": rbytes, "ms_per_frame": round(r_ms, 4),
+                  "achieved_GBs": round(rbytes / (r_ms * 1e-3) / 1e9, 1) if rbytes else None,
+                  "peak_GBs": PEAK_HBM_GBS,
+                  "frac": round(rbytes / (r_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4) if rbytes else None}
+
     out = {"metric": METRIC, "value": round(fps, 2), "unit": "frames/s", "n_gpus": 1, "steps": K,
            "warmup": args.warmup, "ms_per_step": round(1e3 * wall / K, 4), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
@@ -336,10 +444,12 @@ def main():
                       "gaussians": G.n, "width": W, "height": H, "instances_max": kmax,
                       "capacity": capacity},
            "stages_ms": {k: round(v, 4) for k, v in stages.items()},
-           "roofline": roofline}
+           "roofline": roofline, "rasterizer_hbm": raster_hbm}
     log("stages done")
     if not args.no_serve:
         out["serving"] = serving_bench(args.serve_seconds, args.serve_rate, args.serve_budget_gb, args.serve_slots)
+    if args.extra:
+        out["extra"] = extra_measurements(min(K, 200), 20)
     if not args.no_cpu_baseline:
         log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(sc, frames, args.cpu_frames)
