@@ -61,7 +61,7 @@ def _load():
     lib.orc_emit_instances.argtypes = [i32, P, P, i32, P, P]
     lib.orc_sort_instances.argtypes = [i64, P, P]
     lib.orc_tile_ranges.argtypes = [i64, P, i32, P]
-    lib.orc_blend.argtypes = [i32, i32, P, P, P, P, P, P, f64, P, P, P, P]
+    lib.orc_blend.argtypes = [i32, i32, P, P, P, P, P, P, f64, P, P, P, P, P]
     _lib = lib
     return lib
 
@@ -198,6 +198,7 @@ def blend(cam, ranges, vals, opacity, proj, margin: float = 1e-5):
     W, H = int(cam.width), int(cam.height)
     img = np.zeros((3, H, W)); T = np.zeros((H, W))
     nc = np.zeros((H, W), dtype=np.int32); fl = np.zeros((H, W), dtype=np.int32)
+    ev = np.zeros((H, W), dtype=np.int32)
     ranges = _c(ranges, np.int64)
     vals = _c(vals, np.uint32)
     if vals.size == 0:
@@ -205,8 +206,8 @@ def blend(cam, ranges, vals, opacity, proj, margin: float = 1e-5):
     opacity = _c(opacity, np.float32)
     bg = _c(cam.bg, np.float32)
     lib.orc_blend(W, H, _p(ranges), _p(vals), _p(opacity), _p(_c(proj.f32, np.float32)),
-                  _p(_c(proj.f64, np.float64)), _p(bg), float(margin), _p(img), _p(T), _p(nc), _p(fl))
-    return img, T, nc, fl
+                  _p(_c(proj.f64, np.float64)), _p(bg), float(margin), _p(img), _p(T), _p(nc), _p(fl), _p(ev))
+    return img, T, nc, fl, ev
 
 
 def render(s, cam, margin: float = 1e-5):
@@ -216,8 +217,8 @@ def render(s, cam, margin: float = 1e-5):
     tx, ty = tiles_xy(cam.width, cam.height)
     inst = instances(proj.rect, proj.depth_bits, tx)
     rng = tile_ranges(inst.keys, tx * ty)
-    img, T, nc, fl = blend(cam, rng, inst.vals, s.opacity, proj, margin)
-    return types.SimpleNamespace(image=img, final_T=T, n_contrib=nc, flag=fl, proj=proj,
+    img, T, nc, fl, ev = blend(cam, rng, inst.vals, s.opacity, proj, margin)
+    return types.SimpleNamespace(image=img, final_T=T, n_contrib=nc, flag=fl, evals=ev, proj=proj,
                                  K=inst.K, keys=inst.keys, vals=inst.vals, ranges=rng,
                                  tiles_x=tx, tiles_y=ty)
 

@@ -510,8 +510,10 @@ void orc_tile_ranges(int64_t k, const uint64_t *keys, int n_tiles, int64_t *rang
 /*   skip if power > 0; alpha = min(0.99, o exp(power));                */
 /*   skip if alpha < 1/255; stop (without adding) if T (1 - alpha) <    */
 /*   1e-4; otherwise colour += c alpha T and T *= (1 - alpha).           */
-/* Output colour + T * bg, the final T, and the number of list entries  */
-/* visited up to the last contributor.                                   */
+/* Output colour + T * bg, the final T, the number of list entries      */
+/* visited up to the last contributor, and (if evals is not null) the   */
+/* number of list entries the pixel evaluates: up to and including the  */
+/* entry that stops it, else the whole list.                             */
 /* Decisions are taken in binary32 (values f32 from orc_project); the   */
 /* colour and T are accumulated in FP64 from the FP64 values.  flag[p]  */
 /* counts binary32 decisions within `margin` (relative) of their        */
@@ -522,7 +524,7 @@ void orc_blend(int width, int height, const int64_t *ranges, const uint32_t *val
                const float *opacity, const float *f32v /* [n][8] */, const double *f64v /* [n][8] */,
                const float *bg, double margin,
                double *image /* [3][H][W] */, double *final_T /* [H][W] */,
-               int32_t *n_contrib /* [H][W] */, int32_t *flag /* [H][W] */)
+               int32_t *n_contrib /* [H][W] */, int32_t *flag /* [H][W] */, int32_t *evals /* [H][W] or NULL */)
 {
     const int tiles_x = (width + ORC_TILE - 1) / ORC_TILE;
     const float a_min = 1.0f / 255.0f;
@@ -536,6 +538,7 @@ void orc_blend(int width, int height, const int64_t *ranges, const uint32_t *val
             double T = 1.0, C[3] = {0.0, 0.0, 0.0};
             float T32 = 1.0f;
             int last = 0, fl = 0;
+            int ev = (int)(e - b);
             const float fpx = (float)px, fpy = (float)py;
             for (int64_t i = b; i < e; ++i) {
                 const uint32_t g = vals[i];
@@ -557,7 +560,10 @@ void orc_blend(int width, int height, const int64_t *ranges, const uint32_t *val
                 if (alpha32 < a_min) continue;
                 float test32 = T32 * (1.0f - alpha32);
                 if (fabsf(test32 - t_min) <= (float)(10.0 * margin) * t_min) ++fl;
-                if (test32 < t_min) break;
+                if (test32 < t_min) {
+                    ev = (int)(i - b) + 1;
+                    break;
+                }
                 /* FP64 values */
                 double ddx = v64[0] - (double)px, ddy = v64[1] - (double)py;
                 double power = -0.5 * (v64[2] * ddx * ddx + v64[4] * ddy * ddy) - v64[3] * ddx * ddy;
@@ -573,6 +579,7 @@ void orc_blend(int width, int height, const int64_t *ranges, const uint32_t *val
             final_T[pix] = T;
             n_contrib[pix] = last;
             flag[pix] = fl;
+            if (evals) evals[pix] = ev;
         }
     }
 }

@@ -31,7 +31,8 @@ def gpu_render(splats_host, cam, capacity=None, device="cuda:0", ws=None, want_i
     st = g4d.read_status(ws)
     out = types.SimpleNamespace(image=img.cpu().numpy(), final_T=T.cpu().numpy(), n_contrib=nc.cpu().numpy(),
                                 K=int(st.instances), overflow=int(st.overflow), sort_error=int(st.sort_error),
-                                visible=int(st.visible), tiles=int(st.tiles), ws=ws)
+                                visible=int(st.visible), tiles=int(st.tiles), blend_evals=int(st.blend_evals),
+                                ws=ws)
     if want_intermediates:
         K = min(out.K, ws.capacity)
         keys = torch.empty(max(K, 1), dtype=torch.int64, device=device)

@@ -62,6 +62,16 @@ def _check_render(s, cam, name, capacity=None, max_flag_frac=0.01):
     assert c.flagged <= max_flag_frac * c.pixels
     assert c.max_img <= IMG_TOL and c.max_T <= IMG_TOL
     assert c.nc_mismatch == 0
+    # the device's count of evaluated (pixel, list entry) pairs, which the
+    # benchmark's roofline uses: exact unless a flagged decision moves a stop
+    if c.flagged == 0:
+        assert gpu.blend_evals == int(orc.evals.sum()), (gpu.blend_evals, int(orc.evals.sum()))
+    else:
+        tiles_x = (cam.width + 15) // 16
+        py, px = np.nonzero(orc.flag)
+        t = (py // 16) * tiles_x + px // 16
+        slack = int((orc.ranges[t, 1] - orc.ranges[t, 0]).sum())
+        assert abs(gpu.blend_evals - int(orc.evals.sum())) <= slack
     return gpu, orc
 
 

@@ -407,6 +407,7 @@ def test_alpha_clamp_skip_and_early_stop_rules():
     # alpha below 1/255 is skipped
     r = oracle.render(splats([[0, 0, 4.0]], [[0.1] * 3], [[1, 0, 0, 0]], [0.003], colours=[[1, 1, 1]]), cam)
     assert r.image[0, 64, 64] == 0.0 and r.final_T[64, 64] == 1.0
+    assert r.evals[64, 64] == 1                         # no stop: the whole (one-entry) list
     # five stacked Gaussians with alpha 0.95: T = 0.05, 0.0025, 1.25e-4, and the
     # fourth would take T below 1e-4, so compositing stops after three
     s = splats([[0, 0, 2.0 + i] for i in range(5)], [[0.1] * 3] * 5, [[1, 0, 0, 0]] * 5, [0.95] * 5,
@@ -417,6 +418,7 @@ def test_alpha_clamp_skip_and_early_stop_rules():
     assert abs(r.image[0, 64, 64] - expect) < 1e-7
     assert abs(r.final_T[64, 64] - (1 - a) ** 3) < 1e-12
     assert r.n_contrib[64, 64] == 3
+    assert r.evals[64, 64] == 4                         # the fourth entry is evaluated and stops it
 
 
 def _brute_force(s, cam, proj, use_rect=True):
