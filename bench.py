@@ -106,13 +106,15 @@ def cpu_baseline(sc, frames, n_frames: int):
                       f"frame sequence; {dt:.1f} s on {cores} threads of {cpu_model()}"}
 
 
-def serving_bench(seconds: float, rate: float, budget_gb: float, slots: int, warm_s: float = 2.0):
+def serving_bench(seconds: float, rate: float, budget_gb: float, slots: int, warm_s: float = 2.0,
+                  sat_requests: int = 2000):
     """Poisson requests over three resident scenes (50k and 150k Gaussians
     from the cube generator, 300k from the box-and-cluster generator), each
     picking a scene, one of 20 ring cameras, t ~ U[0, 1] and a frame size
     from {400x400, 800x800, 1352x1014}.  Served with continuous batching,
     then the same trace through the plain path (one request at a time, no
-    batching, no graphs)."""
+    batching, no graphs).  Each path then takes the first `sat_requests`
+    requests of the trace back to back (closed loop) for its peak rate."""
     import torch
     from paper_2310_08528_amd import g4d, synth
     dev = "cuda:0"
@@ -152,6 +154,15 @@ def serving_bench(seconds: float, rate: float, budget_gb: float, slots: int, war
                 next_log += 5.0
         srv.drain()
         st = srv.stats()
+        # closed loop: the measured part of the trace submitted back to back
+        # (arrival times ignored), completions per second at saturation
+        srv.reset_stats()
+        sat = [(si, ci, t, r) for (ta, si, ci, t, r) in trace if ta >= warm_s][:sat_requests]
+        t0 = time.perf_counter()
+        for j, (si, ci, t, r) in enumerate(sat):
+            srv.submit(si, cams[si][res.index(tuple(r))][ci], t, outs[tuple(r)][j % 48])
+        srv.drain()
+        st["saturation_frames_per_s"] = len(sat) / (time.perf_counter() - t0)
         srv.close()
         return st
 
@@ -161,7 +172,7 @@ def serving_bench(seconds: float, rate: float, budget_gb: float, slots: int, war
     plain = run(1, False, False)
     log(f"plain: {plain}")
     keep = ("p50_ms", "p99_ms", "mean_ms", "max_ms", "frames_per_s", "completed", "rejected",
-            "batched_launches", "graph_replays", "overflow_retries")
+            "batched_launches", "graph_replays", "overflow_retries", "saturation_frames_per_s")
     return {"workload": f"Poisson {rate:.0f}/s for {seconds:.0f} s (+{warm_s:.0f} s warm-up), 3 resident scenes "
                         "(50k, 150k, 300k), frames 400x400 / 800x800 / 1352x1014",
             "served": {k: served[k] for k in keep}, "plain": {k: plain[k] for k in keep},
