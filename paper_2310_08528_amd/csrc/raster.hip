@@ -1056,7 +1056,7 @@ __global__ __launch_bounds__(kTilePixels) void k_blend(const uint2 *__restrict__
     const float x_hi = fminf(x_lo + 7.0f, (float)(width - 1));
     const float y_hi = fminf(y_lo + 7.0f, (float)(height - 1));
     float T = 1.0f, cr = 0.0f, cg = 0.0f, cbl = 0.0f;
-    bool done = !inside;
+    float live = inside ? 1.0f : 0.0f;   // 0 once the pixel stopped (or outside)
     int last = 0;
     int evals = inside ? end - start : 0;   // list entries this pixel evaluates
     const float a_min = 1.0f / 255.0f;
@@ -1083,7 +1083,7 @@ __global__ __launch_bounds__(kTilePixels) void k_blend(const uint2 *__restrict__
     }
     uint32_t g_next = load_gid(start + 64 + lane);
     for (int b0 = start; b0 < end; b0 += 64) {
-        if (__builtin_amdgcn_ballot_w64(!done) == 0) break;
+        if (__builtin_amdgcn_ballot_w64(live > 0.0f) == 0) break;
         const int i = b0 + lane;
         const float4 A4 = nA, B4 = nB;
         const float C1 = nC;
@@ -1133,24 +1133,28 @@ __global__ __launch_bounds__(kTilePixels) void k_blend(const uint2 *__restrict__
                 const float dx = R0.x - fpx, dy = R0.y - fpy;
                 // -(A dx^2 + C dy^2)/2 - B dx dy = dx (-A/2 dx - B dy) + (-C/2 dy) dy
                 const float power = __builtin_fmaf(dx, __builtin_fmaf(R0.z, dx, R1.x * dy), (R0.w * dy) * dy);
-                const float alpha = fminf(0.99f, __builtin_amdgcn_exp2f(__builtin_fmaf(power, 1.44269504f, R1.y)));
-                const float test = __builtin_fmaf(-alpha, T, T);   // T (1 - alpha), one rounding
-                const bool valid = !done & !(power > 0.0f) & !(alpha < a_min);
-                const bool stop = valid & (test < 0.0001f);
-                const bool add = valid ^ stop;
+                // skipped entries (power > 0, alpha < 1/255) get alpha 0, and so
+                // does every entry after the pixel stopped (live = 0): then
+                // T (1 - alpha) = T >= 1e-4, nothing stops, adds or moves
+                const float pw = power > 0.0f ? -INFINITY : power;
+                float alpha = fminf(0.99f, __builtin_amdgcn_exp2f(__builtin_fmaf(pw, 1.44269504f, R1.y)));
+                alpha = alpha < a_min ? 0.0f : alpha;
+                const float ae = alpha * live;
+                const float test = __builtin_fmaf(-ae, T, T);   // T (1 - alpha), one rounding
+                const bool stop = test < 0.0001f;
+                const int pos1 = __float_as_int(R2.y);
+                evals = stop ? pos1 : evals;
+                live = stop ? 0.0f : live;
                 // the weight alpha T is the drop in transmittance
-                const float Tn = add ? test : T;
+                const float Tn = stop ? T : test;
                 const float w = T - Tn;
                 cr = __builtin_fmaf(R1.z, w, cr);
                 cg = __builtin_fmaf(R1.w, w, cg);
                 cbl = __builtin_fmaf(R2.x, w, cbl);
+                last = w > 0.0f ? pos1 : last;
                 T = Tn;
-                const int pos1 = __float_as_int(R2.y);
-                last = add ? pos1 : last;
-                evals = stop ? pos1 : evals;
-                done = done | stop;
             }
-            if (__builtin_amdgcn_ballot_w64(!done) == 0) break;
+            if (__builtin_amdgcn_ballot_w64(live > 0.0f) == 0) break;
         }
         // the next step rewrites the slots: finish this step's reads first
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
