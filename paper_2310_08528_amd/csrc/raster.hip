@@ -1030,10 +1030,14 @@ __global__ __launch_bounds__(kTilePixels) void k_blend(const uint2 *__restrict__
                                                        unsigned long long *__restrict__ tile_evals, int passes,
                                                        int n) {
     constexpr int NW = kTilePixels / 64;   // waves = quadrants
-    // per wave: 64 record slots; blank records (log2 o = -inf, so alpha = 0)
-    // pad a step to a multiple of the unroll; a slot is three float4 =
-    // (u, v, -A/2, -C/2), (-B, log2 o, r, g), (b, list position + 1 as bits, -, -)
-    __shared__ float4 sR[NW][64 * 3];
+    // per wave: a queue of packed records.  Each step appends its kept
+    // entries, composites whole groups of kBlendUnroll and carries the rest
+    // (fewer than kBlendUnroll) to the front for the next step; the last step
+    // pads with blank records (log2 o = -inf, so alpha = 0).  A slot is three
+    // float4 = (u, v, -A/2, -C/2), (-B, log2 o, r, g), (b, list position + 1
+    // as bits, -, -).
+    constexpr int kQueue = 64 + kBlendUnroll;
+    __shared__ float4 sR[NW][kQueue * 3];
     const int b = (int)blockIdx.x;
     if (b >= n_tiles) return;
     const int tile = (int)order[b];   // block b blends tile order[b]: the longest lists start first
@@ -1082,6 +1086,7 @@ __global__ __launch_bounds__(kTilePixels) void k_blend(const uint2 *__restrict__
         nC = recC[g];
     }
     uint32_t g_next = load_gid(start + 64 + lane);
+    int queued = 0;   // records carried over from the previous step (< kBlendUnroll)
     for (int b0 = start; b0 < end; b0 += 64) {
         if (__builtin_amdgcn_ballot_w64(live > 0.0f) == 0) break;
         const int i = b0 + lane;
@@ -1104,22 +1109,25 @@ __global__ __launch_bounds__(kTilePixels) void k_blend(const uint2 *__restrict__
             keep = rect_may_reach(A4.x, A4.y, A, Bc, C, iA, iC, thr, x_lo, x_hi, y_lo, y_hi);
         }
         const uint64_t km = __builtin_amdgcn_ballot_w64(keep);
-        const int kept = (int)__popcll(km);
-        const int kept4 = (kept + kBlendUnroll - 1) & ~(kBlendUnroll - 1);
-        if (kept == 0) continue;
-        // pack the kept entries in list order; blank records pad to a multiple
-        // of the unroll
+        const int total = queued + (int)__popcll(km);
+        const bool last_step = b0 + 64 >= end;
+        // whole groups now; at the end of the list, everything (padded)
+        const int kept4 = last_step ? (total + kBlendUnroll - 1) & ~(kBlendUnroll - 1)
+                                    : total & ~(kBlendUnroll - 1);
+        // append the kept entries in list order behind the carried ones
         if (keep) {
-            const int slot = (int)__popcll(km & lt);
+            const int slot = queued + (int)__popcll(km & lt);
             R[3 * slot] = A4;
             R[3 * slot + 1] = make_float4(B4.x, __log2f(B4.y), B4.z, B4.w);
             R[3 * slot + 2] = make_float4(C1, __int_as_float(i - start + 1), 0.0f, 0.0f);
         }
-        if (lane >= kept && lane < kept4) {
-            R[3 * lane] = zero4;
-            R[3 * lane + 1] = blank1;
-            R[3 * lane + 2] = zero4;
+        if (lane < kept4 - total) {
+            R[3 * (total + lane)] = zero4;
+            R[3 * (total + lane) + 1] = blank1;
+            R[3 * (total + lane) + 2] = zero4;
         }
+        queued = total - kept4;   // 0 at the last step
+        if (kept4 == 0) continue;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -1155,6 +1163,15 @@ __global__ __launch_bounds__(kTilePixels) void k_blend(const uint2 *__restrict__
                 T = Tn;
             }
             if (__builtin_amdgcn_ballot_w64(live > 0.0f) == 0) break;
+        }
+        // carry the remainder to the front (kept4 >= kBlendUnroll > queued, so
+        // the source and destination slots never overlap)
+        if (lane < queued) {
+            const float4 c0 = R[3 * (kept4 + lane)], c1 = R[3 * (kept4 + lane) + 1];
+            const float4 c2 = R[3 * (kept4 + lane) + 2];
+            R[3 * lane] = c0;
+            R[3 * lane + 1] = c1;
+            R[3 * lane + 2] = c2;
         }
         // the next step rewrites the slots: finish this step's reads first
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
