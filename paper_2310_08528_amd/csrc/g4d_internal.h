@@ -66,7 +66,7 @@ struct WsLayout {
     size_t cam;
     size_t recA, recB, recC, rect, touched, dgid, dk0, dk1, dv0, dv1, offsets, tk0, tk1, tv0, tv1;
     size_t tcnt, tdtot;  // instance sort: per-pass digit counts [256][nblk_k] and digit totals [256]
-    size_t order;        // blend order of the tiles (longest list first)
+    size_t order;        // blend order of the tiles (longest list first): (tile, start, end, 0)
     size_t evals;        // per tile: (pixel, Gaussian) pairs the blend evaluated (u64)
     size_t total;
 };
@@ -108,7 +108,7 @@ inline bool make_layout(int32_t n, int32_t w, int32_t h, int64_t cap, WsLayout *
     L->tv1 = take((size_t)cap * 4);
     L->tcnt = take((size_t)2 * 256 * L->nblk_k * 4);
     L->tdtot = take((size_t)2 * 256 * 4);
-    L->order = take((size_t)L->tiles_max * 4);
+    L->order = take((size_t)L->tiles_max * 16);
     L->evals = take((size_t)L->tiles_max * 8);
     L->total = o;
     return true;

@@ -687,7 +687,11 @@ __device__ __forceinline__ void emit_wave(int n, const uint32_t *__restrict__ or
             const bool live = o < bend;
             uint32_t t = 0xffffffffu;
             if (live) {
-                const int ry = r / ww;
+                // r / ww by a float reciprocal, corrected to the exact quotient
+                // (r < 2^16 and ww <= 256 tiles: the estimate is within one)
+                int ry = (int)((float)r * __builtin_amdgcn_rcpf((float)ww));
+                ry += (ry + 1) * ww <= r;
+                ry -= ry * ww > r;
                 t = (uint32_t)((oy + ry) * tiles_x + ox + (r - ry * ww));
                 if (pack_bits) {
                     tkeys[o] = (t << pack_bits) | og;
@@ -955,8 +959,9 @@ __global__ __launch_bounds__(256) void k_ranges(const DevStatus *__restrict__ st
 // depend on it).  Blocks are dispatched in index order and spread round-robin
 // over the XCDs, so the longest tiles start first and land on different XCDs.
 
+// order[k] = (tile, start, end, 0): the blend reads its tile's range with its id.
 __global__ __launch_bounds__(1024) void k_tile_order(const uint2 *__restrict__ ranges, int n_tiles,
-                                                     uint32_t *__restrict__ order) {
+                                                     uint4 *__restrict__ order) {
     __shared__ uint32_t hist[33];
     const int tid = threadIdx.x;
     if (tid < 33) hist[tid] = 0;
@@ -973,7 +978,10 @@ __global__ __launch_bounds__(1024) void k_tile_order(const uint2 *__restrict__ r
         }
     }
     __syncthreads();
-    for (int t = tid; t < n_tiles; t += 1024) order[atomicAdd(&hist[cls(ranges[t])], 1u)] = (uint32_t)t;
+    for (int t = tid; t < n_tiles; t += 1024) {
+        const uint2 r = ranges[t];
+        order[atomicAdd(&hist[cls(r)], 1u)] = make_uint4((uint32_t)t, r.x, r.y, 0u);
+    }
 }
 
 // ---------------------------------------------------------------- k_blend
@@ -1019,8 +1027,7 @@ __device__ __forceinline__ bool rect_may_reach(float u, float v, float A, float 
 
 constexpr int kBlendUnroll = 8;   // entries composited per step of the loop (power of two, <= 64)
 
-__global__ __launch_bounds__(kTilePixels) void k_blend(const uint2 *__restrict__ ranges,
-                                                       const uint32_t *__restrict__ order,
+__global__ __launch_bounds__(kTilePixels) void k_blend(const uint4 *__restrict__ order,
                                                        const uint32_t *__restrict__ gids, uint32_t gmask,
                                                        const float4 *__restrict__ recA,
                                                        const float4 *__restrict__ recB,
@@ -1040,7 +1047,8 @@ __global__ __launch_bounds__(kTilePixels) void k_blend(const uint2 *__restrict__
     __shared__ float4 sR[NW][kQueue * 3];
     const int b = (int)blockIdx.x;
     if (b >= n_tiles) return;
-    const int tile = (int)order[b];   // block b blends tile order[b]: the longest lists start first
+    const uint4 ord = order[b];   // block b blends tile order[b]: the longest lists start first
+    const int tile = (int)ord.x;
     const int tx = tile % tiles_x, ty = tile / tiles_x;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     if (b == 0 && tid == 0) {
@@ -1052,8 +1060,7 @@ __global__ __launch_bounds__(kTilePixels) void k_blend(const uint2 *__restrict__
     const int px = qx0 + (lane & 7), py = qy0 + (lane >> 3);
     const bool inside = px < width && py < height;
     const size_t pix = inside ? (size_t)py * width + px : 0;
-    const uint2 rg = ranges[tile];
-    const int start = (int)rg.x, end = (int)rg.y;
+    const int start = (int)ord.y, end = (int)ord.z;
     const float fpx = (float)px, fpy = (float)py;
     // this quadrant's rectangle of pixel centres, clipped to the image
     const float x_lo = (float)qx0, y_lo = (float)qy0;
@@ -1340,7 +1347,7 @@ g4d_status render(const g4d_splats *G, const g4d_camera *C, const g4d_workspace 
         hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, s, reinterpret_cast<uint4 *>(ws->ptr), n16, cam, camd);
     }
     mark(1);
-    uint32_t *order = at<uint32_t>(ws, L.order);
+    uint4 *order = at<uint4>(ws, L.order);
     if (n > 0) {
         const int nb_n = (n + 1023) / 1024;
         // 1. preprocess
@@ -1408,7 +1415,7 @@ g4d_status render(const g4d_splats *G, const g4d_camera *C, const g4d_workspace 
     hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, s, ranges, tiles, order);
     mark(7);
     // 7. blend (with n == 0 every range is empty and the image is the background)
-    hipLaunchKernelGGL(k_blend, dim3(tiles), dim3(kTilePixels), 0, s, ranges, order, packed ? tk[0] : tv[0],
+    hipLaunchKernelGGL(k_blend, dim3(tiles), dim3(kTilePixels), 0, s, order, packed ? tk[0] : tv[0],
                        packed ? (1u << gbits) - 1u : 0xffffffffu, recA, recB, recC, C->width,
                        C->height, cam.tiles_x, tiles, camd, st, at<unsigned long long>(ws, L.evals),
                        plan.passes, std::max(n, 1));
