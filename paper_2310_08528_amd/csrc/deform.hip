@@ -44,6 +44,7 @@ namespace {
 
 constexpr int kGB = 64;        // Gaussians per block
 constexpr int kThreads = 256;
+static_assert(kGB == 64 && kThreads >= 3 * 64, "Eq. 8 phase: one Gaussian per lane, one wave per output group");
 
 typedef float float4_t __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
@@ -117,6 +118,24 @@ __global__ __launch_bounds__(kThreads) void k_deform(DeformBatch batch) {
     const int n = job.n;
     const int tid = threadIdx.x;
     const bool features_only = job.out_features != nullptr;
+    // inputs of Eq. 8 for this block's Gaussians, loaded now so that their
+    // latency hides behind the encoder: wave 0 means + opacity logit, wave 1
+    // quaternion, wave 2 log-scales (lane = Gaussian)
+    const int wave_d = tid >> 6, lane_g = tid & 63, dg = g0 + lane_g;
+    float pin[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (!features_only && dg < n) {
+        if (wave_d == 0) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) pin[k] = job.means[(size_t)k * n + dg];
+            pin[3] = job.opac[dg];
+        } else if (wave_d == 1) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) pin[k] = job.quats[(size_t)k * n + dg];
+        } else if (wave_d == 2) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) pin[k] = job.log_scales[(size_t)k * n + dg];
+        }
+    }
 
     // ---- decoder weights (rows of W1; heads padded to 16 rows): the loads
     // are issued here and stay in flight through the encoder's gathers; the
@@ -310,34 +329,34 @@ __global__ __launch_bounds__(kThreads) void k_deform(DeformBatch batch) {
     for (int i = 0; i < 4; ++i) s_delta[(row0 + 4 * lk + i) * 17 + lrow] = acc2[i] + s_b2[lrow];
     __syncthreads();
 
-    // ---- D. Eq. 8 + activations
-    if (tid < kGB) {
-        const int g = g0 + tid;
-        if (g < n) {
-            const float *d = s_delta + tid * 17;
+    // ---- D. Eq. 8 + activations: wave 0 the means and opacity, wave 1 the
+    // rotation, wave 2 the scales (inputs were loaded at the start)
+    if (dg < n) {
+        const float *d = s_delta + lane_g * 17;
+        if (wave_d == 0) {
 #pragma unroll
-            for (int k = 0; k < 3; ++k)
-                job.out_means[(size_t)k * n + g] = job.means[(size_t)k * n + g] + d[k];
+            for (int k = 0; k < 3; ++k) job.out_means[(size_t)k * n + dg] = pin[k] + d[k];
+            job.out_opac[dg] = 1.0f / (1.0f + expf(-pin[3]));
+        } else if (wave_d == 1) {
             float q[4];
             float qn = 0.0f;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                q[k] = job.quats[(size_t)k * n + g] + d[3 + k];
+                q[k] = pin[k] + d[3 + k];
                 qn += q[k] * q[k];
             }
             if (qn > 0.0f) {
                 const float inv = 1.0f / sqrtf(qn);
 #pragma unroll
-                for (int k = 0; k < 4; ++k) job.out_quats[(size_t)k * n + g] = q[k] * inv;
+                for (int k = 0; k < 4; ++k) job.out_quats[(size_t)k * n + dg] = q[k] * inv;
             } else {
-                job.out_quats[g] = 1.0f;
+                job.out_quats[dg] = 1.0f;
 #pragma unroll
-                for (int k = 1; k < 4; ++k) job.out_quats[(size_t)k * n + g] = 0.0f;
+                for (int k = 1; k < 4; ++k) job.out_quats[(size_t)k * n + dg] = 0.0f;
             }
+        } else if (wave_d == 2) {
 #pragma unroll
-            for (int k = 0; k < 3; ++k)
-                job.out_scales[(size_t)k * n + g] = expf(job.log_scales[(size_t)k * n + g] + d[7 + k]);
-            job.out_opac[g] = 1.0f / (1.0f + expf(-job.opac[g]));
+            for (int k = 0; k < 3; ++k) job.out_scales[(size_t)k * n + dg] = expf(pin[k] + d[7 + k]);
         }
     }
 }
