@@ -86,7 +86,9 @@ struct Smem {
     static constexpr size_t w2_bytes = (size_t)16 * W2_LD * sizeof(E);
     static constexpr size_t delta_bytes = (size_t)kGB * 17 * sizeof(float);
     static constexpr size_t bias_bytes = (size_t)(HID + 16) * sizeof(float);
-    static constexpr size_t total = act_bytes + w1_bytes + w2_bytes + delta_bytes + bias_bytes;
+    // W1 is dead once h is computed: the heads' weights and the deltas reuse its space
+    static constexpr size_t wreg_bytes = w1_bytes > w2_bytes + delta_bytes ? w1_bytes : w2_bytes + delta_bytes;
+    static constexpr size_t total = act_bytes + wreg_bytes + bias_bytes;
 };
 
 template <int F, int L, int HID, bool BF16>
@@ -98,9 +100,9 @@ __global__ __launch_bounds__(kThreads) void k_deform(DeformBatch batch) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     E *s_act = reinterpret_cast<E *>(smem);
     E *s_w1 = reinterpret_cast<E *>(smem + S::act_bytes);
-    E *s_w2 = reinterpret_cast<E *>(smem + S::act_bytes + S::w1_bytes);
-    float *s_delta = reinterpret_cast<float *>(smem + S::act_bytes + S::w1_bytes + S::w2_bytes);
-    float *s_b1 = s_delta + kGB * 17;
+    E *s_w2 = reinterpret_cast<E *>(smem + S::act_bytes);                                  // after phase B
+    float *s_delta = reinterpret_cast<float *>(smem + S::act_bytes + S::w2_bytes);          // after phase C
+    float *s_b1 = reinterpret_cast<float *>(smem + S::act_bytes + S::wreg_bytes);
     float *s_b2 = s_b1 + HID;
 
     // Block b runs on XCD b % 8; each XCD takes a contiguous run of the
@@ -232,15 +234,6 @@ __global__ __launch_bounds__(kThreads) void k_deform(DeformBatch batch) {
                 else s_w1[r * S::W1_LD + c] = v1[q];
             }
         }
-#pragma unroll
-        for (int q = 0; q < N2; ++q) {
-            const int i = tid + q * kThreads;
-            if (i < 16 * HID) {
-                const int r = i / HID, c = i - r * HID;
-                if constexpr (BF16) s_w2[r * S::W2_LD + c] = f32_to_bf16_rne(v2[q]);
-                else s_w2[r * S::W2_LD + c] = v2[q];
-            }
-        }
         if (tid < HID) s_b1[tid] = vb1;
         if (tid < 16) s_b2[tid] = vb2;
     }
@@ -288,7 +281,16 @@ __global__ __launch_bounds__(kThreads) void k_deform(DeformBatch batch) {
             }
         }
     }
-    __syncthreads();   // all waves done reading f_h before h overwrites it
+    __syncthreads();   // all waves done reading f_h and W1 before h and W2 overwrite them
+#pragma unroll
+    for (int q = 0; q < N2; ++q) {
+        const int i = tid + q * kThreads;
+        if (i < 16 * HID) {
+            const int r = i / HID, c = i - r * HID;
+            if constexpr (BF16) s_w2[r * S::W2_LD + c] = f32_to_bf16_rne(v2[q]);
+            else s_w2[r * S::W2_LD + c] = v2[q];
+        }
+    }
     // bias + ReLU; lane holds rows row0 + 4*lk + i of column c*16 + lrow
 #pragma unroll
     for (int c = 0; c < HID / 16; ++c) {
