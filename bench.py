@@ -322,7 +322,7 @@ def main():
                     help="also time the large configuration (FP32 and BF16 MLP) and a sweep over N")
     ap.add_argument("--serve-seconds", type=float, default=20.0)
     ap.add_argument("--serve-rate", type=float, default=200.0)
-    ap.add_argument("--serve-slots", type=int, default=16)
+    ap.add_argument("--serve-slots", type=int, default=3)
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
