@@ -433,8 +433,10 @@ def main():
         slot_S.append(ctypes.byref(s_))
         slot_W.append(ctypes.byref(W_.ws))
         slot_I.append(I_.data_ptr())
-    slot_streams = [torch.cuda.Stream() for _ in range(m_max)]   # default priority
-    slot_sp = [x.cuda_stream for x in slot_streams]
+    # slot 0 runs on the current stream, so m slots use m streams (a process
+    # has four hardware queues); the others get streams of their own
+    slot_streams = [torch.cuda.Stream() for _ in range(m_max - 1)]   # default priority
+    slot_sp = [sp] + [x.cuda_stream for x in slot_streams]
 
     def in_flight(m, n_frames, k0):
         for k in range(n_frames):
