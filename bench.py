@@ -201,7 +201,7 @@ def time_scene(sc, precision, steps, warmup, n_frames=None):
     G = g4d.DeviceGaussians(sc.gaussians, dev)
     P = g4d.DevicePlanes(sc.planes, dev)
     M = g4d.DeviceMLP(sc.mlp, dev, precision)
-    S = g4d.DeviceSplats(G.n, G.sh_degree, G.sh, dev)
+    S = g4d.DeviceSplats(G.n, G.sh_degree, None if M.has_colour else G.sh, dev)
     cams = [g4d.camera_struct(c) for c in sc.cameras]
     W, H = sc.cameras[0].width, sc.cameras[0].height
     img = torch.empty((3, H, W), dtype=torch.float32, device=dev)
@@ -265,6 +265,11 @@ def extra_measurements(steps, warmup):
                     "fp32_mlp": time_scene(sc4, g4d.MLP_F32, steps, warmup, n_frames=300),
                     "bf16_mlp": time_scene(sc4, g4d.MLP_BF16, steps, warmup, n_frames=300)}
     del sc4
+    log("extra: colour and opacity heads")
+    out["colour_opacity_heads"] = {
+        "workload": "100k Gaussians, SH3, the 100k configuration's field; decoder with the colour "
+                    "(48 rows) and opacity heads, 800x800",
+        "fp32_mlp": time_scene(synth.config2(colour_opacity=True), g4d.MLP_F32, steps, warmup)}
     out["sweep_n"] = {}
     for n in (10_000, 30_000, 100_000, 300_000):
         log(f"extra: N = {n}")

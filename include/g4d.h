@@ -62,7 +62,7 @@ typedef struct {
     const float *log_scales;    /* [3][n] */
     const float *quats;         /* [4][n], (w, x, y, z), need not be unit */
     const float *opacity_logits;/* [n] */
-    const float *sh;            /* [(d+1)^2][3][n]; not read by g4d_deform */
+    const float *sh;            /* [(d+1)^2][3][n]; read by g4d_deform only with a colour head */
 } g4d_gaussians;
 
 /* Multi-resolution HexPlane R_l(i, j) (Sec. 4.2, Eq. 7).  For each scale l
@@ -90,7 +90,17 @@ typedef enum { G4D_MLP_F32 = 0, G4D_MLP_BF16 = 1 } g4d_mlp_precision;
  * (4), ds = Ws h + bs (3).  Row-major float32 weights.  precision
  * G4D_MLP_BF16 rounds f_h, the weights and h to bfloat16 for the matrix
  * products (FP32 accumulation, FP32 biases).  Supported hidden: 32, 64,
- * 128. */
+ * 128.
+ *
+ * Optional heads of the appendix's colour and opacity deformation (both
+ * null, the default, for the method of Sec. 4.2): dC = Wc h + bc, one row
+ * per SH coefficient in the [(d+1)^2][3] order of the colour array (so
+ * 3 (d+1)^2 rows for the scene's SH degree d), added to the canonical
+ * coefficients; dalpha = Wa h + ba (1 row), added to the opacity logit
+ * before the sigmoid.  With more than 16 head rows in total (dX dr ds dC
+ * dalpha: a colour head at SH degree >= 1) only G4D_MLP_F32 is supported
+ * (G4D_EUNSUPPORTED otherwise).  A weight and its bias are given or null
+ * together (G4D_EINVAL otherwise). */
 typedef struct {
     int32_t in_dim;             /* must equal feat * n_scales */
     int32_t hidden;
@@ -99,11 +109,14 @@ typedef struct {
     const float *wx, *bx;       /* [3][hidden], [3] */
     const float *wr, *br;       /* [4][hidden], [4] */
     const float *ws, *bs;       /* [3][hidden], [3] */
+    const float *wc, *bc;       /* [3 (d+1)^2][hidden], [3 (d+1)^2], or NULL */
+    const float *wa, *ba;       /* [1][hidden], [1], or NULL */
 } g4d_mlp;
 
 /* Render-ready Gaussians G' (the set after Eq. 8 and activation): linear
  * scales, unit quaternions, opacity in (0, 1).  g4d_deform writes means,
- * scales, quats and opacity; g4d_render only reads. */
+ * scales, quats and opacity, and sh when the decoder has a colour head;
+ * g4d_render only reads. */
 typedef struct {
     int32_t n;
     int32_t sh_degree;          /* 0..3 */
@@ -111,7 +124,7 @@ typedef struct {
     float *scales;              /* [3][n] */
     float *quats;               /* [4][n] (w, x, y, z), unit */
     float *opacity;             /* [n] */
-    const float *sh;            /* [(d+1)^2][3][n] */
+    float *sh;                  /* [(d+1)^2][3][n] */
 } g4d_splats;
 
 /* Pinhole view M = [R, T] (Sec. 4.1).  Camera axes: x right, y down,
@@ -157,9 +170,11 @@ typedef struct {
 /* Eq. 7 + Eq. 8 + activations for G->n Gaussians at time t in [0, 1].
  * Writes out->means (X + dX), out->scales (exp(log_s + ds)), out->quats
  * (normalise(r + dr), identity if the sum is zero) and out->opacity
- * (sigmoid(logit)); out->n must equal G->n.  out->sh and out->sh_degree are
- * not touched (callers point out->sh at G->sh).  The output buffers must
- * not alias the inputs. */
+ * (sigmoid(logit [+ dalpha])); out->n must equal G->n.  Without a colour
+ * head out->sh and out->sh_degree are not touched (callers point out->sh at
+ * G->sh); with one, out->sh_degree must equal G->sh_degree and out->sh
+ * (a buffer of its own, not G->sh) receives G->sh + dC.  The output buffers
+ * must not alias the inputs. */
 g4d_status g4d_deform(const g4d_gaussians *G, const g4d_planes *P, const g4d_mlp *M, float t,
                       g4d_splats *out, void *stream);
 
@@ -175,7 +190,8 @@ typedef struct {
 #define G4D_MAX_BATCH_JOBS 8
 
 /* Several g4d_deform calls in one kernel launch (continuous batching).  All
- * jobs must share feat, n_scales, hidden and precision; each thread block
+ * jobs must share feat, n_scales, hidden, precision and the head-tile count
+ * (one 16-row tile of head rows, or four); each thread block
  * works on Gaussians of a single job, so every job's output is bitwise the
  * same as a lone g4d_deform call.  1 <= n_jobs <= G4D_MAX_BATCH_JOBS. */
 g4d_status g4d_deform_batched(const g4d_deform_job *jobs, int32_t n_jobs, void *stream);

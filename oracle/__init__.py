@@ -52,7 +52,8 @@ def _load():
     i32, i64, f64 = ctypes.c_int, ctypes.c_int64, ctypes.c_double
     lib.orc_bilinear.argtypes = [P, i32, i32, i32, f64, f64, P]
     lib.orc_deform.argtypes = [i32, P, P, P, P, i32, i32, P, P, P, P, i32, i32,
-                               P, P, P, P, P, P, P, P, f64, i32, P, P, P, P, P, P]
+                               P, P, P, P, P, P, P, P, f64, i32, P, P, P, P, P, P,
+                               i32, P, P, P, P, P, P]
     lib.orc_sh_basis.argtypes = [i32, i32, f64, f64, f64]
     lib.orc_sh_basis.restype = f64
     lib.orc_project.argtypes = [i32, i32, P, P, P, P, P, P, P, i32, i32, P, P, P, P, P]
@@ -107,7 +108,10 @@ def deform(g, planes, mlp, t: float, bf16_emulate: bool = False, want_features: 
 
     Returns a namespace with FP64 means [3][n], scales [3][n] (linear),
     quats [4][n] (unit), opacity [n] (sigmoid), and optionally f_h [n][in]
-    and the raw deltas [n][10] (dx 3, dr 4, ds 3)."""
+    and the raw deltas [n][10] (dx 3, dr 4, ds 3).  With the appendix's
+    colour head (mlp.wc) ``sh`` is the FP64 C + dC [3 (d+1)^2][n], else
+    None; with the opacity head (mlp.wa) the opacity is sigmoid(logit +
+    dalpha)."""
     lib = _load()
     n = g.n
     L, F = planes.n_scales, planes.feat
@@ -121,12 +125,22 @@ def deform(g, planes, mlp, t: float, bf16_emulate: bool = False, want_features: 
     om = np.zeros((3, n)); osc = np.zeros((3, n)); oq = np.zeros((4, n)); oo = np.zeros(n)
     fh = np.zeros((n, mlp.in_dim)) if want_features else None
     dl = np.zeros((n, 10)) if want_features else None
+    wc, wa = getattr(mlp, "wc", None), getattr(mlp, "wa", None)
+    n_sh = 3 * (g.sh_degree + 1) ** 2 if wc is not None else 0
+    if wc is not None:
+        assert np.asarray(wc).shape == (n_sh, mlp.hidden)
+    wc, bc = (_c(wc, np.float32), _c(mlp.bc, np.float32)) if wc is not None else (None, None)
+    wa, ba = (_c(wa, np.float32), _c(mlp.ba, np.float32)) if wa is not None else (None, None)
+    sh_in = _c(g.sh, np.float32).reshape(-1) if n_sh else None
+    osh = np.zeros((n_sh, n)) if n_sh else None
+    heads = [n_sh] + [_p(x) if x is not None else None for x in (wc, bc, wa, ba, sh_in, osh)]
     lib.orc_deform(n, _p(means), _p(ls), _p(qs), _p(ol), L, F, _p(bmin), _p(bmax), _p(res),
                    ctypes.cast(parr, ctypes.c_void_p), mlp.in_dim, mlp.hidden,
                    *[_p(w) for w in ws], float(t), int(bool(bf16_emulate)),
                    _p(om), _p(osc), _p(oq), _p(oo),
-                   _p(fh) if fh is not None else None, _p(dl) if dl is not None else None)
-    return types.SimpleNamespace(means=om, scales=osc, quats=oq, opacity=oo, features=fh, delta=dl)
+                   _p(fh) if fh is not None else None, _p(dl) if dl is not None else None, *heads)
+    return types.SimpleNamespace(means=om, scales=osc, quats=oq, opacity=oo, features=fh, delta=dl,
+                                 sh=None if osh is None else osh.reshape(np.shape(g.sh)))
 
 
 def to_splats32(d, sh: np.ndarray, sh_degree: int):
@@ -225,5 +239,5 @@ def render(s, cam, margin: float = 1e-5):
 
 def deform_render(g, planes, mlp, t, cam, margin: float = 1e-5):
     d = deform(g, planes, mlp, t)
-    s = to_splats32(d, g.sh, g.sh_degree)
+    s = to_splats32(d, g.sh if d.sh is None else d.sh, g.sh_degree)
     return s, render(s, cam, margin)

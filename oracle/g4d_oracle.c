@@ -107,6 +107,11 @@ static double to_bf16(double x)
 /* norm -> identity); opacity = sigmoid(logit).                         */
 /* bf16_emulate != 0 rounds f_h, W1, h and the head weights to bf16      */
 /* before the FP64 products (biases stay binary32).                     */
+/* Appendix (colour and opacity deformation), optional: with wc, the    */
+/* colour head dC = Wc h + bc gives one offset per SH coefficient       */
+/* (n_sh = 3 (d+1)^2 rows, in the order of the colour array) and        */
+/* out_sh = sh_in + dC; with wa, dalpha = Wa h + ba shifts the opacity  */
+/* logit: opacity = sigmoid(logit + dalpha).                            */
 /* ------------------------------------------------------------------ */
 void orc_deform(int n, const float *means, const float *log_scales, const float *quats,
                 const float *opacity_logits,
@@ -116,7 +121,10 @@ void orc_deform(int n, const float *means, const float *log_scales, const float 
                 const float *wx, const float *bx, const float *wr, const float *br,
                 const float *ws, const float *bs, double t, int bf16_emulate,
                 double *out_means, double *out_scales, double *out_quats, double *out_opacity,
-                double *out_fh /* nullable [n][in_dim] */, double *out_delta /* nullable [n][10] */)
+                double *out_fh /* nullable [n][in_dim] */, double *out_delta /* nullable [n][10] */,
+                int n_sh, const float *wc /* nullable [n_sh][hidden] */, const float *bc,
+                const float *wa /* nullable [1][hidden] */, const float *ba,
+                const float *sh_in /* [n_sh][n], read with wc */, double *out_sh /* [n_sh][n] */)
 {
     static const int axes[6][2] = {{0, 1}, {0, 2}, {1, 2}, {0, 3}, {1, 3}, {2, 3}};
     const float *heads_w[3] = {wx, wr, ws};
@@ -176,6 +184,29 @@ void orc_deform(int n, const float *means, const float *log_scales, const float 
         if (out_delta)
             for (int i = 0; i < 10; ++i) out_delta[(size_t)g * 10 + i] = delta[i];
 
+        /* appendix heads: phi_C and phi_alpha on the same h */
+        double dalpha = 0.0;
+        if (wa) {
+            double acc = 0.0;
+            for (int j = 0; j < hidden; ++j) {
+                double wv = (double)wa[j], hv = hbuf[j];
+                if (bf16_emulate) { wv = to_bf16(wv); hv = to_bf16(hv); }
+                acc += wv * hv;
+            }
+            dalpha = acc + (double)ba[0];
+        }
+        if (wc) {
+            for (int r = 0; r < n_sh; ++r) {
+                double acc = 0.0;
+                for (int j = 0; j < hidden; ++j) {
+                    double wv = (double)wc[(size_t)r * hidden + j], hv = hbuf[j];
+                    if (bf16_emulate) { wv = to_bf16(wv); hv = to_bf16(hv); }
+                    acc += wv * hv;
+                }
+                out_sh[(size_t)r * n + g] = (double)sh_in[(size_t)r * n + g] + acc + (double)bc[r];
+            }
+        }
+
         /* Eq. 8 and activations */
         for (int k = 0; k < 3; ++k)
             out_means[(size_t)k * n + g] = (double)means[(size_t)k * n + g] + delta[k];
@@ -189,7 +220,7 @@ void orc_deform(int n, const float *means, const float *log_scales, const float 
             out_quats[(size_t)k * n + g] = qn > 0.0 ? q[k] / qn : (k == 0 ? 1.0 : 0.0);
         for (int k = 0; k < 3; ++k)
             out_scales[(size_t)k * n + g] = exp((double)log_scales[(size_t)k * n + g] + delta[7 + k]);
-        out_opacity[g] = 1.0 / (1.0 + exp(-(double)opacity_logits[g]));
+        out_opacity[g] = 1.0 / (1.0 + exp(-((double)opacity_logits[g] + dalpha)));
     }
 }
 

@@ -10,10 +10,12 @@
 //   B. Feature merger h = ReLU(W1 f_h + b1) as a [64 x in] x [in x hidden]
 //      product on MFMA (v_mfma_f32_16x16x4_f32, or 16x16x32 bf16 with FP32
 //      accumulation in the bf16 mode); each wave owns 16 Gaussians.
-//   C. The three heads, concatenated into one [hidden x 16] matrix (rows
-//      dx 0-2, dr 3-6, ds 7-9, zero padding) on MFMA.
+//   C. The heads, concatenated into one [hidden x 16 NT] matrix (rows dx 0-2,
+//      dr 3-6, ds 7-9; with the colour and opacity heads of the appendix,
+//      dC 10 .. 10 + 3 (d+1)^2 - 1 and dalpha next; zero padding) on MFMA.
 //   D. Eq. 8 and activations: X + dX, exp(log s + ds), normalise(r + dr),
-//      sigmoid(opacity logit); structure-of-arrays stores.
+//      sigmoid(opacity logit [+ dalpha]), SH coefficients C [+ dC];
+//      structure-of-arrays stores.
 // A launch carries up to G4D_MAX_BATCH_JOBS jobs (continuous batching); a
 // block never mixes jobs, so a job's result does not depend on its batch.
 #include "g4d_internal.h"
@@ -24,7 +26,11 @@ struct DeformJob {
     const float *means, *log_scales, *quats, *opac;
     const float *planes[G4D_MAX_SCALES * 6];
     const float *w1, *b1, *wx, *bx, *wr, *br, *ws, *bs;
+    const float *wc, *bc, *wa, *ba;      // colour / opacity heads (null when absent)
+    const float *sh_in;                  // canonical SH coefficients (colour head only)
     float *out_means, *out_scales, *out_quats, *out_opac;
+    float *out_sh;                       // C + dC (colour head only)
+    int n_sh;                            // 3 (d+1)^2 colour rows, 0 without a colour head
     float *out_features;                 // non-null: write f_h and stop after phase A
     int res[G4D_MAX_SCALES][4];
     float gscale[G4D_MAX_SCALES][4];     // (res - 1) / (bmax - bmin) per axis; res_t - 1 for t
@@ -44,7 +50,7 @@ namespace {
 
 constexpr int kGB = 64;        // Gaussians per block
 constexpr int kThreads = 256;
-static_assert(kGB == 64 && kThreads >= 3 * 64, "Eq. 8 phase: one Gaussian per lane, one wave per output group");
+static_assert(kGB == 64 && kThreads >= 4 * 64, "Eq. 8 phase: one Gaussian per lane, one wave per output group");
 
 typedef float float4_t __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
@@ -70,7 +76,7 @@ __device__ __forceinline__ void grid_coord(float x, float scale, int n, int &i0,
     w = g - (float)i;
 }
 
-template <int F, int L, int HID, bool BF16>
+template <int F, int L, int HID, bool BF16, int NT>
 struct Smem {
     static constexpr int K = F * L;                        // in_dim
     static constexpr int KP = BF16 ? ((K + 31) / 32) * 32 : K;   // padded K
@@ -83,17 +89,39 @@ struct Smem {
     static constexpr size_t h_bytes = (size_t)kGB * H_LD * sizeof(E);
     static constexpr size_t act_bytes = fh_bytes > h_bytes ? fh_bytes : h_bytes;   // f_h, then h
     static constexpr size_t w1_bytes = (size_t)HID * W1_LD * sizeof(E);
-    static constexpr size_t w2_bytes = (size_t)16 * W2_LD * sizeof(E);
-    static constexpr size_t delta_bytes = (size_t)kGB * 17 * sizeof(float);
-    static constexpr size_t bias_bytes = (size_t)(HID + 16) * sizeof(float);
+    static constexpr int DS = 16 * NT + 1;                 // delta row stride (floats)
+    static constexpr size_t w2_bytes = (size_t)16 * NT * W2_LD * sizeof(E);
+    static constexpr size_t delta_bytes = (size_t)kGB * DS * sizeof(float);
+    static constexpr size_t bias_bytes = (size_t)(HID + 16 * NT) * sizeof(float);
     // W1 is dead once h is computed: the heads' weights and the deltas reuse its space
     static constexpr size_t wreg_bytes = w1_bytes > w2_bytes + delta_bytes ? w1_bytes : w2_bytes + delta_bytes;
     static constexpr size_t total = act_bytes + wreg_bytes + bias_bytes;
 };
 
-template <int F, int L, int HID, bool BF16>
+// Row r of the concatenated decoder heads: its weights (null for padding)
+// and its bias.
+__device__ __forceinline__ const float *head_w(const DeformJob &job, int r, int hid) {
+    if (r < 3) return job.wx + r * hid;
+    if (r < 7) return job.wr + (r - 3) * hid;
+    if (r < 10) return job.ws + (r - 7) * hid;
+    if (r < 10 + job.n_sh) return job.wc + (r - 10) * hid;
+    if (r == 10 + job.n_sh && job.wa) return job.wa;
+    return nullptr;
+}
+__device__ __forceinline__ float head_b(const DeformJob &job, int r) {
+    if (r < 3) return job.bx[r];
+    if (r < 7) return job.br[r - 3];
+    if (r < 10) return job.bs[r - 7];
+    if (r < 10 + job.n_sh) return job.bc[r - 10];
+    if (r == 10 + job.n_sh && job.wa) return job.ba[0];
+    return 0.0f;
+}
+
+// NT: 16-row tiles of decoder heads (1: dx dr ds; 4: with the colour and
+// opacity heads, up to SH degree 3)
+template <int F, int L, int HID, bool BF16, int NT>
 __global__ __launch_bounds__(kThreads) void k_deform(DeformBatch batch) {
-    using S = Smem<F, L, HID, BF16>;
+    using S = Smem<F, L, HID, BF16, NT>;
     using E = typename S::E;
     constexpr int K = S::K;
     constexpr int KP = S::KP;
@@ -144,7 +172,7 @@ __global__ __launch_bounds__(kThreads) void k_deform(DeformBatch batch) {
     // LDS stores follow the encoder (registers are free here: LDS, not VGPRs,
     // limits the blocks per CU).
     constexpr int N1 = (HID * KP + kThreads - 1) / kThreads;
-    constexpr int N2 = (16 * HID + kThreads - 1) / kThreads;
+    constexpr int N2 = (16 * NT * HID + kThreads - 1) / kThreads;
     float v1[N1], v2[N2];
     float vb1 = 0.0f, vb2 = 0.0f;
     if (!features_only) {
@@ -158,13 +186,11 @@ __global__ __launch_bounds__(kThreads) void k_deform(DeformBatch batch) {
         for (int q = 0; q < N2; ++q) {
             const int i = tid + q * kThreads;
             const int r = i / HID, c = i - r * HID;
-            const float *src = r < 3 ? job.wx + r * HID : (r < 7 ? job.wr + (r - 3) * HID : job.ws + (r - 7) * HID);
-            v2[q] = (i < 16 * HID && r < 10) ? src[c] : 0.0f;
+            const float *src = i < 16 * NT * HID ? head_w(job, r, HID) : nullptr;
+            v2[q] = src ? src[c] : 0.0f;
         }
         vb1 = tid < HID ? job.b1[tid] : 0.0f;
-        if (tid < 3) vb2 = job.bx[tid];
-        else if (tid < 7) vb2 = job.br[tid - 3];
-        else if (tid < 10) vb2 = job.bs[tid - 7];
+        if (tid < 16 * NT) vb2 = head_b(job, tid);
     }
 
     // ---- A. encoder: f_h for 64 Gaussians
@@ -235,7 +261,7 @@ __global__ __launch_bounds__(kThreads) void k_deform(DeformBatch batch) {
             }
         }
         if (tid < HID) s_b1[tid] = vb1;
-        if (tid < 16) s_b2[tid] = vb2;
+        if (tid < 16 * NT) s_b2[tid] = vb2;
     }
     if constexpr (BF16 && KP > K) {
         // zero the padding columns K..KP of f_h
@@ -285,7 +311,7 @@ __global__ __launch_bounds__(kThreads) void k_deform(DeformBatch batch) {
 #pragma unroll
     for (int q = 0; q < N2; ++q) {
         const int i = tid + q * kThreads;
-        if (i < 16 * HID) {
+        if (i < 16 * NT * HID) {
             const int r = i / HID, c = i - r * HID;
             if constexpr (BF16) s_w2[r * S::W2_LD + c] = f32_to_bf16_rne(v2[q]);
             else s_w2[r * S::W2_LD + c] = v2[q];
@@ -306,16 +332,21 @@ __global__ __launch_bounds__(kThreads) void k_deform(DeformBatch batch) {
     }
     __syncthreads();
 
-    // ---- C. heads: delta[64 x 16] = h W2^T + b2
-    float4_t acc2 = float4_t{0.0f, 0.0f, 0.0f, 0.0f};
+    // ---- C. heads: delta[64 x 16 NT] = h W2^T + b2
+    float4_t acc2[NT];
+#pragma unroll
+    for (int c = 0; c < NT; ++c) acc2[c] = float4_t{0.0f, 0.0f, 0.0f, 0.0f};
     if constexpr (!BF16) {
         const float *hs = reinterpret_cast<const float *>(s_act);
         const float *w2 = reinterpret_cast<const float *>(s_w2);
 #pragma unroll 4
         for (int kk = 0; kk < HID / 4; ++kk) {
             const float a = hs[(row0 + lrow) * S::H_LD + kk * 4 + lk];
-            const float b = w2[lrow * S::W2_LD + kk * 4 + lk];
-            acc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc2, 0, 0, 0);
+#pragma unroll
+            for (int c = 0; c < NT; ++c) {
+                const float b = w2[(c * 16 + lrow) * S::W2_LD + kk * 4 + lk];
+                acc2[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc2[c], 0, 0, 0);
+            }
         }
     } else {
         const uint16_t *hs = reinterpret_cast<const uint16_t *>(s_act);
@@ -323,22 +354,31 @@ __global__ __launch_bounds__(kThreads) void k_deform(DeformBatch batch) {
 #pragma unroll
         for (int kk = 0; kk < HID / 32; ++kk) {
             const bf16x8_t a = *reinterpret_cast<const bf16x8_t *>(hs + (row0 + lrow) * S::H_LD + kk * 32 + lk * 8);
-            const bf16x8_t b = *reinterpret_cast<const bf16x8_t *>(w2 + lrow * S::W2_LD + kk * 32 + lk * 8);
-            acc2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc2, 0, 0, 0);
+#pragma unroll
+            for (int c = 0; c < NT; ++c) {
+                const bf16x8_t b =
+                    *reinterpret_cast<const bf16x8_t *>(w2 + (c * 16 + lrow) * S::W2_LD + kk * 32 + lk * 8);
+                acc2[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc2[c], 0, 0, 0);
+            }
         }
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) s_delta[(row0 + 4 * lk + i) * 17 + lrow] = acc2[i] + s_b2[lrow];
+    for (int c = 0; c < NT; ++c)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            s_delta[(row0 + 4 * lk + i) * S::DS + c * 16 + lrow] = acc2[c][i] + s_b2[c * 16 + lrow];
     __syncthreads();
 
     // ---- D. Eq. 8 + activations: wave 0 the means and opacity, wave 1 the
-    // rotation, wave 2 the scales (inputs were loaded at the start)
+    // rotation, wave 2 the scales (inputs were loaded at the start), wave 3
+    // the SH coefficients when there is a colour head
     if (dg < n) {
-        const float *d = s_delta + lane_g * 17;
+        const float *d = s_delta + lane_g * S::DS;
         if (wave_d == 0) {
 #pragma unroll
             for (int k = 0; k < 3; ++k) job.out_means[(size_t)k * n + dg] = pin[k] + d[k];
-            job.out_opac[dg] = 1.0f / (1.0f + expf(-pin[3]));
+            const float logit = job.wa ? pin[3] + d[10 + job.n_sh] : pin[3];
+            job.out_opac[dg] = 1.0f / (1.0f + expf(-logit));
         } else if (wave_d == 1) {
             float q[4];
             float qn = 0.0f;
@@ -359,6 +399,9 @@ __global__ __launch_bounds__(kThreads) void k_deform(DeformBatch batch) {
         } else if (wave_d == 2) {
 #pragma unroll
             for (int k = 0; k < 3; ++k) job.out_scales[(size_t)k * n + dg] = expf(pin[k] + d[7 + k]);
+        } else if (wave_d == 3) {
+            for (int r = 0; r < job.n_sh; ++r)
+                job.out_sh[(size_t)r * n + dg] = job.sh_in[(size_t)r * n + dg] + d[10 + r];
         }
     }
 }
@@ -366,12 +409,13 @@ __global__ __launch_bounds__(kThreads) void k_deform(DeformBatch batch) {
 using DeformKernel = void (*)(DeformBatch);
 
 struct KernelEntry {
-    int feat, scales, hidden, bf16;
+    int feat, scales, hidden, bf16, nt;
     DeformKernel fn;
     size_t smem;
 };
 
-#define G4D_DEFORM_ENTRY(F, L, H, B) {F, L, H, B, k_deform<F, L, H, (bool)B>, Smem<F, L, H, (bool)B>::total}
+#define G4D_DEFORM_ENTRY(F, L, H, B) {F, L, H, B, 1, k_deform<F, L, H, (bool)B, 1>, Smem<F, L, H, (bool)B, 1>::total}
+#define G4D_DEFORM_ENTRY_CO(F, L, H) {F, L, H, 0, 4, k_deform<F, L, H, false, 4>, Smem<F, L, H, false, 4>::total}
 
 const KernelEntry kDeformKernels[] = {
     G4D_DEFORM_ENTRY(16, 1, 32, 0), G4D_DEFORM_ENTRY(16, 1, 64, 0), G4D_DEFORM_ENTRY(16, 1, 128, 0),
@@ -382,11 +426,16 @@ const KernelEntry kDeformKernels[] = {
     G4D_DEFORM_ENTRY(16, 2, 64, 1), G4D_DEFORM_ENTRY(16, 3, 64, 1),
     G4D_DEFORM_ENTRY(32, 1, 64, 1), G4D_DEFORM_ENTRY(32, 2, 64, 1), G4D_DEFORM_ENTRY(32, 2, 128, 1),
     G4D_DEFORM_ENTRY(32, 3, 64, 1), G4D_DEFORM_ENTRY(32, 3, 128, 1),
+    // with the colour and opacity heads (FP32 decoder)
+    G4D_DEFORM_ENTRY_CO(16, 1, 32), G4D_DEFORM_ENTRY_CO(16, 1, 64), G4D_DEFORM_ENTRY_CO(16, 1, 128),
+    G4D_DEFORM_ENTRY_CO(16, 2, 64), G4D_DEFORM_ENTRY_CO(16, 3, 64),
+    G4D_DEFORM_ENTRY_CO(32, 1, 64), G4D_DEFORM_ENTRY_CO(32, 2, 64), G4D_DEFORM_ENTRY_CO(32, 2, 128),
+    G4D_DEFORM_ENTRY_CO(32, 3, 64), G4D_DEFORM_ENTRY_CO(32, 3, 128),
 };
 
-const KernelEntry *find_kernel(int feat, int scales, int hidden, int bf16) {
+const KernelEntry *find_kernel(int feat, int scales, int hidden, int bf16, int nt = 1) {
     for (const auto &e : kDeformKernels)
-        if (e.feat == feat && e.scales == scales && e.hidden == hidden && e.bf16 == bf16) return &e;
+        if (e.feat == feat && e.scales == scales && e.hidden == hidden && e.bf16 == bf16 && e.nt == nt) return &e;
     return nullptr;
 }
 
@@ -431,6 +480,16 @@ g4d_status fill_job(const g4d_gaussians *G, const g4d_planes *P, const g4d_mlp *
         J->wr = M->wr; J->br = M->br; J->ws = M->ws; J->bs = M->bs;
         J->out_means = out->means; J->out_scales = out->scales;
         J->out_quats = out->quats; J->out_opac = out->opacity;
+        // appendix heads: dC over all SH coefficients, dalpha on the opacity logit
+        if ((M->wc == nullptr) != (M->bc == nullptr) || (M->wa == nullptr) != (M->ba == nullptr)) return G4D_EINVAL;
+        if (M->wc) {
+            if (G->sh_degree < 0 || G->sh_degree > 3 || out->sh_degree != G->sh_degree) return G4D_EINVAL;
+            if (G->n > 0 && (!G->sh || !out->sh || out->sh == G->sh)) return G4D_EINVAL;
+            J->wc = M->wc; J->bc = M->bc;
+            J->n_sh = 3 * (G->sh_degree + 1) * (G->sh_degree + 1);
+            J->sh_in = G->sh; J->out_sh = out->sh;
+        }
+        if (M->wa) { J->wa = M->wa; J->ba = M->ba; }
     }
     return G4D_OK;
 }
@@ -467,8 +526,11 @@ g4d_status deform_batched(const g4d_deform_job *jobs, int n_jobs, hipStream_t s)
         if (!q.M || !q.P) return G4D_EINVAL;
         g4d_status st = fill_job(q.G, q.P, q.M, q.t, q.out, nullptr, &B.job[j]);
         if (st != G4D_OK) return st;
+        // head rows dx dr ds [dC] [dalpha]: one 16-row tile, or four
+        const int rows = B.job[j].n_sh + (q.M->wa ? 11 : 10);
+        const int nt = rows <= 16 ? 1 : 4;
         const KernelEntry *e = find_kernel(q.P->feat, q.P->n_scales, q.M->hidden,
-                                           q.M->precision == G4D_MLP_BF16 ? 1 : 0);
+                                           q.M->precision == G4D_MLP_BF16 ? 1 : 0, nt);
         if (!e || (q.M->precision != G4D_MLP_F32 && q.M->precision != G4D_MLP_BF16)) return G4D_EUNSUPPORTED;
         if (ke && e != ke) return G4D_EINVAL;   // one shape class per launch
         ke = e;

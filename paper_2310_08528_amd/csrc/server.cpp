@@ -209,7 +209,12 @@ namespace serve {
 
 namespace {
 
-size_t splat_bytes(int n) { return align_up((size_t)n * 11 * sizeof(float), 256); }
+// Per-frame Gaussians of a scene: means, scales, quats, opacity, and the
+// deformed SH coefficients when the decoder has a colour head.
+int colour_rows(const Scene &sc) { return sc.M.wc ? 3 * (sc.sh_degree + 1) * (sc.sh_degree + 1) : 0; }
+size_t splat_bytes(const Scene &sc) {
+    return align_up((size_t)sc.n * (11 + colour_rows(sc)) * sizeof(float), 256);
+}
 
 int64_t initial_capacity(const g4d_server *S, int scene, int w, int h) {
     const int n = S->scenes[scene]->n;
@@ -222,7 +227,7 @@ int64_t initial_capacity(const g4d_server *S, int scene, int w, int h) {
 
 size_t set_bytes(const g4d_server *S, int scene, int w, int h, int64_t cap) {
     const int n = S->scenes[scene]->n;
-    return splat_bytes(n) + g4d_render_workspace_bytes(std::max(n, 1), w, h, cap) + 256;
+    return splat_bytes(*S->scenes[scene]) + g4d_render_workspace_bytes(std::max(n, 1), w, h, cap) + 256;
 }
 
 bool dev_alloc(g4d_server *S, BufferSet *b) {
@@ -242,8 +247,8 @@ bool dev_alloc(g4d_server *S, BufferSet *b) {
     b->splats.scales = f + 3 * (size_t)n;
     b->splats.quats = f + 6 * (size_t)n;
     b->splats.opacity = f + 10 * (size_t)n;
-    b->splats.sh = sc.G.sh;
-    char *wsp = base + splat_bytes(n);
+    b->splats.sh = colour_rows(sc) ? f + 11 * (size_t)n : const_cast<float *>(sc.G.sh);
+    char *wsp = base + splat_bytes(sc);
     wsp = reinterpret_cast<char *>(align_up(reinterpret_cast<uintptr_t>(wsp), 256));
     b->ws.ptr = wsp;
     b->ws.bytes = g4d_render_workspace_bytes(std::max(n, 1), w, h, b->capacity);
@@ -487,6 +492,7 @@ extern "C" g4d_status g4d_server_add_scene(g4d_server *S, const g4d_gaussians *G
                                            const g4d_mlp *M, int32_t *scene_id) {
     if (!S || !G || !P || !M || !scene_id || G->n < 1 || G->sh_degree < 0 || G->sh_degree > 3) return G4D_EINVAL;
     if (M->in_dim != P->feat * P->n_scales || P->n_scales < 1 || P->n_scales > 3) return G4D_EINVAL;
+    if ((M->wc == nullptr) != (M->bc == nullptr) || (M->wa == nullptr) != (M->ba == nullptr)) return G4D_EINVAL;
     auto sc = std::make_unique<Scene>();
     sc->n = G->n;
     sc->sh_degree = G->sh_degree;
@@ -525,6 +531,15 @@ extern "C" g4d_status g4d_server_add_scene(g4d_server *S, const g4d_gaussians *G
     G4D_COPY(sc->M.br, M->br, 4 * 4);
     G4D_COPY(sc->M.ws, M->ws, 3 * hd * 4);
     G4D_COPY(sc->M.bs, M->bs, 3 * 4);
+    if (M->wc) {
+        const size_t rows = 3 * (size_t)(G->sh_degree + 1) * (G->sh_degree + 1);
+        G4D_COPY(sc->M.wc, M->wc, rows * hd * 4);
+        G4D_COPY(sc->M.bc, M->bc, rows * 4);
+    }
+    if (M->wa) {
+        G4D_COPY(sc->M.wa, M->wa, hd * 4);
+        G4D_COPY(sc->M.ba, M->ba, 4);
+    }
 #undef G4D_COPY
     std::lock_guard<std::mutex> lk(S->mu);
     *scene_id = (int32_t)S->scenes.size();
@@ -544,7 +559,9 @@ extern "C" g4d_status g4d_server_submit(g4d_server *S, int32_t scene_id, const g
     r->ticket = S->next_ticket++;
     r->key = ClassKey{scene_id, cam->width, cam->height};
     const Scene &sc = *S->scenes[scene_id];
-    r->shape = sc.P.feat * 1000000 + sc.P.n_scales * 10000 + sc.M.hidden * 10 + sc.M.precision;
+    // deform shape class: the kernel variant (head tiles: 1 for up to 16 head rows, else 4)
+    const int head_tiles = 10 + colour_rows(sc) + (sc.M.wa ? 1 : 0) <= 16 ? 1 : 4;
+    r->shape = sc.P.feat * 1000000 + sc.P.n_scales * 10000 + sc.M.hidden * 10 + sc.M.precision + 2 * head_tiles;
     r->cam = *cam;
     r->t = t;
     r->out = out_image;

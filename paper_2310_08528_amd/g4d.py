@@ -42,7 +42,7 @@ class Planes(ctypes.Structure):
 class MLP(ctypes.Structure):
     _fields_ = [("in_dim", c_i32), ("hidden", c_i32), ("precision", c_i32),
                 ("w1", c_p), ("b1", c_p), ("wx", c_p), ("bx", c_p), ("wr", c_p), ("br", c_p),
-                ("ws", c_p), ("bs", c_p)]
+                ("ws", c_p), ("bs", c_p), ("wc", c_p), ("bc", c_p), ("wa", c_p), ("ba", c_p)]
 
 
 class Splats(ctypes.Structure):
@@ -223,15 +223,27 @@ class DeviceMLP:
         f = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(device)
         self.in_dim, self.hidden, self.precision = mlp.in_dim, mlp.hidden, precision
         self.w = {k: f(getattr(mlp, k)) for k in ("w1", "b1", "wx", "bx", "wr", "br", "ws", "bs")}
+        # optional colour / opacity heads (absent: null pointers)
+        for k in ("wc", "bc", "wa", "ba"):
+            a = getattr(mlp, k, None)
+            self.w[k] = None if a is None else f(a)
+
+    @property
+    def has_colour(self) -> bool:
+        return self.w["wc"] is not None
 
     def struct(self) -> MLP:
         w = self.w
         return MLP(self.in_dim, self.hidden, self.precision, _ptr(w["w1"]), _ptr(w["b1"]), _ptr(w["wx"]),
-                   _ptr(w["bx"]), _ptr(w["wr"]), _ptr(w["br"]), _ptr(w["ws"]), _ptr(w["bs"]))
+                   _ptr(w["bx"]), _ptr(w["wr"]), _ptr(w["br"]), _ptr(w["ws"]), _ptr(w["bs"]),
+                   _ptr(w["wc"]), _ptr(w["bc"]), _ptr(w["wa"]), _ptr(w["ba"]))
 
 
 class DeviceSplats:
-    """Render-ready Gaussians (deform output / render input) in device tensors."""
+    """Render-ready Gaussians (deform output / render input) in device tensors.
+
+    With a decoder that has a colour head, the deform writes the SH
+    coefficients: pass sh=None to give the splats a buffer of their own."""
 
     def __init__(self, n, sh_degree, sh, device, means=None, scales=None, quats=None, opacity=None):
         import torch
@@ -241,8 +253,11 @@ class DeviceSplats:
         self.n, self.sh_degree = int(n), int(sh_degree)
         self.means, self.scales = mk((3, n), means), mk((3, n), scales)
         self.quats, self.opacity = mk((4, n), quats), mk((n,), opacity)
-        self.sh = sh if isinstance(sh, torch.Tensor) else torch.as_tensor(
-            np.ascontiguousarray(sh, dtype=np.float32)).to(device)
+        if sh is None:
+            self.sh = torch.empty((3 * (self.sh_degree + 1) ** 2, n), dtype=torch.float32, device=device)
+        else:
+            self.sh = sh if isinstance(sh, torch.Tensor) else torch.as_tensor(
+                np.ascontiguousarray(sh, dtype=np.float32)).to(device)
 
     @classmethod
     def from_host(cls, s, device):

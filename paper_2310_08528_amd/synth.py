@@ -85,6 +85,9 @@ class MLP:
 
     w1 [hidden][in_dim], b1 [hidden]; wx [3][hidden], bx [3];
     wr [4][hidden], br [4]; ws [3][hidden], bs [3].  float32, row-major.
+    Optional heads of the appendix's colour and opacity deformation:
+    wc [3 (d+1)^2][hidden], bc [3 (d+1)^2] (one row per SH coefficient, in
+    the colour array's order) and wa [1][hidden], ba [1]; None when absent.
     """
     w1: np.ndarray
     b1: np.ndarray
@@ -94,6 +97,10 @@ class MLP:
     br: np.ndarray
     ws: np.ndarray
     bs: np.ndarray
+    wc: Optional[np.ndarray] = None
+    bc: Optional[np.ndarray] = None
+    wa: Optional[np.ndarray] = None
+    ba: Optional[np.ndarray] = None
 
     @property
     def in_dim(self) -> int:
@@ -242,7 +249,10 @@ def make_planes(rng: np.random.Generator, means: np.ndarray, feat: int,
 
 
 def make_mlp(rng: np.random.Generator, in_dim: int, hidden: int, zero_bias: bool = False,
-             zero: bool = False) -> MLP:
+             zero: bool = False, colour_rows: int = 0, opacity: bool = False) -> MLP:
+    """PyTorch-default uniform init.  The colour (colour_rows > 0) and
+    opacity heads are drawn after the base weights, which therefore do not
+    depend on whether they are present."""
     def lin(fan_out, fan_in):
         k = 1.0 / math.sqrt(fan_in)
         w = rng.uniform(-k, k, size=(fan_out, fan_in))
@@ -256,7 +266,17 @@ def make_mlp(rng: np.random.Generator, in_dim: int, hidden: int, zero_bias: bool
     wx, bx = lin(3, hidden)
     wr, br = lin(4, hidden)
     ws, bs = lin(3, hidden)
-    return MLP(w1=w1, b1=b1, wx=wx, bx=bx, wr=wr, br=br, ws=ws, bs=bs)
+    m = MLP(w1=w1, b1=b1, wx=wx, bx=bx, wr=wr, br=br, ws=ws, bs=bs)
+    if colour_rows:
+        m.wc, m.bc = lin(colour_rows, hidden)
+    if opacity:
+        m.wa, m.ba = lin(1, hidden)
+    return m
+
+
+def sh_rows(sh_degree: int) -> int:
+    """SH coefficients per Gaussian: 3 colour channels x (d+1)^2 bands."""
+    return 3 * (sh_degree + 1) ** 2
 
 
 # ------------------------------------------------------------------- cameras
@@ -332,12 +352,14 @@ def config1(plane_dist: str = "normal", n: int = 2000, zero_field: bool = False)
 
 
 def config2(plane_dist: str = "normal", n: int = 100_000, width: int = 800, height: int = 800,
-            n_cams: int = 20, n_times: int = 20) -> Scene:
+            n_cams: int = 20, n_times: int = 20, colour_opacity: bool = False) -> Scene:
+    """colour_opacity adds the appendix's colour and opacity heads."""
     rng = _streams(2)
     means = means_shell(rng["means"], n)
     g = make_gaussians(rng, n, means, 3, "normal")
     pl = make_planes(rng["planes"], g.means, 32, [64, 128], 25, plane_dist)
-    mlp = make_mlp(rng["mlp"], pl.in_dim, 64)
+    mlp = make_mlp(rng["mlp"], pl.in_dim, 64, colour_rows=sh_rows(3) if colour_opacity else 0,
+                   opacity=colour_opacity)
     cams = ring_cameras(n_cams, 4.0, width, height)
     ts = np.linspace(0.0, 1.0, n_times)
     return Scene(g, pl, mlp, cams, ts, "C2")
@@ -356,7 +378,8 @@ def config4(plane_dist: str = "normal", n: int = 300_000, width: int = 1352, hei
 
 
 def tiny_scene(seed: int, n: int = 48, width: int = 48, height: int = 40, sh_degree: int = 1,
-               plane_dist: str = "uniform", log_scale_mean: float = -2.2) -> Scene:
+               plane_dist: str = "uniform", log_scale_mean: float = -2.2,
+               colour_opacity: bool = False) -> Scene:
     """A few dozen Gaussians in front of one camera: small enough for
     per-pixel brute force over every Gaussian."""
     rng = _streams(100 + seed)
@@ -364,7 +387,8 @@ def tiny_scene(seed: int, n: int = 48, width: int = 48, height: int = 40, sh_deg
     g = make_gaussians(rng, n, means, sh_degree, "normal")
     g.log_scales = _f32(rng["extra"].normal(log_scale_mean, 0.4, size=(3, n)))
     pl = make_planes(rng["planes"], g.means, 16, [8], 4, plane_dist)
-    mlp = make_mlp(rng["mlp"], pl.in_dim, 32)
+    mlp = make_mlp(rng["mlp"], pl.in_dim, 32, colour_rows=sh_rows(sh_degree) if colour_opacity else 0,
+                   opacity=colour_opacity)
     cam = look_at_camera((0.6, 0.3, 3.0), (0.0, 0.0, 0.0), width, height, 50.0)
     return Scene(g, pl, mlp, [cam], np.array([0.3]), f"tiny{seed}")
 

@@ -68,12 +68,14 @@ def gpu_deform(scene, t, device="cuda:0", precision=g4d.MLP_F32, planes=None, ml
     G = g4d.DeviceGaussians(scene.gaussians, device)
     P = g4d.DevicePlanes(planes or scene.planes, device)
     M = g4d.DeviceMLP(mlp or scene.mlp, device, precision)
-    out = g4d.DeviceSplats(G.n, G.sh_degree, G.sh, device)
+    # with a colour head the deform writes the SH coefficients into a buffer of their own
+    out = g4d.DeviceSplats(G.n, G.sh_degree, None if M.has_colour else G.sh, device)
     g4d.deform(G, P, M, t, out)
     torch.cuda.synchronize()
+    sh = out.sh.cpu().numpy().reshape(np.shape(scene.gaussians.sh)) if M.has_colour else scene.gaussians.sh
     host = types.SimpleNamespace(means=out.means.cpu().numpy(), scales=out.scales.cpu().numpy(),
                                  quats=out.quats.cpu().numpy(), opacity=out.opacity.cpu().numpy(),
-                                 sh=scene.gaussians.sh, sh_degree=scene.gaussians.sh_degree, n=G.n)
+                                 sh=sh, sh_degree=scene.gaussians.sh_degree, n=G.n)
     return host, (G, P, M, out)
 
 

@@ -55,3 +55,79 @@ def test_host_validation_rejects_null_arguments_without_touching_the_device():
     G = g4d.Gaussians(0, 0, None, None, None, None, None)
     P = g4d.Planes()
     assert lib.g4d_deform_features(ctypes.byref(G), ctypes.byref(P), ctypes.c_float(2.0), None, None) == g4d.EINVAL
+
+
+_STRUCTS = {
+    "g4d_gaussians": g4d.Gaussians, "g4d_planes": g4d.Planes, "g4d_mlp": g4d.MLP,
+    "g4d_splats": g4d.Splats, "g4d_camera": g4d.Camera, "g4d_workspace": g4d.Workspace,
+    "g4d_device_status": g4d.DeviceStatus, "g4d_deform_job": g4d.DeformJob,
+    "g4d_server_config": g4d.ServerConfig, "g4d_server_stats": g4d.ServerStats,
+    "g4d_sim_config": g4d.SimConfig, "g4d_sim_result": g4d.SimResult,
+}
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """Every ctypes structure of the binding has the size and field offsets
+    that a C compiler gives the header's struct (compiled here with gcc)."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not found")
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "g4d.h"', "int main(void) {"]
+    for cname, py in _STRUCTS.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call([gcc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)], text=True).split("\n")
+    got = {}
+    for line in out:
+        if line:
+            cname, what, val = line.split()
+            got[(cname, what)] = int(val)
+    for cname, py in _STRUCTS.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
+
+
+def test_decoder_head_pairs_are_validated_on_the_host():
+    """A colour or opacity head weight without its bias (or the reverse) is
+    rejected before any launch; with n = 0 nothing would be launched anyway."""
+    lib = g4d.load()
+    fake = 1 << 20          # never dereferenced: validation fails before any launch
+    G = g4d.Gaussians(0, 1, fake, fake, fake, fake, fake)
+    P = g4d.Planes()
+    P.n_scales, P.feat = 1, 16
+    for k in range(3):
+        P.bmin[k], P.bmax[k] = -1.0, 1.0
+    for k in range(4):
+        P.res[0][k] = 4
+    for p in range(6):
+        P.plane[0][p] = fake
+    out = g4d.Splats(0, 1, fake, fake, fake, fake, fake + 256)
+
+    def mlp(**heads):
+        m = g4d.MLP(16, 32, g4d.MLP_F32, fake, fake, fake, fake, fake, fake, fake, fake)
+        for k, v in heads.items():
+            setattr(m, k, v)
+        return m
+
+    def call(m, o=out):
+        return lib.g4d_deform(ctypes.byref(G), ctypes.byref(P), ctypes.byref(m), ctypes.c_float(0.5),
+                              ctypes.byref(o), None)
+    assert call(mlp(wc=fake)) == g4d.EINVAL
+    assert call(mlp(bc=fake)) == g4d.EINVAL
+    assert call(mlp(wa=fake)) == g4d.EINVAL
+    assert call(mlp(ba=fake)) == g4d.EINVAL
+    # a colour head needs the output SH degree to match the input's
+    bad = g4d.Splats(0, 2, fake, fake, fake, fake, fake + 256)
+    assert call(mlp(wc=fake, bc=fake), bad) == g4d.EINVAL
+    # valid heads with n = 0: nothing to do
+    assert call(mlp(wc=fake, bc=fake, wa=fake, ba=fake)) == g4d.OK
+    assert call(mlp()) == g4d.OK

@@ -140,6 +140,71 @@ def test_zero_field_with_bias_gives_uniform_closed_form_delta():
     np.testing.assert_allclose(d.quats, q / np.linalg.norm(q, axis=0), atol=1e-14)
 
 
+# ------------------------------------- colour and opacity heads (appendix)
+
+def _with_heads(mlp, wc, bc, wa, ba):
+    import dataclasses
+    f = lambda a: np.ascontiguousarray(a, dtype=np.float32)
+    return dataclasses.replace(mlp, wc=f(wc), bc=f(bc), wa=f(wa), ba=f(ba))
+
+
+def test_zero_colour_and_opacity_heads_reduce_to_the_base_method():
+    """All-zero colour and opacity heads leave every output of the Sec. 4.2
+    method bit-for-bit unchanged and return the canonical SH coefficients."""
+    g, planes, mlp = _small_field()
+    rows, hid = synth.sh_rows(g.sh_degree), mlp.hidden
+    m0 = _with_heads(mlp, np.zeros((rows, hid)), np.zeros(rows), np.zeros((1, hid)), np.zeros(1))
+    a = oracle.deform(g, planes, mlp, 0.6)
+    b = oracle.deform(g, planes, m0, 0.6)
+    assert a.sh is None
+    for k in ("means", "scales", "quats", "opacity"):
+        np.testing.assert_array_equal(getattr(a, k), getattr(b, k))
+    np.testing.assert_array_equal(b.sh, g.sh.astype(np.float64))
+
+
+def test_colour_head_rows_follow_the_colour_array_order():
+    """Give colour row r the weights of decoder row r mod 10 (dx 0-2, dr
+    3-6, ds 7-9) and the opacity head those of dx_y: every offset must then
+    equal the already-pinned deformation delta of that row, which fixes the
+    row-to-coefficient mapping ([(d+1)^2][3] order), the shared h and the
+    sign of both heads."""
+    g, planes, mlp = _small_field()
+    assert g.sh_degree == 1
+    rows = synth.sh_rows(g.sh_degree)
+    base_w = np.concatenate([mlp.wx, mlp.wr, mlp.ws], 0)
+    base_b = np.concatenate([mlp.bx, mlp.br, mlp.bs], 0)
+    sel = np.arange(rows) % 10
+    m = _with_heads(mlp, base_w[sel], base_b[sel], mlp.wx[1:2], mlp.bx[1:2])
+    d = oracle.deform(g, planes, m, 0.25, want_features=True)
+    dC = (d.sh - g.sh.astype(np.float64)).reshape(rows, g.n)
+    for r in range(rows):
+        np.testing.assert_allclose(dC[r], d.delta[:, r % 10], rtol=1e-12, atol=1e-12)
+    logit = np.log(d.opacity / (1.0 - d.opacity))
+    np.testing.assert_allclose(logit - g.opacity_logits, d.delta[:, 1], rtol=1e-9, atol=1e-9)
+    # the opacity head moves the opacity, the colour head leaves Eq. 8 alone
+    base = oracle.deform(g, planes, mlp, 0.25)
+    for k in ("means", "scales", "quats"):
+        np.testing.assert_array_equal(getattr(d, k), getattr(base, k))
+
+
+def test_zero_field_colour_offset_is_uniform_closed_form():
+    """Zero planes give f_h = 0, so every Gaussian's colour moves by the same
+    dC = Wc ReLU(b1) + bc and its opacity logit by Wa ReLU(b1) + ba."""
+    g, planes, mlp = _small_field("zero")
+    rng = np.random.default_rng(12)
+    rows, hid = synth.sh_rows(g.sh_degree), mlp.hidden
+    m = _with_heads(mlp, rng.uniform(-0.3, 0.3, (rows, hid)), rng.uniform(-0.2, 0.2, rows),
+                    rng.uniform(-0.3, 0.3, (1, hid)), rng.uniform(-0.2, 0.2, 1))
+    d = oracle.deform(g, planes, m, 0.7)
+    h = np.maximum(mlp.b1.astype(np.float64), 0.0)
+    dC = m.wc.astype(np.float64) @ h + m.bc
+    da = float(m.wa.astype(np.float64)[0] @ h + m.ba[0])
+    got = (d.sh - g.sh.astype(np.float64)).reshape(rows, g.n)
+    np.testing.assert_allclose(got, np.repeat(dC[:, None], g.n, 1), atol=1e-12)
+    np.testing.assert_allclose(d.opacity, 1 / (1 + np.exp(-(g.opacity_logits.astype(np.float64) + da))),
+                               rtol=1e-13)
+
+
 def test_constant_temporal_planes_make_deformation_time_independent():
     g, planes, mlp = _small_field("uniform")
     for lv in planes.planes:
