@@ -252,10 +252,71 @@ def time_scene(sc, precision, steps, warmup, n_frames=None):
             "stages_ms": {k: round(v, 4) for k, v in stages.items()}, "instances_max": kmax}
 
 
+def time_composition(steps, warmup, n_each=50_000):
+    """frames/s of the composition workload: two scenes (two deform kernel
+    variants, so two launches) placed into one set by g4d_deform_compose,
+    then one render at 800x800."""
+    import torch
+    from paper_2310_08528_amd import g4d, synth
+    dev = "cuda:0"
+    ev = HipEvents()
+    items, cams_h, ts = synth.composition(n_each=n_each)
+    dev_items = [(g4d.DeviceGaussians(g, dev), g4d.DevicePlanes(pl, dev), g4d.DeviceMLP(m, dev), g4d.placement(*p))
+                 for g, pl, m, p in items]
+    n = sum(it[0].n for it in dev_items)
+    S = g4d.DeviceSplats(n, 3, None, dev)
+    cams = [g4d.camera_struct(c) for c in cams_h]
+    W, H = cams_h[0].width, cams_h[0].height
+    img = torch.empty((3, H, W), dtype=torch.float32, device=dev)
+    nf = max(len(cams), len(ts))
+    frames = [(k % len(cams), float(ts[k % len(ts)])) for k in range(nf)]
+
+    def frame(k):
+        ci, t = frames[k % nf]
+        g4d.deform_compose([(G, P, M, t, pl) for G, P, M, pl in dev_items], S)
+        g4d.render(S, cams[ci], ws, img)
+    ws = g4d.RenderWorkspace(n, W, H, 64 * n + 4096, dev)
+    kmax = 0
+    for k in range(nf):
+        frame(k)
+        st = g4d.read_status(ws)
+        kmax = max(kmax, int(st.instances))
+    if kmax > 64 * n + 4096:
+        ws = g4d.RenderWorkspace(n, W, H, int(kmax * 1.25) + 4096, dev)
+    for k in range(warmup):
+        frame(k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        frame(k)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = g4d.read_status(ws)
+    assert st.overflow == 0 and st.sort_error == 0
+    sp = torch.cuda.current_stream().cuda_stream
+    marks = [(ev.create(), ev.create(), ev.create()) for _ in range(min(steps, 50))]
+    for k, (a, b, c) in enumerate(marks):
+        ci, t = frames[k % nf]
+        ev.record(a, sp)
+        g4d.deform_compose([(G, P, M, t, pl) for G, P, M, pl in dev_items], S)
+        ev.record(b, sp)
+        g4d.render(S, cams[ci], ws, img)
+        ev.record(c, sp)
+    torch.cuda.synchronize()
+    return {"workload": f"2 scenes x {n_each} Gaussians (shell SH3 F32 64+128/t25 MLP 64; cube SH0 F16 32/t8 "
+                        f"MLP 64 with colour + opacity heads), placed, {W}x{H}",
+            "gaussians": n, "steps": steps, "frames_per_s": round(steps / wall, 2),
+            "ms_per_frame": round(1e3 * wall / steps, 4),
+            "compose_ms": round(float(np.mean([ev.elapsed(a, b) for a, b, _ in marks])), 4),
+            "render_ms": round(float(np.mean([ev.elapsed(b, c) for _, b, c in marks])), 4),
+            "instances_max": kmax}
+
+
 def extra_measurements(steps, warmup):
     """The large configuration (300k Gaussians, planes 64/128/256 x t150,
-    MLP 96-128-10, 1352x1014) with the FP32 and the BF16-input MFMA MLP, and
-    the 100k workload's generator swept over N at 800x800."""
+    MLP 96-128-10, 1352x1014) with the FP32 and the BF16-input MFMA MLP, the
+    100k workload with the colour and opacity heads, the composition
+    workload, and the 100k workload's generator swept over N at 800x800."""
     from paper_2310_08528_amd import g4d, synth
     out = {}
     log("extra: large configuration")
@@ -270,6 +331,8 @@ def extra_measurements(steps, warmup):
         "workload": "100k Gaussians, SH3, the 100k configuration's field; decoder with the colour "
                     "(48 rows) and opacity heads, 800x800",
         "fp32_mlp": time_scene(synth.config2(colour_opacity=True), g4d.MLP_F32, steps, warmup)}
+    log("extra: composition")
+    out["composition"] = time_composition(steps, warmup)
     out["sweep_n"] = {}
     for n in (10_000, 30_000, 100_000, 300_000):
         log(f"extra: N = {n}")

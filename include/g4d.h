@@ -196,6 +196,48 @@ typedef struct {
  * same as a lone g4d_deform call.  1 <= n_jobs <= G4D_MAX_BATCH_JOBS. */
 g4d_status g4d_deform_batched(const g4d_deform_job *jobs, int32_t n_jobs, void *stream);
 
+/* Placement of one scene in a composition (the naive rigid edit of the
+ * appendix's "Editing with 4D Gaussians"): after Eq. 8 and the activations,
+ * mean'' = scale * R(rotation) mean' + translation, quat'' = rotation (x)
+ * quat' (Hamilton product, so the Gaussian's rotation matrix becomes
+ * R(rotation) R(quat')), scales'' = scale * scales'; opacity and the SH
+ * coefficients are kept (view-dependent colour is not rotated). */
+typedef struct {
+    float rotation[4];          /* (w, x, y, z), nonzero; normalised by the call */
+    float scale;                /* uniform, > 0 and finite */
+    float translation[3];
+} g4d_placement;
+
+/* One scene of a composition: its canonical Gaussians, field, decoder (with
+ * or without the colour / opacity heads), time and placement. */
+typedef struct {
+    const g4d_gaussians *G;
+    const g4d_planes *P;
+    const g4d_mlp *M;
+    float t;
+    g4d_placement place;
+} g4d_compose_item;
+
+#define G4D_MAX_COMPOSE_ITEMS 64
+
+/* Multi-scene composition (Sec. 5.4, "Composition with 4D Gaussians"): the
+ * deformed sets of several trained scenes placed in one space,
+ * G' = {G'_1, ..., G'_n}, written into one render-ready set that a single
+ * g4d_render call draws.  Item i fills the index range [o_i, o_i + n_i) of
+ * every structure-of-arrays row of `out`, o_i = n_0 + ... + n_(i-1);
+ * out->n must equal the sum of the n_i.  out->sh holds
+ * [(D+1)^2][3][out->n] with D = out->sh_degree >= every item's SH degree:
+ * an item's coefficients (C, or C + dC with a colour head) fill its range of
+ * its own rows and zeros the rows of higher bands (the same colour).
+ * out->sh must be a buffer of its own.  Items whose deform kernels differ
+ * (feat, n_scales, hidden, precision, head tiles) run as separate launches
+ * on the stream, in order; each item's values are bitwise those of a lone
+ * g4d_deform followed by the placement (none at the identity placement).
+ * 1 <= n_items <= G4D_MAX_COMPOSE_ITEMS; every argument is checked before
+ * the first launch.  Device pointers throughout. */
+g4d_status g4d_deform_compose(const g4d_compose_item *items, int32_t n_items, g4d_splats *out,
+                              void *stream);
+
 /* The encoder output f_h (Eq. 7) alone, [n][in_dim] float32: exposes the
  * intermediate of g4d_deform for verification.  Same kernel code path. */
 g4d_status g4d_deform_features(const g4d_gaussians *G, const g4d_planes *P, float t,

@@ -143,6 +143,59 @@ def deform(g, planes, mlp, t: float, bf16_emulate: bool = False, want_features: 
                                  sh=None if osh is None else osh.reshape(np.shape(g.sh)))
 
 
+def _quat_matrix(q):
+    """Rotation matrix of the unit quaternion q = (w, x, y, z)."""
+    w, x, y, z = q
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                     [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                     [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+
+
+def _quat_mul(a, b):
+    """Hamilton product a (x) b of quaternions (w, x, y, z); b may be [4][n]."""
+    aw, ax, ay, az = a
+    bw, bx, by, bz = b
+    return np.stack([aw * bw - ax * bx - ay * by - az * bz,
+                     aw * bx + ax * bw + ay * bz - az * by,
+                     aw * by - ax * bz + ay * bw + az * bx,
+                     aw * bz + ax * by - ay * bx + az * bw])
+
+
+def place(d, rotation, scale, translation):
+    """The rigid edit of a deformed set (Sec. 5.4 composition, appendix
+    "Editing with 4D Gaussians": the rotation must reach the Gaussians'
+    quaternions and the scaling their scales): mean'' = s R mean' + T,
+    quat'' = rotation (x) quat', scales'' = s scales'.  FP64."""
+    q = np.asarray(rotation, dtype=np.float64)
+    q = q / np.linalg.norm(q)
+    R = _quat_matrix(q)
+    T = np.asarray(translation, dtype=np.float64)[:, None]
+    return types.SimpleNamespace(means=scale * (R @ d.means) + T, scales=scale * d.scales,
+                                 quats=_quat_mul(q, d.quats), opacity=d.opacity.copy(), sh=d.sh)
+
+
+def compose(items, sh_degree_out: int):
+    """Multi-scene composition (Sec. 5.4): G' = {G'_1, ..., G'_n}.  items:
+    list of (gaussians, planes, mlp, t, (rotation, scale, translation) or
+    None).  Each item is deformed (FP64), placed, and concatenated in order;
+    SH coefficients are padded with zero rows up to sh_degree_out.  Returns
+    FP64 means/scales/quats/opacity and the SH [(D+1)^2][3][N]."""
+    parts, shs = [], []
+    for g, planes, mlp, t, pl in items:
+        d = deform(g, planes, mlp, t)
+        if pl is not None:
+            d = place(d, *pl)
+        parts.append(d)
+        sh = np.asarray(g.sh if d.sh is None else d.sh, dtype=np.float64)
+        rows = np.zeros(((sh_degree_out + 1) ** 2, 3, g.n))
+        rows[:sh.shape[0]] = sh
+        shs.append(rows)
+    cat = lambda k: np.concatenate([getattr(p, k) for p in parts], axis=-1)
+    return types.SimpleNamespace(means=cat("means"), scales=cat("scales"), quats=cat("quats"),
+                                 opacity=cat("opacity"), sh=np.concatenate(shs, axis=-1),
+                                 sh_degree=int(sh_degree_out))
+
+
 def to_splats32(d, sh: np.ndarray, sh_degree: int):
     """Round an FP64 deformation result to the binary32 render input."""
     return types.SimpleNamespace(

@@ -14,26 +14,39 @@
 //      dr 3-6, ds 7-9; with the colour and opacity heads of the appendix,
 //      dC 10 .. 10 + 3 (d+1)^2 - 1 and dalpha next; zero padding) on MFMA.
 //   D. Eq. 8 and activations: X + dX, exp(log s + ds), normalise(r + dr),
-//      sigmoid(opacity logit [+ dalpha]), SH coefficients C [+ dC];
-//      structure-of-arrays stores.
+//      sigmoid(opacity logit [+ dalpha]), SH coefficients C [+ dC]; in a
+//      composition, the scene's placement and its index range of the
+//      combined set; structure-of-arrays stores.
 // A launch carries up to G4D_MAX_BATCH_JOBS jobs (continuous batching); a
 // block never mixes jobs, so a job's result does not depend on its batch.
 #include "g4d_internal.h"
 
+#include <cmath>
+#include <vector>
+
 namespace g4d {
 
+constexpr int kMaxScales = 3;   // scales the kernels support (<= G4D_MAX_SCALES)
+static_assert(kMaxScales <= G4D_MAX_SCALES, "scale count");
+
+// One job of a launch.  Kept compact: a launch passes G4D_MAX_BATCH_JOBS of
+// them by value as kernel arguments (at most 4 KB).
 struct DeformJob {
     const float *means, *log_scales, *quats, *opac;
-    const float *planes[G4D_MAX_SCALES * 6];
+    const float *planes[kMaxScales * 6];
     const float *w1, *b1, *wx, *bx, *wr, *br, *ws, *bs;
     const float *wc, *bc, *wa, *ba;      // colour / opacity heads (null when absent)
-    const float *sh_in;                  // canonical SH coefficients (colour head only)
+    const float *sh_in;                  // canonical SH coefficients [n_sh_in][n]
     float *out_means, *out_scales, *out_quats, *out_opac;
-    float *out_sh;                       // C + dC (colour head only)
-    int n_sh;                            // 3 (d+1)^2 colour rows, 0 without a colour head
+    float *out_sh;                       // [n_sh_out][out_stride] (C [+ dC], zero rows past n_sh_in)
+    int16_t n_sh_head;                   // 3 (d+1)^2 colour-head rows, 0 without a colour head
+    int16_t n_sh_in, n_sh_out;           // SH rows read / written (0: SH not written)
+    int16_t placed;                      // apply the placement below
+    int out_stride, out_offset;          // output row stride and this job's first index
+    float place_q[4], place_s, place_t[3];   // unit quaternion, uniform scale, translation
     float *out_features;                 // non-null: write f_h and stop after phase A
-    int res[G4D_MAX_SCALES][4];
-    float gscale[G4D_MAX_SCALES][4];     // (res - 1) / (bmax - bmin) per axis; res_t - 1 for t
+    int res[kMaxScales][4];
+    float gscale[kMaxScales][4];         // (res - 1) / (bmax - bmin) per axis; res_t - 1 for t
     float bmin[3];
     int n;
     float t;
@@ -45,12 +58,14 @@ struct DeformBatch {
     int n_blocks;   // blocks of work (the grid is padded to a multiple of 8)
     DeformJob job[G4D_MAX_BATCH_JOBS];
 };
+static_assert(sizeof(DeformBatch) <= 4096, "a launch's jobs travel as kernel arguments");
 
 namespace {
 
 constexpr int kGB = 64;        // Gaussians per block
 constexpr int kThreads = 256;
-static_assert(kGB == 64 && kThreads >= 4 * 64, "Eq. 8 phase: one Gaussian per lane, one wave per output group");
+static_assert(kGB == 64 && kThreads >= 3 * 64, "Eq. 8 phase: one Gaussian per lane, one wave per output group");
+static_assert(48 * kGB % kThreads == 0, "SH phase: whole rows of (d+1)^2 x 3 <= 48 coefficients per thread");
 
 typedef float float4_t __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
@@ -104,23 +119,23 @@ __device__ __forceinline__ const float *head_w(const DeformJob &job, int r, int 
     if (r < 3) return job.wx + r * hid;
     if (r < 7) return job.wr + (r - 3) * hid;
     if (r < 10) return job.ws + (r - 7) * hid;
-    if (r < 10 + job.n_sh) return job.wc + (r - 10) * hid;
-    if (r == 10 + job.n_sh && job.wa) return job.wa;
+    if (r < 10 + job.n_sh_head) return job.wc + (r - 10) * hid;
+    if (r == 10 + job.n_sh_head && job.wa) return job.wa;
     return nullptr;
 }
 __device__ __forceinline__ float head_b(const DeformJob &job, int r) {
     if (r < 3) return job.bx[r];
     if (r < 7) return job.br[r - 3];
     if (r < 10) return job.bs[r - 7];
-    if (r < 10 + job.n_sh) return job.bc[r - 10];
-    if (r == 10 + job.n_sh && job.wa) return job.ba[0];
+    if (r < 10 + job.n_sh_head) return job.bc[r - 10];
+    if (r == 10 + job.n_sh_head && job.wa) return job.ba[0];
     return 0.0f;
 }
 
 // NT: 16-row tiles of decoder heads (1: dx dr ds; 4: with the colour and
 // opacity heads, up to SH degree 3)
 template <int F, int L, int HID, bool BF16, int NT>
-__global__ __launch_bounds__(kThreads) void k_deform(DeformBatch batch) {
+__device__ __forceinline__ void deform_block(const DeformBatch &batch) {
     using S = Smem<F, L, HID, BF16, NT>;
     using E = typename S::E;
     constexpr int K = S::K;
@@ -370,15 +385,34 @@ __global__ __launch_bounds__(kThreads) void k_deform(DeformBatch batch) {
     __syncthreads();
 
     // ---- D. Eq. 8 + activations: wave 0 the means and opacity, wave 1 the
-    // rotation, wave 2 the scales (inputs were loaded at the start), wave 3
-    // the SH coefficients when there is a colour head
+    // rotation, wave 2 the scales (inputs were loaded at the start)
     if (dg < n) {
         const float *d = s_delta + lane_g * S::DS;
+        const size_t os = (size_t)job.out_stride, oi = (size_t)job.out_offset + dg;
         if (wave_d == 0) {
+            float x[3];
 #pragma unroll
-            for (int k = 0; k < 3; ++k) job.out_means[(size_t)k * n + dg] = pin[k] + d[k];
-            const float logit = job.wa ? pin[3] + d[10 + job.n_sh] : pin[3];
-            job.out_opac[dg] = 1.0f / (1.0f + expf(-logit));
+            for (int k = 0; k < 3; ++k) x[k] = pin[k] + d[k];
+            if (job.placed) {
+                // rotation matrix of the unit quaternion (w, x, y, z), row-major
+                const float qw = job.place_q[0], qx = job.place_q[1], qy = job.place_q[2], qz = job.place_q[3];
+                const float R[9] = {1.0f - 2.0f * (qy * qy + qz * qz), 2.0f * (qx * qy - qw * qz),
+                                    2.0f * (qx * qz + qw * qy),        2.0f * (qx * qy + qw * qz),
+                                    1.0f - 2.0f * (qx * qx + qz * qz), 2.0f * (qy * qz - qw * qx),
+                                    2.0f * (qx * qz - qw * qy),        2.0f * (qy * qz + qw * qx),
+                                    1.0f - 2.0f * (qx * qx + qy * qy)};
+                float y[3];
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+                    y[k] = job.place_s * (R[3 * k] * x[0] + R[3 * k + 1] * x[1] + R[3 * k + 2] * x[2]) +
+                           job.place_t[k];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) x[k] = y[k];
+            }
+#pragma unroll
+            for (int k = 0; k < 3; ++k) job.out_means[k * os + oi] = x[k];
+            const float logit = job.wa ? pin[3] + d[10 + job.n_sh_head] : pin[3];
+            job.out_opac[oi] = 1.0f / (1.0f + expf(-logit));
         } else if (wave_d == 1) {
             float q[4];
             float qn = 0.0f;
@@ -390,20 +424,62 @@ __global__ __launch_bounds__(kThreads) void k_deform(DeformBatch batch) {
             if (qn > 0.0f) {
                 const float inv = 1.0f / sqrtf(qn);
 #pragma unroll
-                for (int k = 0; k < 4; ++k) job.out_quats[(size_t)k * n + dg] = q[k] * inv;
+                for (int k = 0; k < 4; ++k) q[k] *= inv;
             } else {
-                job.out_quats[dg] = 1.0f;
-#pragma unroll
-                for (int k = 1; k < 4; ++k) job.out_quats[(size_t)k * n + dg] = 0.0f;
+                q[0] = 1.0f;
+                q[1] = q[2] = q[3] = 0.0f;
             }
+            if (job.placed) {
+                // Hamilton product place_q (x) q: rotation matrix R(place_q) R(q)
+                const float *a = job.place_q;
+                const float w = a[0] * q[0] - a[1] * q[1] - a[2] * q[2] - a[3] * q[3];
+                const float xq = a[0] * q[1] + a[1] * q[0] + a[2] * q[3] - a[3] * q[2];
+                const float yq = a[0] * q[2] - a[1] * q[3] + a[2] * q[0] + a[3] * q[1];
+                const float zq = a[0] * q[3] + a[1] * q[2] - a[2] * q[1] + a[3] * q[0];
+                q[0] = w; q[1] = xq; q[2] = yq; q[3] = zq;
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) job.out_quats[k * os + oi] = q[k];
         } else if (wave_d == 2) {
 #pragma unroll
-            for (int k = 0; k < 3; ++k) job.out_scales[(size_t)k * n + dg] = expf(pin[k] + d[7 + k]);
-        } else if (wave_d == 3) {
-            for (int r = 0; r < job.n_sh; ++r)
-                job.out_sh[(size_t)r * n + dg] = job.sh_in[(size_t)r * n + dg] + d[10 + r];
+            for (int k = 0; k < 3; ++k) {
+                const float sc = expf(pin[k] + d[7 + k]);
+                job.out_scales[k * os + oi] = job.placed ? job.place_s * sc : sc;
+            }
         }
     }
+    // ---- E. SH coefficients, when written (colour head, composition): all
+    // threads, element (row, Gaussian) = (i / 64, i % 64) for a coalesced row
+    // run per wave; every load is issued before the first store
+    if (job.n_sh_out > 0) {
+        constexpr int kShPer = 48 * kGB / kThreads;
+        float shv[kShPer];
+#pragma unroll
+        for (int q = 0; q < kShPer; ++q) {
+            const int i = tid + q * kThreads, r = i / kGB, g = g0 + i % kGB;
+            shv[q] = (r < job.n_sh_in && g < n) ? job.sh_in[(size_t)r * n + g] : 0.0f;
+        }
+#pragma unroll
+        for (int q = 0; q < kShPer; ++q) {
+            const int i = tid + q * kThreads, r = i / kGB, gl = i % kGB, g = g0 + gl;
+            if (r < job.n_sh_out && g < n) {
+                const float dc = r < job.n_sh_head ? s_delta[gl * S::DS + 10 + r] : 0.0f;
+                job.out_sh[(size_t)r * job.out_stride + job.out_offset + g] = shv[q] + dc;
+            }
+        }
+    }
+}
+
+template <int F, int L, int HID, bool BF16>
+__global__ __launch_bounds__(kThreads) void k_deform(DeformBatch batch) {
+    deform_block<F, L, HID, BF16, 1>(batch);
+}
+
+// with the colour and opacity heads: held to three waves per SIMD (the LDS
+// of the four head tiles allows three blocks per CU)
+template <int F, int L, int HID>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_deform_heads(DeformBatch batch) {
+    deform_block<F, L, HID, false, 4>(batch);
 }
 
 using DeformKernel = void (*)(DeformBatch);
@@ -414,8 +490,8 @@ struct KernelEntry {
     size_t smem;
 };
 
-#define G4D_DEFORM_ENTRY(F, L, H, B) {F, L, H, B, 1, k_deform<F, L, H, (bool)B, 1>, Smem<F, L, H, (bool)B, 1>::total}
-#define G4D_DEFORM_ENTRY_CO(F, L, H) {F, L, H, 0, 4, k_deform<F, L, H, false, 4>, Smem<F, L, H, false, 4>::total}
+#define G4D_DEFORM_ENTRY(F, L, H, B) {F, L, H, B, 1, k_deform<F, L, H, (bool)B>, Smem<F, L, H, (bool)B, 1>::total}
+#define G4D_DEFORM_ENTRY_CO(F, L, H) {F, L, H, 0, 4, k_deform_heads<F, L, H>, Smem<F, L, H, false, 4>::total}
 
 const KernelEntry kDeformKernels[] = {
     G4D_DEFORM_ENTRY(16, 1, 32, 0), G4D_DEFORM_ENTRY(16, 1, 64, 0), G4D_DEFORM_ENTRY(16, 1, 128, 0),
@@ -440,7 +516,7 @@ const KernelEntry *find_kernel(int feat, int scales, int hidden, int bf16, int n
 }
 
 bool planes_ok(const g4d_planes *P) {
-    if (!P || P->n_scales < 1 || P->n_scales > 3 || (P->feat != 16 && P->feat != 32)) return false;
+    if (!P || P->n_scales < 1 || P->n_scales > kMaxScales || (P->feat != 16 && P->feat != 32)) return false;
     for (int k = 0; k < 3; ++k)
         if (!(P->bmax[k] > P->bmin[k])) return false;
     for (int l = 0; l < P->n_scales; ++l) {
@@ -482,11 +558,12 @@ g4d_status fill_job(const g4d_gaussians *G, const g4d_planes *P, const g4d_mlp *
         J->out_quats = out->quats; J->out_opac = out->opacity;
         // appendix heads: dC over all SH coefficients, dalpha on the opacity logit
         if ((M->wc == nullptr) != (M->bc == nullptr) || (M->wa == nullptr) != (M->ba == nullptr)) return G4D_EINVAL;
+        J->out_stride = G->n;
         if (M->wc) {
             if (G->sh_degree < 0 || G->sh_degree > 3 || out->sh_degree != G->sh_degree) return G4D_EINVAL;
             if (G->n > 0 && (!G->sh || !out->sh || out->sh == G->sh)) return G4D_EINVAL;
             J->wc = M->wc; J->bc = M->bc;
-            J->n_sh = 3 * (G->sh_degree + 1) * (G->sh_degree + 1);
+            J->n_sh_head = J->n_sh_in = J->n_sh_out = (int16_t)(3 * (G->sh_degree + 1) * (G->sh_degree + 1));
             J->sh_in = G->sh; J->out_sh = out->sh;
         }
         if (M->wa) { J->wa = M->wa; J->ba = M->ba; }
@@ -527,7 +604,7 @@ g4d_status deform_batched(const g4d_deform_job *jobs, int n_jobs, hipStream_t s)
         g4d_status st = fill_job(q.G, q.P, q.M, q.t, q.out, nullptr, &B.job[j]);
         if (st != G4D_OK) return st;
         // head rows dx dr ds [dC] [dalpha]: one 16-row tile, or four
-        const int rows = B.job[j].n_sh + (q.M->wa ? 11 : 10);
+        const int rows = B.job[j].n_sh_head + (q.M->wa ? 11 : 10);
         const int nt = rows <= 16 ? 1 : 4;
         const KernelEntry *e = find_kernel(q.P->feat, q.P->n_scales, q.M->hidden,
                                            q.M->precision == G4D_MLP_BF16 ? 1 : 0, nt);
@@ -550,7 +627,84 @@ g4d_status deform_features(const g4d_gaussians *G, const g4d_planes *P, float t,
     return launch(B, e, s);
 }
 
+// Sec. 5.4 composition: every item's deformed set, placed, into its index
+// range of one render-ready set.  All items are validated before the first
+// launch; consecutive items of one kernel variant share a launch.
+g4d_status deform_compose(const g4d_compose_item *items, int n_items, g4d_splats *out, hipStream_t s) {
+    if (!items || !out || n_items < 1 || n_items > G4D_MAX_COMPOSE_ITEMS) return G4D_EINVAL;
+    if (out->n < 0 || out->sh_degree < 0 || out->sh_degree > 3) return G4D_EINVAL;
+    int64_t total = 0;
+    for (int i = 0; i < n_items; ++i) {
+        const g4d_gaussians *G = items[i].G;
+        if (!G || G->n < 0 || G->sh_degree < 0 || G->sh_degree > out->sh_degree) return G4D_EINVAL;
+        if (G->n > 0 && (!G->sh || G->sh == out->sh)) return G4D_EINVAL;
+        total += G->n;
+    }
+    if (total != out->n || total > (int64_t(1) << 26)) return G4D_EINVAL;
+    if (total > 0 && (!out->means || !out->scales || !out->quats || !out->opacity || !out->sh))
+        return G4D_EINVAL;
+    const int rows_out = 3 * (out->sh_degree + 1) * (out->sh_degree + 1);
+    std::vector<DeformJob> jobs((size_t)n_items);
+    std::vector<const KernelEntry *> kern((size_t)n_items);
+    int64_t offset = 0;
+    for (int i = 0; i < n_items; ++i) {
+        const g4d_compose_item &it = items[i];
+        const g4d_gaussians *G = it.G;
+        if (!it.P || !it.M) return G4D_EINVAL;
+        // the item's own view of the output: its sizes, the combined arrays
+        g4d_splats sub = *out;
+        sub.n = G->n;
+        sub.sh_degree = G->sh_degree;
+        DeformJob &J = jobs[(size_t)i];
+        g4d_status st = fill_job(G, it.P, it.M, it.t, &sub, nullptr, &J);
+        if (st != G4D_OK) return st;
+        J.out_stride = (int)total;
+        J.out_offset = (int)offset;
+        J.sh_in = G->sh;
+        J.out_sh = out->sh;
+        J.n_sh_in = (int16_t)(3 * (G->sh_degree + 1) * (G->sh_degree + 1));
+        J.n_sh_out = (int16_t)rows_out;
+        const g4d_placement &pl = it.place;
+        const double qn = std::sqrt((double)pl.rotation[0] * pl.rotation[0] + (double)pl.rotation[1] * pl.rotation[1] +
+                                    (double)pl.rotation[2] * pl.rotation[2] + (double)pl.rotation[3] * pl.rotation[3]);
+        if (!(qn > 0.0) || !std::isfinite(qn) || !(pl.scale > 0.0f) || !std::isfinite(pl.scale)) return G4D_EINVAL;
+        for (int k = 0; k < 3; ++k)
+            if (!std::isfinite(pl.translation[k])) return G4D_EINVAL;
+        for (int k = 0; k < 4; ++k) J.place_q[k] = (float)(pl.rotation[k] / qn);
+        J.place_s = pl.scale;
+        for (int k = 0; k < 3; ++k) J.place_t[k] = pl.translation[k];
+        J.placed = !(J.place_q[0] == 1.0f && J.place_q[1] == 0.0f && J.place_q[2] == 0.0f && J.place_q[3] == 0.0f &&
+                     pl.scale == 1.0f && pl.translation[0] == 0.0f && pl.translation[1] == 0.0f &&
+                     pl.translation[2] == 0.0f);
+        const int rows = J.n_sh_head + (it.M->wa ? 11 : 10);
+        const KernelEntry *e = find_kernel(it.P->feat, it.P->n_scales, it.M->hidden,
+                                           it.M->precision == G4D_MLP_BF16 ? 1 : 0, rows <= 16 ? 1 : 4);
+        if (!e || (it.M->precision != G4D_MLP_F32 && it.M->precision != G4D_MLP_BF16)) return G4D_EUNSUPPORTED;
+        kern[(size_t)i] = e;
+        offset += G->n;
+    }
+    DeformBatch B{};
+    const KernelEntry *ke = nullptr;
+    for (int i = 0; i <= n_items; ++i) {
+        const bool flush = B.n_jobs > 0 && (i == n_items || kern[(size_t)i] != ke || B.n_jobs == G4D_MAX_BATCH_JOBS);
+        if (flush) {
+            g4d_status st = launch(B, ke, s);
+            if (st != G4D_OK) return st;
+            B = DeformBatch{};
+        }
+        if (i == n_items) break;
+        B.job[B.n_jobs++] = jobs[(size_t)i];
+        ke = kern[(size_t)i];
+    }
+    return G4D_OK;
+}
+
 }  // namespace g4d
+
+extern "C" g4d_status g4d_deform_compose(const g4d_compose_item *items, int32_t n_items, g4d_splats *out,
+                                         void *stream) {
+    return g4d::deform_compose(items, n_items, out, reinterpret_cast<hipStream_t>(stream));
+}
 
 extern "C" g4d_status g4d_deform(const g4d_gaussians *G, const g4d_planes *P, const g4d_mlp *M,
                                  float t, g4d_splats *out, void *stream) {

@@ -72,6 +72,18 @@ class DeformJob(ctypes.Structure):
                 ("M", ctypes.POINTER(MLP)), ("t", c_f32), ("out", ctypes.POINTER(Splats))]
 
 
+class Placement(ctypes.Structure):
+    _fields_ = [("rotation", c_f32 * 4), ("scale", c_f32), ("translation", c_f32 * 3)]
+
+
+class ComposeItem(ctypes.Structure):
+    _fields_ = [("G", ctypes.POINTER(Gaussians)), ("P", ctypes.POINTER(Planes)),
+                ("M", ctypes.POINTER(MLP)), ("t", c_f32), ("place", Placement)]
+
+
+MAX_COMPOSE_ITEMS = 64
+
+
 class ServerConfig(ctypes.Structure):
     _fields_ = [("hbm_budget", c_sz), ("max_slots", c_i32), ("use_graphs", c_i32),
                 ("batch_deform", c_i32), ("max_width", c_i32), ("max_height", c_i32),
@@ -102,6 +114,7 @@ SIGNATURES = {
     "g4d_deform": (c_i32, [ctypes.POINTER(Gaussians), ctypes.POINTER(Planes), ctypes.POINTER(MLP), c_f32,
                            ctypes.POINTER(Splats), c_p]),
     "g4d_deform_batched": (c_i32, [ctypes.POINTER(DeformJob), c_i32, c_p]),
+    "g4d_deform_compose": (c_i32, [ctypes.POINTER(ComposeItem), c_i32, ctypes.POINTER(Splats), c_p]),
     "g4d_deform_features": (c_i32, [ctypes.POINTER(Gaussians), ctypes.POINTER(Planes), c_f32, c_p, c_p]),
     "g4d_render_workspace_bytes": (c_sz, [c_i32, c_i32, c_i32, c_i64]),
     "g4d_render": (c_i32, [ctypes.POINTER(Splats), ctypes.POINTER(Camera), ctypes.POINTER(Workspace), c_p, c_p,
@@ -321,6 +334,33 @@ def deform_batched(jobs, stream=None):
         keep += [gs, ps, ms, os_]
         arr[i] = DeformJob(ctypes.pointer(gs), ctypes.pointer(ps), ctypes.pointer(ms), float(t), ctypes.pointer(os_))
     check(load().g4d_deform_batched(arr, len(jobs), _stream(stream)), "g4d_deform_batched")
+
+
+def placement(rotation=(1.0, 0.0, 0.0, 0.0), scale=1.0, translation=(0.0, 0.0, 0.0)) -> Placement:
+    """A scene's placement in a composition: quaternion (w, x, y, z), uniform
+    scale, translation."""
+    p = Placement()
+    for k in range(4):
+        p.rotation[k] = float(rotation[k])
+    p.scale = float(scale)
+    for k in range(3):
+        p.translation[k] = float(translation[k])
+    return p
+
+
+def deform_compose(items, out: DeviceSplats, stream=None):
+    """items: list of (DeviceGaussians, DevicePlanes, DeviceMLP, t, placement
+    or None).  Writes every item's deformed, placed set into its index range
+    of ``out`` (out.n = sum of the items' n; out.sh a buffer of its own)."""
+    keep = []
+    arr = (ComposeItem * len(items))()
+    for i, (G, P, M, t, pl) in enumerate(items):
+        gs, ps, ms = G.struct(), P.struct(), M.struct()
+        keep += [gs, ps, ms]
+        arr[i] = ComposeItem(ctypes.pointer(gs), ctypes.pointer(ps), ctypes.pointer(ms), float(t),
+                             pl if pl is not None else placement())
+    os_ = out.struct()
+    check(load().g4d_deform_compose(arr, len(items), ctypes.byref(os_), _stream(stream)), "g4d_deform_compose")
 
 
 def deform_features(G: DeviceGaussians, P: DevicePlanes, t: float, features, stream=None):

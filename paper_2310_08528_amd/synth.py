@@ -417,6 +417,33 @@ def serving_scenes(scale: float = 1.0):
     return out
 
 
+def composition(n_each: int = 50_000, width: int = 800, height: int = 800, n_cams: int = 20,
+                n_times: int = 20):
+    """Two trained-scene stand-ins placed side by side in one space (the
+    composition workload): a 100k-configuration-family shell (SH3, planes
+    64+128 x t25 F32, MLP 64) and a small-configuration-family cube (SH0,
+    planes 32 x t8 F16, MLP 64) whose decoder also has the colour and opacity
+    heads, each with n_each Gaussians.  Returns (items, cameras, timestamps)
+    with items = [(gaussians, planes, mlp, (rotation wxyz, scale,
+    translation))]; the two decoders run as two deform launches."""
+    out = []
+    rng = _streams(70)
+    means = means_shell(rng["means"], n_each)
+    g = make_gaussians(rng, n_each, means, 3, "normal")
+    pl = make_planes(rng["planes"], g.means, 32, [64, 128], 25)
+    mlp = make_mlp(rng["mlp"], pl.in_dim, 64)
+    th = math.radians(30.0)
+    out.append((g, pl, mlp, ((math.cos(th / 2), 0.0, math.sin(th / 2), 0.0), 0.8, (-1.1, 0.0, 0.0))))
+    rng = _streams(71)
+    means = means_cube(rng["means"], n_each)
+    g = make_gaussians(rng, n_each, means, 0, "rgb0")
+    pl = make_planes(rng["planes"], g.means, 16, [32], 8)
+    mlp = make_mlp(rng["mlp"], pl.in_dim, 64, colour_rows=sh_rows(0), opacity=True)
+    out.append((g, pl, mlp, ((1.0, 0.0, 0.0, 0.0), 0.7, (1.1, 0.0, 0.0))))
+    cams = ring_cameras(n_cams, 4.5, width, height)
+    return out, cams, np.linspace(0.0, 1.0, n_times)
+
+
 def poisson_arrivals(rate_hz: float, duration_s: float, n_scenes: int, n_cams: int,
                      resolutions: Sequence[Sequence[int]], seed: int = 5):
     """Poisson request trace: (arrival_s, scene, camera, t, (W, H))."""

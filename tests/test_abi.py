@@ -131,3 +131,37 @@ def test_decoder_head_pairs_are_validated_on_the_host():
     # valid heads with n = 0: nothing to do
     assert call(mlp(wc=fake, bc=fake, wa=fake, ba=fake)) == g4d.OK
     assert call(mlp()) == g4d.OK
+
+
+def test_compose_arguments_are_validated_on_the_host():
+    """g4d_deform_compose checks every item and the output before its first
+    launch; with empty items nothing would be launched anyway."""
+    lib = g4d.load()
+    fake = 1 << 20
+    G = g4d.Gaussians(0, 1, fake, fake, fake, fake, fake)
+    P = g4d.Planes()
+    P.n_scales, P.feat = 1, 16
+    for k in range(3):
+        P.bmin[k], P.bmax[k] = -1.0, 1.0
+    for k in range(4):
+        P.res[0][k] = 4
+    for p in range(6):
+        P.plane[0][p] = fake
+    M = g4d.MLP(16, 32, g4d.MLP_F32, fake, fake, fake, fake, fake, fake, fake, fake)
+    Gp, Pp, Mp = ctypes.pointer(G), ctypes.pointer(P), ctypes.pointer(M)
+
+    def call(places, out_deg=1, out_sh=fake + 512, n_items=None):
+        arr = (g4d.ComposeItem * len(places))()
+        for i, pl in enumerate(places):
+            arr[i] = g4d.ComposeItem(Gp, Pp, Mp, 0.5, pl)
+        out = g4d.Splats(0, out_deg, fake, fake, fake, fake, out_sh)
+        return lib.g4d_deform_compose(arr, len(places) if n_items is None else n_items, ctypes.byref(out), None)
+    ok = g4d.placement((0.0, 0.0, 2.0, 0.0), 2.0, (1.0, 2.0, 3.0))
+    assert call([ok, g4d.placement()]) == g4d.OK
+    assert call([ok, g4d.placement(scale=0.0)]) == g4d.EINVAL
+    assert call([ok, g4d.placement(scale=float("inf"))]) == g4d.EINVAL
+    assert call([g4d.placement(rotation=(0, 0, 0, 0))]) == g4d.EINVAL
+    assert call([g4d.placement(translation=(0, float("nan"), 0))]) == g4d.EINVAL
+    assert call([ok], out_deg=0) == g4d.EINVAL               # an item's SH degree above the output's
+    assert call([ok], n_items=0) == g4d.EINVAL
+    assert call([ok] * (g4d.MAX_COMPOSE_ITEMS + 1)) == g4d.EINVAL

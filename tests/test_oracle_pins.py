@@ -405,6 +405,70 @@ def test_projection_invariant_under_joint_world_rotation():
     np.testing.assert_allclose(p1.f64[vis, :5], p0.f64[vis, :5], rtol=2e-4, atol=2e-3)
 
 
+# --------------------------------------------- composition (Sec. 5.4)
+
+def test_composition_at_identity_is_the_concatenation():
+    """G' = {G'_1, G'_2}: with identity placements the composed set is the
+    items' deformed sets one after the other, the lower-degree item's SH
+    padded with zero rows."""
+    a = synth.tiny_scene(60, n=30, sh_degree=1)
+    b = synth.tiny_scene(61, n=45, sh_degree=3, colour_opacity=True)
+    items = [(a.gaussians, a.planes, a.mlp, 0.2, None), (b.gaussians, b.planes, b.mlp, 0.9, None)]
+    c = oracle.compose(items, 3)
+    da = oracle.deform(a.gaussians, a.planes, a.mlp, 0.2)
+    db = oracle.deform(b.gaussians, b.planes, b.mlp, 0.9)
+    for k in ("means", "scales", "quats", "opacity"):
+        np.testing.assert_array_equal(getattr(c, k), np.concatenate([getattr(da, k), getattr(db, k)], -1))
+    assert c.sh.shape == (16, 3, 75)
+    np.testing.assert_array_equal(c.sh[:4, :, :30], a.gaussians.sh.astype(np.float64))
+    assert not c.sh[4:, :, :30].any()
+    np.testing.assert_array_equal(c.sh[:, :, 30:], db.sh)
+
+
+def test_placement_moves_means_and_covariances_rigidly():
+    """A placed Gaussian's mean is s R X + T and its covariance
+    s^2 R Sigma R^T, with R and Sigma built by scipy from the quaternions
+    (scalar-last there): pins the quaternion product and the scale."""
+    sc = synth.tiny_scene(62, n=25, sh_degree=0)
+    d = oracle.deform(sc.gaussians, sc.planes, sc.mlp, 0.5)
+    Q = Rotation.from_rotvec([0.4, -0.9, 1.3])
+    s, T = 1.7, np.array([0.5, -2.0, 3.0])
+    q_wxyz = np.roll(Q.as_quat(), 1)
+    p = oracle.place(d, q_wxyz * 2.5, s, T)      # the rotation need not be unit
+    np.testing.assert_allclose(p.means, s * Q.apply(d.means.T).T + T[:, None], rtol=0, atol=1e-13)
+    np.testing.assert_allclose(p.opacity, d.opacity, rtol=0, atol=0)
+    for i in range(d.means.shape[1]):
+        R0 = Rotation.from_quat(np.roll(d.quats[:, i], -1)).as_matrix()
+        S0 = np.diag(d.scales[:, i] ** 2)
+        R1 = Rotation.from_quat(np.roll(p.quats[:, i], -1)).as_matrix()
+        S1 = np.diag(p.scales[:, i] ** 2)
+        Q3 = Q.as_matrix()
+        np.testing.assert_allclose(R1 @ S1 @ R1.T, s * s * Q3 @ (R0 @ S0 @ R0.T) @ Q3.T, rtol=1e-12, atol=1e-15)
+        assert abs(np.linalg.norm(p.quats[:, i]) - 1.0) < 1e-14
+
+
+def test_placed_scene_projects_like_a_moved_camera():
+    """Placing a scene by a similarity (R, T, s) and moving the camera by the
+    same similarity leaves every projected position and conic unchanged
+    (the 2D covariance scales by s^2 / s^2) and multiplies depths by s."""
+    sc = synth.tiny_scene(63, n=40, sh_degree=0, log_scale_mean=-2.5)
+    d = oracle.deform(sc.gaussians, sc.planes, sc.mlp, 0.35)
+    Q = Rotation.from_rotvec([0.2, 0.7, -0.3])
+    s, T = 1.5, np.array([0.3, 0.1, -0.4])
+    p = oracle.place(d, np.roll(Q.as_quat(), 1), s, T)
+    eye, up = np.array([0.6, 0.3, 3.0]), np.array([0.0, 1.0, 0.0])
+    cam0 = synth.look_at_camera(eye, (0, 0, 0), 96, 80)
+    cam1 = synth.look_at_camera(s * Q.apply(eye) + T, T, 96, 80, up=Q.apply(up))
+    p0 = oracle.project(oracle.to_splats32(d, sc.gaussians.sh, 0), cam0)
+    p1 = oracle.project(oracle.to_splats32(p, sc.gaussians.sh, 0), cam1)
+    vis = p0.radius > 0
+    assert vis.sum() > 30
+    np.testing.assert_allclose(p1.f64[vis, :5], p0.f64[vis, :5], rtol=2e-4, atol=2e-3)
+    z0 = p0.depth_bits[vis].view(np.float32).astype(np.float64)
+    z1 = p1.depth_bits[vis].view(np.float32).astype(np.float64)
+    np.testing.assert_allclose(z1, s * z0, rtol=1e-5)
+
+
 def test_rotation_matrix_convention_matches_scipy():
     """Sigma = R S S^T R^T with R from scipy (scalar-last quaternion); checked
     through the projected covariance of an on-axis Gaussian seen by W = I."""
