@@ -1,0 +1,148 @@
+"""Pins of the gradient oracle (oracle/grad.py), CPU only.
+
+The FP64 torch forward is an implementation of its own; it is pinned to the
+C oracle's forward (deformation, SH basis, image) and its autograd gradient
+to central finite differences of that forward."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import grad as og
+from paper_2310_08528_amd import synth
+
+
+def _c1_subset(n=500, size=64, seed_t=0.5):
+    """The small configuration's generator at 500 Gaussians, 64x64."""
+    sc = synth.config1(plane_dist="uniform", n=n)
+    cam = synth.look_at_camera((0.0, 0.0, 4.0), (0.0, 0.0, 0.0), size, size, 50.0)
+    return sc, cam, seed_t
+
+
+def _structure(splats32, cam):
+    r = oracle.render(splats32, cam)
+    return r, r.ranges, r.vals
+
+
+def test_torch_deform_matches_the_c_oracle():
+    for sc in (synth.tiny_scene(3, n=64), synth.tiny_scene(7, n=80, sh_degree=2, colour_opacity=True)):
+        d = oracle.deform(sc.gaussians, sc.planes, sc.mlp, 0.41)
+        p = {k: og._t(getattr(sc.gaussians, k)) for k in og.CANON_KEYS}
+        pl = [[og._t(x) for x in lv] for lv in sc.planes.planes]
+        m = {k: (og._t(getattr(sc.mlp, k)) if getattr(sc.mlp, k, None) is not None else None) for k in og.MLP_KEYS}
+        with torch.no_grad():
+            t = og.deform_torch(p, pl, m, 0.41, sc.planes.bmin, sc.planes.bmax)
+        for k in ("means", "scales", "quats", "opacity"):
+            np.testing.assert_allclose(t[k].numpy(), getattr(d, k), rtol=1e-11, atol=1e-12)
+        if d.sh is not None:
+            np.testing.assert_allclose(t["sh"].numpy(), d.sh, rtol=1e-11, atol=1e-12)
+
+
+def test_cartesian_sh_basis_matches_the_closed_form():
+    rng = np.random.default_rng(4)
+    dirs = rng.normal(size=(3, 40))
+    dirs /= np.linalg.norm(dirs, axis=0)
+    Y = og.sh_basis_cartesian(3, torch.as_tensor(dirs)).numpy()
+    for l in range(4):
+        for m in range(-l, l + 1):
+            ref = [oracle.sh_basis(l, m, dirs[:, i]) for i in range(dirs.shape[1])]
+            np.testing.assert_allclose(Y[l * l + l + m], ref, rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.parametrize("seed,deg", [(0, 0), (2, 3)])
+def test_torch_render_matches_the_c_oracle(seed, deg):
+    sc = synth.tiny_scene(seed, sh_degree=deg)
+    d = oracle.deform(sc.gaussians, sc.planes, sc.mlp, 0.3)
+    s32 = oracle.to_splats32(d, sc.gaussians.sh, deg)
+    r, ranges, vals = _structure(s32, sc.cameras[0])
+    s = {k: og._t(getattr(s32, k)) for k in og.SPLAT_KEYS}
+    s["sh_degree"] = deg
+    with torch.no_grad():
+        img = og.render_torch(s, sc.cameras[0], ranges, vals).numpy()
+    ok = r.flag == 0
+    assert ok.mean() > 0.97
+    np.testing.assert_allclose(img[:, ok], r.image[:, ok], rtol=0, atol=1e-9)
+
+
+def _fd_check(f, params, grads, picks, eps=1e-6, rtol=2e-5):
+    """Central differences of the scalar f() at picked entries of params."""
+    worst = 0.0
+    for name, idx in picks:
+        x = params[name]
+        with torch.no_grad():
+            old = float(x[idx])
+            x[idx] = old + eps
+            fp = float(f())
+            x[idx] = old - eps
+            fm = float(f())
+            x[idx] = old
+        fd = (fp - fm) / (2 * eps)
+        g = float(grads[name][idx])
+        scale = max(np.abs(grads[name]).max(), 1e-12)
+        err = abs(fd - g) / scale
+        worst = max(worst, err)
+        assert err <= rtol, (name, idx, fd, g, scale)
+    return worst
+
+
+def test_render_gradient_matches_central_differences():
+    sc = synth.tiny_scene(5, n=48, sh_degree=2)
+    d = oracle.deform(sc.gaussians, sc.planes, sc.mlp, 0.3)
+    s32 = oracle.to_splats32(d, sc.gaussians.sh, 2)
+    cam = sc.cameras[0]
+    r, ranges, vals = _structure(s32, cam)
+    rng = np.random.default_rng(0)
+    w = rng.choice([-1.0, 1.0], size=r.image.shape) * (r.flag == 0)[None]
+    img, grads = og.render_grads(s32, cam, ranges, vals, w)
+    s = {k: og._t(getattr(s32, k)) for k in og.SPLAT_KEYS}
+    s["sh_degree"] = 2
+    wt = torch.as_tensor(w)
+    f = lambda: (wt * og.render_torch(s, cam, ranges, vals)).sum()
+    vis = np.nonzero(np.abs(grads["opacity"]) > 0)[0]
+    assert len(vis) > 20
+    picks = []
+    for gi in vis[:: max(1, len(vis) // 8)]:
+        picks += [("means", (0, gi)), ("means", (2, gi)), ("scales", (1, gi)), ("quats", (0, gi)),
+                  ("quats", (3, gi)), ("opacity", (gi,)), ("sh", (0, 1, gi)), ("sh", (5, 2, gi))]
+    _fd_check(f, s, grads, picks)
+
+
+def test_deform_render_gradient_matches_central_differences():
+    """Canonical parameters, plane cells and decoder weights, through the
+    deformation and the render (500 Gaussians, 64x64)."""
+    sc, cam, t = _c1_subset()
+    d = oracle.deform(sc.gaussians, sc.planes, sc.mlp, t)
+    s32 = oracle.to_splats32(d, sc.gaussians.sh, 0)
+    r, ranges, vals = _structure(s32, cam)
+    rng = np.random.default_rng(1)
+    w = rng.choice([-1.0, 1.0], size=r.image.shape) * (r.flag == 0)[None] / r.image[0].size
+    img, grads = og.deform_render_grads(sc.gaussians, sc.planes, sc.mlp, t, cam, ranges, vals, w)
+    p = {k: og._t(getattr(sc.gaussians, k)) for k in og.CANON_KEYS}
+    pl = [[og._t(x) for x in lv] for lv in sc.planes.planes]
+    m = {k: (og._t(getattr(sc.mlp, k)) if getattr(sc.mlp, k, None) is not None else None) for k in og.MLP_KEYS}
+    wt = torch.as_tensor(w)
+
+    def f():
+        dd = og.deform_torch(p, pl, m, t, sc.planes.bmin, sc.planes.bmax)
+        dd["sh_degree"] = 0
+        return (wt * og.render_torch(dd, cam, ranges, vals)).sum()
+    params = dict(p)
+    params.update({k: v for k, v in m.items() if v is not None})
+    flat = dict(grads)
+    for lvl in range(len(pl)):
+        for q in range(6):
+            params[f"plane{lvl}_{q}"] = pl[lvl][q]
+            flat[f"plane{lvl}_{q}"] = grads["planes"][lvl][q]
+    vis = np.nonzero(np.abs(grads["opacity_logits"]) > 0)[0]
+    assert len(vis) > 100
+    picks = []
+    for gi in vis[:: len(vis) // 6]:
+        picks += [("means", (0, gi)), ("log_scales", (2, gi)), ("quats", (1, gi)), ("opacity_logits", (gi,)),
+                  ("sh", (0, 0, gi))]
+    picks += [("w1", (3, 5)), ("b1", (7,)), ("wx", (1, 9)), ("bx", (2,)), ("wr", (0, 4)), ("ws", (2, 11)),
+              ("bs", (0,))]
+    for q in range(6):
+        gq = flat[f"plane0_{q}"]
+        big = np.unravel_index(np.argsort(np.abs(gq), axis=None)[-2:], gq.shape)
+        picks += [(f"plane0_{q}", tuple(int(i[k]) for i in big)) for k in range(2)]
+    _fd_check(f, params, flat, picks, eps=1e-6, rtol=5e-5)
