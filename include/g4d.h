@@ -155,6 +155,16 @@ typedef struct {
     int64_t instance_capacity;  /* max number of (Gaussian, tile) pairs, < 2^30 */
 } g4d_workspace;
 
+/* Gradients with respect to render-ready Gaussians (same layouts as
+ * g4d_splats). */
+typedef struct {
+    float *means;               /* [3][n] */
+    float *scales;              /* [3][n] */
+    float *quats;               /* [4][n] */
+    float *opacity;             /* [n] */
+    float *sh;                  /* [(d+1)^2][3][n] */
+} g4d_splats_grad;
+
 /* Device-side outcome of the last render on a workspace. */
 typedef struct {
     int64_t instances;          /* K: (Gaussian, tile) pairs the frame needed */
@@ -299,6 +309,24 @@ g4d_status g4d_render_export(const g4d_workspace *ws, int32_t kind, int32_t n, i
  * 4 instance offsets, 5 emit, 6 tile sort, 7 ranges, 8 blend.  count must
  * be 9; events == NULL turns recording off.  The caller owns the events. */
 g4d_status g4d_set_stage_events(void *const *events, int32_t count);
+
+/* ------------------------------------------------------------- backward */
+
+/* Gradient of a scalar loss L through the last g4d_render on `ws`
+ * (Eq. 1-4 and Eq. 2-3): given dL/dimage (grad_image, [3][H][W] like the
+ * image), writes dL/d(means, scales, quats, opacity, sh) of the render-ready
+ * Gaussians into `grad` (overwritten, not accumulated; zero for Gaussians
+ * that touch no pixel).  The render must have been called with these G and C
+ * and with final_T and n_contrib outputs, which are passed here unchanged;
+ * the workspace must not have been used since.  Per-tile recomputation: each
+ * pixel walks its tile's list back to front from its final transmittance and
+ * last contributing entry, redoing the forward's binary32 alpha (so skip and
+ * stop decisions are the forward's); alpha clamped at 0.99 passes no
+ * gradient to opacity or position.  Gradients with respect to the camera are
+ * not computed.  Device pointers; the call allocates nothing. */
+g4d_status g4d_render_backward(const g4d_splats *G, const g4d_camera *C, const g4d_workspace *ws,
+                               const float *final_T, const int32_t *n_contrib, const float *grad_image,
+                               const g4d_splats_grad *grad, void *stream);
 
 /* -------------------------------------------------------------- utilities */
 

@@ -29,6 +29,7 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
           "-I", os.path.join(ROOT, "include"), "-Wno-unused-command-line-argument"]
 PER_FILE = {
     "raster.hip": ["-ffp-contract=off"],
+    "render_bwd.hip": ["-ffp-contract=off"],   # the forward's alpha, bit for bit
 }
 
 

@@ -68,6 +68,7 @@ struct WsLayout {
     size_t tcnt, tdtot;  // instance sort: per-pass digit counts [256][nblk_k] and digit totals [256]
     size_t order;        // blend order of the tiles (longest list first): (tile, start, end, 0)
     size_t evals;        // per tile: (pixel, Gaussian) pairs the blend evaluated (u64)
+    size_t grad2d;       // render backward: per Gaussian dL/d(u, v, conic A B C, colour r g b, opacity), [9][n]
     size_t total;
 };
 
@@ -110,6 +111,7 @@ inline bool make_layout(int32_t n, int32_t w, int32_t h, int64_t cap, WsLayout *
     L->tdtot = take((size_t)2 * 256 * 4);
     L->order = take((size_t)L->tiles_max * 16);
     L->evals = take((size_t)L->tiles_max * 8);
+    L->grad2d = take((size_t)nn * 9 * 4);
     L->total = o;
     return true;
 }
@@ -143,6 +145,9 @@ g4d_status render(const g4d_splats *G, const g4d_camera *C, const g4d_workspace 
                   float *final_T, int32_t *n_contrib, hipStream_t s);
 g4d_status read_status(const g4d_workspace *ws, g4d_device_status *out, hipStream_t s);
 g4d_status deform_batched(const g4d_deform_job *jobs, int n_jobs, hipStream_t s);
+g4d_status render_backward(const g4d_splats *G, const g4d_camera *C, const g4d_workspace *ws,
+                           const float *final_T, const int32_t *n_contrib, const float *grad_image,
+                           const g4d_splats_grad *out, hipStream_t s);
 g4d_status graph_find_camera_node(hipGraph_t g, hipGraphNode_t *out);
 g4d_status graph_set_frame(hipGraphExec_t exec, hipGraphNode_t node, const g4d_workspace *ws,
                            const g4d_camera *C, float *image, float *final_T, int32_t *n_contrib);

@@ -50,6 +50,10 @@ class Splats(ctypes.Structure):
                 ("opacity", c_p), ("sh", c_p)]
 
 
+class SplatsGrad(ctypes.Structure):
+    _fields_ = [("means", c_p), ("scales", c_p), ("quats", c_p), ("opacity", c_p), ("sh", c_p)]
+
+
 class Camera(ctypes.Structure):
     _fields_ = [("width", c_i32), ("height", c_i32), ("viewmat", c_f32 * 12), ("fx", c_f32),
                 ("fy", c_f32), ("cx", c_f32), ("cy", c_f32), ("tan_half_fov_x", c_f32),
@@ -119,6 +123,8 @@ SIGNATURES = {
     "g4d_render_workspace_bytes": (c_sz, [c_i32, c_i32, c_i32, c_i64]),
     "g4d_render": (c_i32, [ctypes.POINTER(Splats), ctypes.POINTER(Camera), ctypes.POINTER(Workspace), c_p, c_p,
                            c_p, c_p]),
+    "g4d_render_backward": (c_i32, [ctypes.POINTER(Splats), ctypes.POINTER(Camera), ctypes.POINTER(Workspace),
+                                    c_p, c_p, c_p, ctypes.POINTER(SplatsGrad), c_p]),
     "g4d_read_status": (c_i32, [ctypes.POINTER(Workspace), ctypes.POINTER(DeviceStatus), c_p]),
     "g4d_render_export": (c_i32, [ctypes.POINTER(Workspace), c_i32, c_i32, c_i64, c_p, c_sz, c_p]),
     "g4d_set_stage_events": (c_i32, [ctypes.POINTER(c_p), c_i32]),
@@ -374,6 +380,30 @@ def render(S: DeviceSplats, cam, ws: RenderWorkspace, image, final_T=None, n_con
     cs = cam if isinstance(cam, Camera) else camera_struct(cam)
     check(load().g4d_render(ctypes.byref(ss), ctypes.byref(cs), ctypes.byref(ws.ws), _ptr(image), _ptr(final_T),
                             _ptr(n_contrib), _stream(stream)), "g4d_render")
+
+
+class DeviceSplatsGrad:
+    """Gradients with respect to render-ready Gaussians, device tensors."""
+
+    def __init__(self, n, sh_degree, device):
+        import torch
+        e = lambda *shape: torch.empty(shape, dtype=torch.float32, device=device)
+        self.n, self.sh_degree = int(n), int(sh_degree)
+        self.means, self.scales, self.quats = e(3, n), e(3, n), e(4, n)
+        self.opacity, self.sh = e(n), e((sh_degree + 1) ** 2, 3, n)
+
+    def struct(self) -> SplatsGrad:
+        return SplatsGrad(_ptr(self.means), _ptr(self.scales), _ptr(self.quats), _ptr(self.opacity), _ptr(self.sh))
+
+
+def render_backward(S: DeviceSplats, cam, ws: RenderWorkspace, final_T, n_contrib, grad_image,
+                    grad: DeviceSplatsGrad, stream=None):
+    """dL/d(render-ready Gaussians) through the last render on ``ws``."""
+    ss, gs = S.struct(), grad.struct()
+    cs = cam if isinstance(cam, Camera) else camera_struct(cam)
+    check(load().g4d_render_backward(ctypes.byref(ss), ctypes.byref(cs), ctypes.byref(ws.ws), _ptr(final_T),
+                                     _ptr(n_contrib), _ptr(grad_image), ctypes.byref(gs), _stream(stream)),
+          "g4d_render_backward")
 
 
 def read_status(ws: RenderWorkspace, stream=None) -> DeviceStatus:

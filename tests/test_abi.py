@@ -63,6 +63,7 @@ _STRUCTS = {
     "g4d_device_status": g4d.DeviceStatus, "g4d_deform_job": g4d.DeformJob,
     "g4d_server_config": g4d.ServerConfig, "g4d_server_stats": g4d.ServerStats,
     "g4d_sim_config": g4d.SimConfig, "g4d_sim_result": g4d.SimResult,
+    "g4d_splats_grad": g4d.SplatsGrad, "g4d_placement": g4d.Placement, "g4d_compose_item": g4d.ComposeItem,
 }
 
 
@@ -165,3 +166,8 @@ def test_compose_arguments_are_validated_on_the_host():
     assert call([ok], out_deg=0) == g4d.EINVAL               # an item's SH degree above the output's
     assert call([ok], n_items=0) == g4d.EINVAL
     assert call([ok] * (g4d.MAX_COMPOSE_ITEMS + 1)) == g4d.EINVAL
+
+
+def test_render_backward_arguments_are_validated_on_the_host():
+    lib = g4d.load()
+    assert lib.g4d_render_backward(None, None, None, None, None, None, None, None) == g4d.EINVAL
