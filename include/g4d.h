@@ -328,6 +328,34 @@ g4d_status g4d_render_backward(const g4d_splats *G, const g4d_camera *C, const g
                                const float *final_T, const int32_t *n_contrib, const float *grad_image,
                                const g4d_splats_grad *grad, void *stream);
 
+/* Gradients with respect to the deformation's inputs: the canonical
+ * Gaussians (same layouts as g4d_gaussians), every plane cell (same layouts
+ * as g4d_planes) and the decoder weights (same layouts as g4d_mlp; the
+ * colour / opacity head entries are used when the decoder has them). */
+typedef struct {
+    float *means;               /* [3][n] */
+    float *log_scales;          /* [3][n] */
+    float *quats;               /* [4][n] */
+    float *opacity_logits;      /* [n] */
+    float *sh;                  /* [(d+1)^2][3][n], or NULL when not wanted */
+    float *plane[G4D_MAX_SCALES][6];
+    float *w1, *b1, *wx, *bx, *wr, *br, *ws, *bs;
+    float *wc, *bc, *wa, *ba;
+} g4d_deform_grad;
+
+/* Gradient of a scalar loss L through g4d_deform (Sec. 4.2, Eq. 7-8): given
+ * dL/d(render-ready set) in grad_out (e.g. from g4d_render_backward),
+ * writes dL/d(canonical Gaussians) and accumulates, from zero, dL/d(plane
+ * cells) and dL/d(decoder weights) into `grad` (the call clears them first).
+ * The forward is recomputed (nothing from it is kept); plane gradients are
+ * an atomic scatter of the bilinear weights; the grid coordinates carry the
+ * bilinear slopes, zero for a mean on or outside the box border (where the
+ * query is clamped) and for the time axis (t is not a parameter).
+ * FP32 decoder only (G4D_EUNSUPPORTED for G4D_MLP_BF16).  Device pointers;
+ * the call allocates nothing. */
+g4d_status g4d_deform_backward(const g4d_gaussians *G, const g4d_planes *P, const g4d_mlp *M, float t,
+                               const g4d_splats_grad *grad_out, const g4d_deform_grad *grad, void *stream);
+
 /* -------------------------------------------------------------- utilities */
 
 const char *g4d_status_string(int32_t status);

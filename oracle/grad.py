@@ -229,6 +229,60 @@ def render_grads(splats, cam, ranges, vals, weight):
     return img.detach().numpy(), {k: s[k].grad.numpy() for k in SPLAT_KEYS}
 
 
+def _leaf_inputs(g, planes, mlp):
+    p = {k: _t(getattr(g, k), True) for k in CANON_KEYS}
+    pl = [[_t(x, True) for x in lv] for lv in planes.planes]
+    m = {k: (_t(getattr(mlp, k), True) if getattr(mlp, k, None) is not None else None) for k in MLP_KEYS}
+    return p, pl, m
+
+
+def _collect(p, pl, m):
+    grads = {k: (p[k].grad.numpy() if p[k].grad is not None else np.zeros(tuple(p[k].shape)))
+             for k in CANON_KEYS}
+    grads["planes"] = [[x.grad.numpy() for x in lv] for lv in pl]
+    for k in MLP_KEYS:
+        if m[k] is not None:
+            grads[k] = m[k].grad.numpy()
+    return grads
+
+
+def relu_flags(g, planes, mlp, t, rel: float = 1e-5):
+    """Gaussians with a hidden unit whose FP64 pre-activation W1 f_h + b1 lies
+    within rel x (sum |W1 f_h| + |b1|) of zero: there the ReLU decision of a
+    binary32 forward may differ from FP64's, and the gradient with it."""
+    p, pl, m = _leaf_inputs(g, planes, mlp)
+    with torch.no_grad():
+        feats = []
+        n = p["means"].shape[1]
+        lo = torch.as_tensor(np.asarray(planes.bmin, np.float64), dtype=F64)[:, None]
+        hi = torch.as_tensor(np.asarray(planes.bmax, np.float64), dtype=F64)[:, None]
+        u = 2.0 * (p["means"] - lo) / (hi - lo) - 1.0
+        u = torch.cat([u, torch.full((1, n), 2.0 * t - 1.0, dtype=F64)], 0)
+        for lv in pl:
+            f = torch.ones((lv[0].shape[2], n), dtype=F64)
+            for x, (a, b) in zip(lv, _PLANES):
+                grid = torch.stack([u[a], u[b]], -1)[None, None]
+                f = f * torch.nn.functional.grid_sample(x.permute(2, 0, 1)[None], grid, mode="bilinear",
+                                                        padding_mode="border", align_corners=True)[0, :, 0, :]
+            feats.append(f)
+        fh = torch.cat(feats, 0).T
+        pre = fh @ m["w1"].T + m["b1"]
+        mag = fh.abs() @ m["w1"].abs().T + m["b1"].abs()
+        return ((pre.abs() <= rel * mag).any(dim=1)).numpy()
+
+
+def deform_grads(g, planes, mlp, t, gout):
+    """Gradient of L = sum_k <gout[k], deform(...)[k]> (k over means, scales,
+    quats, opacity, sh) with respect to the canonical Gaussians, every plane
+    cell and the decoder weights, FP64."""
+    p, pl, m = _leaf_inputs(g, planes, mlp)
+    d = deform_torch(p, pl, m, t, planes.bmin, planes.bmax)
+    loss = sum((torch.as_tensor(np.asarray(gout[k], np.float64)).reshape(d[k].shape) * d[k]).sum()
+               for k in SPLAT_KEYS)
+    loss.backward()
+    return _collect(p, pl, m)
+
+
 MLP_KEYS = ("w1", "b1", "wx", "bx", "wr", "br", "ws", "bs", "wc", "bc", "wa", "ba")
 CANON_KEYS = ("means", "log_scales", "quats", "opacity_logits", "sh")
 
@@ -238,17 +292,10 @@ def deform_render_grads(g, planes, mlp, t, cam, ranges, vals, weight):
     with respect to the canonical Gaussians, every plane cell and the
     decoder weights, FP64.  Returns (image, grads) with grads["planes"] a
     list over scales of six arrays shaped like the planes."""
-    p = {k: _t(getattr(g, k), True) for k in CANON_KEYS}
-    pl = [[_t(x, True) for x in lv] for lv in planes.planes]
-    m = {k: (_t(getattr(mlp, k), True) if getattr(mlp, k, None) is not None else None) for k in MLP_KEYS}
+    p, pl, m = _leaf_inputs(g, planes, mlp)
     d = deform_torch(p, pl, m, t, planes.bmin, planes.bmax)
     d["sh_degree"] = int(g.sh_degree)
     img = render_torch(d, cam, ranges, vals)
     loss = (torch.as_tensor(np.asarray(weight, np.float64)) * img).sum()
     loss.backward()
-    grads = {k: p[k].grad.numpy() for k in CANON_KEYS}
-    grads["planes"] = [[x.grad.numpy() for x in lv] for lv in pl]
-    for k in MLP_KEYS:
-        if m[k] is not None:
-            grads[k] = m[k].grad.numpy()
-    return img.detach().numpy(), grads
+    return img.detach().numpy(), _collect(p, pl, m)

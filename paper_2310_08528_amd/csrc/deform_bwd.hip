@@ -1,0 +1,496 @@
+// Backward of the Gaussian deformation field on gfx950 (Sec. 4.2, Eq. 7-8).
+//
+// One 256-thread block per 64 Gaussians, FP32 decoder.  The block first
+// recomputes the forward (encoder f_h, hidden h, head outputs) in LDS, then:
+//   Eq. 8 + activations   d(X + dX) -> dX and dX_canonical; d exp(log s + ds)
+//                         -> d log s = d ds = ds' s'; d normalise(r + dr) ->
+//                         (I - r' r'^T) dr' / |r + dr|; d sigmoid(logit
+//                         [+ dalpha]) -> s (1 - s) do'; C [+ dC] -> dC = dC'.
+//   heads                 dh = W2^T ddelta (ReLU mask), dW2 += ddelta h^T,
+//                         db2 += ddelta (block sums, one atomic per weight)
+//   feature merger        dW1 += dz f_h^T, db1 += dz, df_h = W1^T dz
+//   encoder (Eq. 7)       per scale, the product rule over the six planes
+//                         (prefix and suffix products), then the bilinear
+//                         query's four corners receive weight x gradient by
+//                         atomic scatter into the plane gradients, and the
+//                         grid coordinates receive the bilinear slopes
+//                         (zero at and beyond the box border, as the border
+//                         clamp of the query has no slope there).
+// Weights are read from global memory (L1/L2-resident: every block reads
+// them); f_h, h, the deltas and dz live in LDS.
+#include "g4d_internal.h"
+
+#include <vector>
+
+namespace g4d {
+namespace {
+
+constexpr int kGB = 64;
+constexpr int kThreads = 256;
+constexpr int kMaxScalesB = 3;
+
+struct BwdJob {
+    const float *means, *log_scales, *quats, *opac, *sh;
+    const float *planes[kMaxScalesB * 6];
+    const float *w1, *b1;
+    const float *hw[5], *hb[5];          // head weights / biases: dx, dr, ds, dC, dalpha (null when absent)
+    int hrows[5];                        // rows of each head (3, 4, 3, 3 (d+1)^2 or 0, 1 or 0)
+    const float *g_means, *g_scales, *g_quats, *g_opac, *g_sh;   // dL/d render-ready set
+    float *d_means, *d_log_scales, *d_quats, *d_opac, *d_sh;     // canonical (written)
+    float *d_planes[kMaxScalesB * 6];    // accumulated
+    float *d_w1, *d_b1;
+    float *d_hw[5], *d_hb[5];
+    int res[kMaxScalesB][4];
+    float gscale[kMaxScalesB][4];
+    float bmin[3], bmax[3];
+    int n, n_sh_rows;                    // n_sh_rows: 3 (d+1)^2 of the Gaussians
+    float t;
+};
+
+__device__ constexpr int axis_a(int p) { return p == 2 ? 1 : (p == 5 ? 2 : (p == 4 ? 1 : 0)); }
+__device__ constexpr int axis_b(int p) { return p == 0 ? 1 : (p == 1 || p == 2 ? 2 : 3); }
+
+__device__ __forceinline__ void grid_coord(float x, float scale, int n, int &i0, float &w) {
+    float g = x * scale;
+    g = fminf(fmaxf(g, 0.0f), (float)(n - 1));
+    int i = (int)floorf(g);
+    i = min(i, n - 2);
+    i0 = i;
+    w = g - (float)i;
+}
+
+// Head row r of the concatenated heads: (head, row within it)
+__device__ __forceinline__ bool head_of(const BwdJob &J, int r, int &h, int &k) {
+    int base = 0;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        if (r < base + J.hrows[q]) {
+            h = q;
+            k = r - base;
+            return true;
+        }
+        base += J.hrows[q];
+    }
+    return false;
+}
+
+template <int F, int L, int HID>
+__global__ __launch_bounds__(kThreads) void k_deform_bwd(BwdJob J, int rows) {
+    constexpr int K = F * L;
+    constexpr int FH = K + 1, HH = HID + 1, DS = 65;
+    extern __shared__ __attribute__((aligned(16))) float smem[];
+    float *s_fh = smem;                  // [64][K+1]: f_h, later df_h
+    float *s_h = s_fh + kGB * FH;        // [64][HID+1]: h (after ReLU)
+    float *s_dz = s_h + kGB * HH;        // [64][HID+1]: dL/d(pre-activation)
+    float *s_dd = s_dz + kGB * HH;       // [64][65]: head outputs, then their gradients
+    float *s_dm = s_dd + kGB * DS;       // [64][3]: dL/d canonical mean
+    const int tid = threadIdx.x;
+    const int g0 = blockIdx.x * kGB;
+    const int n = J.n;
+
+    // ---- A. encoder (as in the forward)
+    constexpr int LPG = F / 4;
+    constexpr int GPP = kThreads / LPG;
+#pragma unroll
+    for (int pass = 0; pass < kGB / GPP; ++pass) {
+        const int gl = pass * GPP + tid / LPG, c4 = tid % LPG, g = g0 + gl;
+        const bool valid = g < n;
+        float x[4];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) x[k] = valid ? J.means[(size_t)k * n + g] - J.bmin[k] : 0.0f;
+        x[3] = J.t;
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            float4 prod = make_float4(1.f, 1.f, 1.f, 1.f);
+#pragma unroll
+            for (int p = 0; p < 6; ++p) {
+                const int a = axis_a(p), b = axis_b(p);
+                const int na = J.res[l][a], nb = J.res[l][b];
+                int ia, ib;
+                float wa, wb;
+                grid_coord(x[a], J.gscale[l][a], na, ia, wa);
+                grid_coord(x[b], J.gscale[l][b], nb, ib, wb);
+                const float *base = J.planes[l * 6 + p] + ((size_t)ib * na + ia) * F + 4 * c4;
+                const float4 v00 = *reinterpret_cast<const float4 *>(base);
+                const float4 v10 = *reinterpret_cast<const float4 *>(base + F);
+                const float4 v01 = *reinterpret_cast<const float4 *>(base + (size_t)na * F);
+                const float4 v11 = *reinterpret_cast<const float4 *>(base + (size_t)na * F + F);
+                const float w00 = (1.0f - wa) * (1.0f - wb), w10 = wa * (1.0f - wb);
+                const float w01 = (1.0f - wa) * wb, w11 = wa * wb;
+                prod.x *= w00 * v00.x + w10 * v10.x + w01 * v01.x + w11 * v11.x;
+                prod.y *= w00 * v00.y + w10 * v10.y + w01 * v01.y + w11 * v11.y;
+                prod.z *= w00 * v00.z + w10 * v10.z + w01 * v01.z + w11 * v11.z;
+                prod.w *= w00 * v00.w + w10 * v10.w + w01 * v01.w + w11 * v11.w;
+            }
+            if (!valid) prod = make_float4(0.f, 0.f, 0.f, 0.f);
+            float *dst = s_fh + gl * FH + l * F + 4 * c4;
+            dst[0] = prod.x; dst[1] = prod.y; dst[2] = prod.z; dst[3] = prod.w;
+        }
+    }
+    __syncthreads();
+    // ---- B. h = ReLU(W1 f_h + b1); Gaussian fastest, so a weight is one broadcast load
+    for (int idx = tid; idx < kGB * HID; idx += kThreads) {
+        const int g = idx % kGB, j = idx / kGB;
+        float acc = J.b1[j];
+        const float *w = J.w1 + (size_t)j * K;
+        for (int i = 0; i < K; ++i) acc += w[i] * s_fh[g * FH + i];
+        s_h[g * HH + j] = fmaxf(acc, 0.0f);
+    }
+    __syncthreads();
+    // ---- C. head outputs delta = W2 h + b2
+    for (int idx = tid; idx < kGB * rows; idx += kThreads) {
+        const int g = idx % kGB, r = idx / kGB;
+        int hq, k;
+        float acc = 0.0f;
+        if (head_of(J, r, hq, k)) {
+            acc = J.hb[hq][k];
+            const float *w = J.hw[hq] + (size_t)k * HID;
+            for (int j = 0; j < HID; ++j) acc += w[j] * s_h[g * HH + j];
+        }
+        s_dd[g * DS + r] = acc;
+    }
+    __syncthreads();
+    // ---- Eq. 8 + activations, backward (one Gaussian per thread of wave 0);
+    // the other waves copy the SH gradient (C' = C [+ dC]: dL/dC = dL/dC')
+    if (tid < kGB) {
+        const int gl = tid, g = g0 + gl;
+        float *dd = s_dd + gl * DS;
+        if (g < n) {
+            // means: X' = X + dX
+            for (int k = 0; k < 3; ++k) {
+                const float gm = J.g_means[(size_t)k * n + g];
+                dd[k] = gm;
+                s_dm[gl * 3 + k] = gm;
+            }
+            // quaternion: r' = (r + dr) / |r + dr|
+            float q[4], gq[4], qn = 0.0f;
+            for (int k = 0; k < 4; ++k) {
+                q[k] = J.quats[(size_t)k * n + g] + dd[3 + k];
+                gq[k] = J.g_quats[(size_t)k * n + g];
+                qn += q[k] * q[k];
+            }
+            float dq[4] = {0.f, 0.f, 0.f, 0.f};
+            if (qn > 0.0f) {
+                const float inv = 1.0f / sqrtf(qn);
+                float dot = 0.0f;
+                for (int k = 0; k < 4; ++k) dot += q[k] * inv * gq[k];
+                for (int k = 0; k < 4; ++k) dq[k] = (gq[k] - q[k] * inv * dot) * inv;
+            }
+            for (int k = 0; k < 4; ++k) {
+                dd[3 + k] = dq[k];
+                J.d_quats[(size_t)k * n + g] = dq[k];
+            }
+            // scales: s' = exp(log s + ds)
+            for (int k = 0; k < 3; ++k) {
+                const float sc = expf(J.log_scales[(size_t)k * n + g] + dd[7 + k]);
+                const float d = J.g_scales[(size_t)k * n + g] * sc;
+                dd[7 + k] = d;
+                J.d_log_scales[(size_t)k * n + g] = d;
+            }
+            // colour head: dC rows
+            const int nc = J.hrows[3];
+            for (int r = 0; r < nc; ++r) dd[10 + r] = J.g_sh[(size_t)r * n + g];
+            // opacity: o' = sigmoid(logit [+ dalpha])
+            const float logit = J.opac[g] + (J.hrows[4] ? dd[10 + nc] : 0.0f);
+            const float sg = 1.0f / (1.0f + expf(-logit));
+            const float dl = J.g_opac[g] * sg * (1.0f - sg);
+            J.d_opac[g] = dl;
+            if (J.hrows[4]) dd[10 + nc] = dl;
+            for (int r = 10 + nc + J.hrows[4]; r < rows; ++r) dd[r] = 0.0f;
+        } else {
+            for (int r = 0; r < rows; ++r) dd[r] = 0.0f;
+            for (int k = 0; k < 3; ++k) s_dm[gl * 3 + k] = 0.0f;
+        }
+    } else if (J.d_sh) {
+        for (int idx = tid - kGB; idx < kGB * J.n_sh_rows; idx += kThreads - kGB) {
+            const int gl = idx % kGB, r = idx / kGB, g = g0 + gl;
+            if (g < n) J.d_sh[(size_t)r * n + g] = J.g_sh[(size_t)r * n + g];
+        }
+    }
+    __syncthreads();
+    // ---- heads backward: dz = (W2^T ddelta) * [h > 0]
+    for (int idx = tid; idx < kGB * HID; idx += kThreads) {
+        const int g = idx % kGB, j = idx / kGB;
+        float acc = 0.0f;
+        for (int r = 0; r < rows; ++r) {
+            int hq, k;
+            if (head_of(J, r, hq, k)) acc += J.hw[hq][(size_t)k * HID + j] * s_dd[g * DS + r];
+        }
+        s_dz[g * HH + j] = s_h[g * HH + j] > 0.0f ? acc : 0.0f;
+    }
+    // dW2 += ddelta h^T, db2 += ddelta (sums over the block's Gaussians)
+    for (int idx = tid; idx < rows * (HID + 1); idx += kThreads) {
+        const int r = idx / (HID + 1), j = idx % (HID + 1);
+        int hq, k;
+        if (!head_of(J, r, hq, k)) continue;
+        float acc = 0.0f;
+        if (j < HID) {
+            for (int g = 0; g < kGB; ++g) acc += s_dd[g * DS + r] * s_h[g * HH + j];
+            if (acc != 0.0f) atomicAdd(&J.d_hw[hq][(size_t)k * HID + j], acc);
+        } else {
+            for (int g = 0; g < kGB; ++g) acc += s_dd[g * DS + r];
+            if (acc != 0.0f) atomicAdd(&J.d_hb[hq][k], acc);
+        }
+    }
+    __syncthreads();
+    // ---- feature merger: dW1 += dz f_h^T, db1 += dz
+    for (int idx = tid; idx < HID * (K + 1); idx += kThreads) {
+        const int j = idx / (K + 1), i = idx % (K + 1);
+        float acc = 0.0f;
+        if (i < K) {
+            for (int g = 0; g < kGB; ++g) acc += s_dz[g * HH + j] * s_fh[g * FH + i];
+            if (acc != 0.0f) atomicAdd(&J.d_w1[(size_t)j * K + i], acc);
+        } else {
+            for (int g = 0; g < kGB; ++g) acc += s_dz[g * HH + j];
+            if (acc != 0.0f) atomicAdd(&J.d_b1[j], acc);
+        }
+    }
+    __syncthreads();
+    // df_h = W1^T dz (overwrites f_h)
+    for (int idx = tid; idx < kGB * K; idx += kThreads) {
+        const int g = idx % kGB, i = idx / kGB;
+        float acc = 0.0f;
+        for (int j = 0; j < HID; ++j) acc += J.w1[(size_t)j * K + i] * s_dz[g * HH + j];
+        s_fh[g * FH + i] = acc;
+    }
+    __syncthreads();
+    // ---- encoder backward (Eq. 7)
+#pragma unroll
+    for (int pass = 0; pass < kGB / GPP; ++pass) {
+        const int gl = pass * GPP + tid / LPG, c4 = tid % LPG, g = g0 + gl;
+        const bool valid = g < n;
+        float x[4];
+        bool inner[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const float m = valid ? J.means[(size_t)k * n + g] : J.bmin[k];
+            x[k] = m - J.bmin[k];
+            inner[k] = m > J.bmin[k] && m < J.bmax[k];   // strictly inside the box: the clamp has slope 1
+        }
+        x[3] = J.t;
+        float dx3[3] = {0.f, 0.f, 0.f};
+        if (valid) {
+#pragma unroll
+            for (int l = 0; l < L; ++l) {
+                float4 val[6];
+                float wa_[6], wb_[6];
+                size_t off[6];
+                int na_[6];
+#pragma unroll
+                for (int p = 0; p < 6; ++p) {
+                    const int a = axis_a(p), b = axis_b(p);
+                    const int na = J.res[l][a], nb = J.res[l][b];
+                    int ia, ib;
+                    float wa, wb;
+                    grid_coord(x[a], J.gscale[l][a], na, ia, wa);
+                    grid_coord(x[b], J.gscale[l][b], nb, ib, wb);
+                    off[p] = ((size_t)ib * na + ia) * F + 4 * c4;
+                    na_[p] = na;
+                    wa_[p] = wa;
+                    wb_[p] = wb;
+                    const float *base = J.planes[l * 6 + p] + off[p];
+                    const float4 v00 = *reinterpret_cast<const float4 *>(base);
+                    const float4 v10 = *reinterpret_cast<const float4 *>(base + F);
+                    const float4 v01 = *reinterpret_cast<const float4 *>(base + (size_t)na * F);
+                    const float4 v11 = *reinterpret_cast<const float4 *>(base + (size_t)na * F + F);
+                    const float w00 = (1.0f - wa) * (1.0f - wb), w10 = wa * (1.0f - wb);
+                    const float w01 = (1.0f - wa) * wb, w11 = wa * wb;
+                    val[p].x = w00 * v00.x + w10 * v10.x + w01 * v01.x + w11 * v11.x;
+                    val[p].y = w00 * v00.y + w10 * v10.y + w01 * v01.y + w11 * v11.y;
+                    val[p].z = w00 * v00.z + w10 * v10.z + w01 * v01.z + w11 * v11.z;
+                    val[p].w = w00 * v00.w + w10 * v10.w + w01 * v01.w + w11 * v11.w;
+                }
+                const float *df = s_fh + gl * FH + l * F + 4 * c4;
+                const float4 dF = make_float4(df[0], df[1], df[2], df[3]);
+                // products of the other five planes: prefix x suffix
+                float4 pre[6], suf[6];
+                pre[0] = make_float4(1.f, 1.f, 1.f, 1.f);
+                suf[5] = pre[0];
+#pragma unroll
+                for (int p = 1; p < 6; ++p) {
+                    pre[p] = make_float4(pre[p - 1].x * val[p - 1].x, pre[p - 1].y * val[p - 1].y,
+                                         pre[p - 1].z * val[p - 1].z, pre[p - 1].w * val[p - 1].w);
+                    const int q = 5 - p;
+                    suf[q] = make_float4(suf[q + 1].x * val[q + 1].x, suf[q + 1].y * val[q + 1].y,
+                                         suf[q + 1].z * val[q + 1].z, suf[q + 1].w * val[q + 1].w);
+                }
+#pragma unroll
+                for (int p = 0; p < 6; ++p) {
+                    const float4 dv = make_float4(dF.x * pre[p].x * suf[p].x, dF.y * pre[p].y * suf[p].y,
+                                                  dF.z * pre[p].z * suf[p].z, dF.w * pre[p].w * suf[p].w);
+                    const float wa = wa_[p], wb = wb_[p];
+                    const float w00 = (1.0f - wa) * (1.0f - wb), w10 = wa * (1.0f - wb);
+                    const float w01 = (1.0f - wa) * wb, w11 = wa * wb;
+                    float *gb = J.d_planes[l * 6 + p] + off[p];
+                    const size_t rowF = (size_t)na_[p] * F;
+                    const float dvv[4] = {dv.x, dv.y, dv.z, dv.w};
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        if (dvv[c] == 0.0f) continue;
+                        if (w00 != 0.0f) atomicAdd(gb + c, w00 * dvv[c]);
+                        if (w10 != 0.0f) atomicAdd(gb + F + c, w10 * dvv[c]);
+                        if (w01 != 0.0f) atomicAdd(gb + rowF + c, w01 * dvv[c]);
+                        if (w11 != 0.0f) atomicAdd(gb + rowF + F + c, w11 * dvv[c]);
+                    }
+                    // slopes of the bilinear query along its two grid axes
+                    const int a = axis_a(p), b = axis_b(p);
+                    const float *base = J.planes[l * 6 + p] + off[p];
+                    const float4 v00 = *reinterpret_cast<const float4 *>(base);
+                    const float4 v10 = *reinterpret_cast<const float4 *>(base + F);
+                    const float4 v01 = *reinterpret_cast<const float4 *>(base + rowF);
+                    const float4 v11 = *reinterpret_cast<const float4 *>(base + rowF + F);
+                    const float sa = dv.x * ((1.0f - wb) * (v10.x - v00.x) + wb * (v11.x - v01.x)) +
+                                     dv.y * ((1.0f - wb) * (v10.y - v00.y) + wb * (v11.y - v01.y)) +
+                                     dv.z * ((1.0f - wb) * (v10.z - v00.z) + wb * (v11.z - v01.z)) +
+                                     dv.w * ((1.0f - wb) * (v10.w - v00.w) + wb * (v11.w - v01.w));
+                    const float sb = dv.x * ((1.0f - wa) * (v01.x - v00.x) + wa * (v11.x - v10.x)) +
+                                     dv.y * ((1.0f - wa) * (v01.y - v00.y) + wa * (v11.y - v10.y)) +
+                                     dv.z * ((1.0f - wa) * (v01.z - v00.z) + wa * (v11.z - v10.z)) +
+                                     dv.w * ((1.0f - wa) * (v01.w - v00.w) + wa * (v11.w - v10.w));
+                    if (a < 3 && inner[a]) dx3[a] += sa * J.gscale[l][a];
+                    if (b < 3 && inner[b]) dx3[b] += sb * J.gscale[l][b];
+                }
+            }
+        }
+        // sum over the LPG lanes of this Gaussian
+#pragma unroll
+        for (int o = LPG / 2; o >= 1; o >>= 1) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) dx3[k] += __shfl_xor(dx3[k], o, 64);
+        }
+        if (c4 == 0 && valid) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) s_dm[gl * 3 + k] += dx3[k];
+        }
+    }
+    __syncthreads();
+    if (tid < kGB && g0 + tid < n) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) J.d_means[(size_t)k * n + g0 + tid] = s_dm[tid * 3 + k];
+    }
+}
+
+// Up to 40 arrays cleared in one launch.
+struct FillList {
+    float *ptr[40];
+    uint32_t count[40];
+    int n;
+};
+
+__global__ void k_fill_list(FillList f) {
+    const int a = blockIdx.y;
+    if (a >= f.n) return;
+    float *p = f.ptr[a];
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < f.count[a]; i += gridDim.x * blockDim.x) p[i] = 0.0f;
+}
+
+using BwdKernel = void (*)(BwdJob, int);
+struct BwdEntry {
+    int feat, scales, hidden;
+    BwdKernel fn;
+};
+#define G4D_BWD_ENTRY(F, L, H) {F, L, H, k_deform_bwd<F, L, H>}
+const BwdEntry kBwdKernels[] = {
+    G4D_BWD_ENTRY(16, 1, 32), G4D_BWD_ENTRY(16, 1, 64), G4D_BWD_ENTRY(16, 1, 128), G4D_BWD_ENTRY(16, 2, 64),
+    G4D_BWD_ENTRY(16, 3, 64), G4D_BWD_ENTRY(32, 1, 64), G4D_BWD_ENTRY(32, 2, 64), G4D_BWD_ENTRY(32, 2, 128),
+    G4D_BWD_ENTRY(32, 3, 64), G4D_BWD_ENTRY(32, 3, 128),
+};
+
+size_t bwd_smem(int K, int HID) { return ((size_t)kGB * (K + 1) + 2 * (size_t)kGB * (HID + 1) + kGB * 65 + kGB * 3) * 4; }
+
+}  // namespace
+
+g4d_status deform_backward(const g4d_gaussians *G, const g4d_planes *P, const g4d_mlp *M, float t,
+                           const g4d_splats_grad *gout, const g4d_deform_grad *d, hipStream_t s) {
+    if (!G || !P || !M || !gout || !d) return G4D_EINVAL;
+    if (G->n < 0 || G->sh_degree < 0 || G->sh_degree > 3 || !(t >= 0.0f && t <= 1.0f)) return G4D_EINVAL;
+    if (P->n_scales < 1 || P->n_scales > kMaxScalesB || (P->feat != 16 && P->feat != 32)) return G4D_EINVAL;
+    for (int k = 0; k < 3; ++k)
+        if (!(P->bmax[k] > P->bmin[k])) return G4D_EINVAL;
+    if (M->in_dim != P->feat * P->n_scales) return G4D_EINVAL;
+    if (M->precision != G4D_MLP_F32) return G4D_EUNSUPPORTED;
+    if ((M->wc == nullptr) != (M->bc == nullptr) || (M->wa == nullptr) != (M->ba == nullptr)) return G4D_EINVAL;
+    const BwdEntry *ke = nullptr;
+    for (const auto &e : kBwdKernels)
+        if (e.feat == P->feat && e.scales == P->n_scales && e.hidden == M->hidden) ke = &e;
+    if (!ke) return G4D_EUNSUPPORTED;
+    const int n = G->n, hid = M->hidden, K = M->in_dim;
+    const int n_sh = 3 * (G->sh_degree + 1) * (G->sh_degree + 1);
+    BwdJob J{};
+    J.means = G->means; J.log_scales = G->log_scales; J.quats = G->quats; J.opac = G->opacity_logits; J.sh = G->sh;
+    J.w1 = M->w1; J.b1 = M->b1;
+    const float *hw[5] = {M->wx, M->wr, M->ws, M->wc, M->wa};
+    const float *hb[5] = {M->bx, M->br, M->bs, M->bc, M->ba};
+    const int hr[5] = {3, 4, 3, M->wc ? n_sh : 0, M->wa ? 1 : 0};
+    float *dhw[5] = {d->wx, d->wr, d->ws, d->wc, d->wa};
+    float *dhb[5] = {d->bx, d->br, d->bs, d->bc, d->ba};
+    int rows = 0;
+    for (int q = 0; q < 5; ++q) {
+        J.hw[q] = hw[q]; J.hb[q] = hb[q]; J.hrows[q] = hr[q];
+        J.d_hw[q] = dhw[q]; J.d_hb[q] = dhb[q];
+        if (hr[q] && (!hw[q] || !hb[q] || !dhw[q] || !dhb[q])) return G4D_EINVAL;
+        rows += hr[q];
+    }
+    if (!M->w1 || !M->b1 || !d->w1 || !d->b1) return G4D_EINVAL;
+    J.d_w1 = d->w1;
+    J.d_b1 = d->b1;
+    J.g_means = gout->means; J.g_scales = gout->scales; J.g_quats = gout->quats; J.g_opac = gout->opacity;
+    J.g_sh = gout->sh;
+    J.d_means = d->means; J.d_log_scales = d->log_scales; J.d_quats = d->quats; J.d_opac = d->opacity_logits;
+    J.d_sh = d->sh;
+    if (n > 0 && (!G->means || !G->log_scales || !G->quats || !G->opacity_logits || !gout->means ||
+                  !gout->scales || !gout->quats || !gout->opacity || !d->means || !d->log_scales || !d->quats ||
+                  !d->opacity_logits))
+        return G4D_EINVAL;
+    if (n > 0 && (M->wc || d->sh) && !gout->sh) return G4D_EINVAL;
+    FillList fl{};
+    auto add = [&](float *p, size_t cnt) {
+        if (p && cnt) { fl.ptr[fl.n] = p; fl.count[fl.n] = (uint32_t)cnt; ++fl.n; }
+    };
+    for (int l = 0; l < P->n_scales; ++l) {
+        for (int p = 0; p < 6; ++p) {
+            static const int ax[6][2] = {{0, 1}, {0, 2}, {1, 2}, {0, 3}, {1, 3}, {2, 3}};
+            if (!P->plane[l][p] || !d->plane[l][p]) return G4D_EINVAL;
+            J.planes[l * 6 + p] = P->plane[l][p];
+            J.d_planes[l * 6 + p] = d->plane[l][p];
+            add(d->plane[l][p], (size_t)P->res[l][ax[p][0]] * P->res[l][ax[p][1]] * P->feat);
+        }
+        for (int k = 0; k < 4; ++k) {
+            if (P->res[l][k] < 2) return G4D_EINVAL;
+            J.res[l][k] = P->res[l][k];
+        }
+        for (int k = 0; k < 3; ++k)
+            J.gscale[l][k] = (float)((double)(P->res[l][k] - 1) / ((double)P->bmax[k] - (double)P->bmin[k]));
+        J.gscale[l][3] = (float)(P->res[l][3] - 1);
+    }
+    add(d->w1, (size_t)hid * K);
+    add(d->b1, (size_t)hid);
+    for (int q = 0; q < 5; ++q)
+        if (hr[q]) { add(dhw[q], (size_t)hr[q] * hid); add(dhb[q], (size_t)hr[q]); }
+    for (int k = 0; k < 3; ++k) { J.bmin[k] = P->bmin[k]; J.bmax[k] = P->bmax[k]; }
+    J.n = n;
+    J.n_sh_rows = n_sh;
+    J.t = t;
+    hipLaunchKernelGGL(k_fill_list, dim3(64, (unsigned)fl.n), dim3(256), 0, s, fl);
+    if (n > 0) {
+        const size_t smem = bwd_smem(K, hid);
+        static bool attr_done[sizeof(kBwdKernels) / sizeof(kBwdKernels[0])] = {};
+        const size_t idx = (size_t)(ke - kBwdKernels);
+        if (!attr_done[idx]) {
+            G4D_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void *>(ke->fn),
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+            attr_done[idx] = true;
+        }
+        hipLaunchKernelGGL(ke->fn, dim3((n + kGB - 1) / kGB), dim3(kThreads), smem, s, J, rows);
+    }
+    G4D_HIP_CHECK(hipGetLastError());
+    return G4D_OK;
+}
+
+}  // namespace g4d
+
+extern "C" g4d_status g4d_deform_backward(const g4d_gaussians *G, const g4d_planes *P, const g4d_mlp *M, float t,
+                                          const g4d_splats_grad *grad_out, const g4d_deform_grad *grad,
+                                          void *stream) {
+    return g4d::deform_backward(G, P, M, t, grad_out, grad, reinterpret_cast<hipStream_t>(stream));
+}

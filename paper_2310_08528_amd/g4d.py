@@ -54,6 +54,13 @@ class SplatsGrad(ctypes.Structure):
     _fields_ = [("means", c_p), ("scales", c_p), ("quats", c_p), ("opacity", c_p), ("sh", c_p)]
 
 
+class DeformGrad(ctypes.Structure):
+    _fields_ = [("means", c_p), ("log_scales", c_p), ("quats", c_p), ("opacity_logits", c_p), ("sh", c_p),
+                ("plane", (c_p * 6) * 4),
+                ("w1", c_p), ("b1", c_p), ("wx", c_p), ("bx", c_p), ("wr", c_p), ("br", c_p), ("ws", c_p),
+                ("bs", c_p), ("wc", c_p), ("bc", c_p), ("wa", c_p), ("ba", c_p)]
+
+
 class Camera(ctypes.Structure):
     _fields_ = [("width", c_i32), ("height", c_i32), ("viewmat", c_f32 * 12), ("fx", c_f32),
                 ("fy", c_f32), ("cx", c_f32), ("cy", c_f32), ("tan_half_fov_x", c_f32),
@@ -123,6 +130,8 @@ SIGNATURES = {
     "g4d_render_workspace_bytes": (c_sz, [c_i32, c_i32, c_i32, c_i64]),
     "g4d_render": (c_i32, [ctypes.POINTER(Splats), ctypes.POINTER(Camera), ctypes.POINTER(Workspace), c_p, c_p,
                            c_p, c_p]),
+    "g4d_deform_backward": (c_i32, [ctypes.POINTER(Gaussians), ctypes.POINTER(Planes), ctypes.POINTER(MLP), c_f32,
+                                    ctypes.POINTER(SplatsGrad), ctypes.POINTER(DeformGrad), c_p]),
     "g4d_render_backward": (c_i32, [ctypes.POINTER(Splats), ctypes.POINTER(Camera), ctypes.POINTER(Workspace),
                                     c_p, c_p, c_p, ctypes.POINTER(SplatsGrad), c_p]),
     "g4d_read_status": (c_i32, [ctypes.POINTER(Workspace), ctypes.POINTER(DeviceStatus), c_p]),
@@ -404,6 +413,39 @@ def render_backward(S: DeviceSplats, cam, ws: RenderWorkspace, final_T, n_contri
     check(load().g4d_render_backward(ctypes.byref(ss), ctypes.byref(cs), ctypes.byref(ws.ws), _ptr(final_T),
                                      _ptr(n_contrib), _ptr(grad_image), ctypes.byref(gs), _stream(stream)),
           "g4d_render_backward")
+
+
+class DeviceDeformGrad:
+    """Gradients of the deformation's inputs (canonical Gaussians, plane
+    cells, decoder weights), device tensors shaped like the inputs."""
+
+    def __init__(self, G: DeviceGaussians, P: DevicePlanes, M: DeviceMLP, device):
+        import torch
+        e = lambda t: torch.empty_like(t) if t is not None else None
+        self.means, self.log_scales, self.quats = e(G.means), e(G.log_scales), e(G.quats)
+        self.opacity_logits, self.sh = e(G.opacity_logits), e(G.sh)
+        self.planes = [[e(p) for p in lv] for lv in P.tensors]
+        self.w = {k: e(v) for k, v in M.w.items()}
+
+    def struct(self) -> DeformGrad:
+        d = DeformGrad()
+        d.means, d.log_scales, d.quats = _ptr(self.means), _ptr(self.log_scales), _ptr(self.quats)
+        d.opacity_logits, d.sh = _ptr(self.opacity_logits), _ptr(self.sh)
+        for l, lv in enumerate(self.planes):
+            for p, t in enumerate(lv):
+                d.plane[l][p] = _ptr(t)
+        for k, v in self.w.items():
+            setattr(d, k, _ptr(v))
+        return d
+
+
+def deform_backward(G: DeviceGaussians, P: DevicePlanes, M: DeviceMLP, t: float, grad_out: DeviceSplatsGrad,
+                    grad: DeviceDeformGrad, stream=None):
+    """dL/d(canonical Gaussians, plane cells, decoder weights) from
+    dL/d(render-ready set)."""
+    gs, ps, ms, go, gd = G.struct(), P.struct(), M.struct(), grad_out.struct(), grad.struct()
+    check(load().g4d_deform_backward(ctypes.byref(gs), ctypes.byref(ps), ctypes.byref(ms), float(t),
+                                     ctypes.byref(go), ctypes.byref(gd), _stream(stream)), "g4d_deform_backward")
 
 
 def read_status(ws: RenderWorkspace, stream=None) -> DeviceStatus:

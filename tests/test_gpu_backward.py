@@ -90,3 +90,101 @@ def test_render_backward_small_config_subset(dev):
     s32 = oracle.to_splats32(d, sc.gaussians.sh, 0)
     errs = _render_bwd_case(s32, cam, "C1 500 @ 64x64", seed=3)
     assert max(errs.values()) <= GRAD_TOL, errs
+
+
+# ---------------------------------------------------------------- deformation
+
+def _deform_compare(gpu, ref, name, tol):
+    errs = {}
+    for k in og.CANON_KEYS + tuple(k for k in og.MLP_KEYS if k in ref):
+        if k in ref and k in gpu and gpu[k] is not None:
+            scale = max(float(np.abs(ref[k]).max()), 1e-30)
+            errs[k] = float(np.abs(np.asarray(gpu[k], np.float64).reshape(ref[k].shape) - ref[k]).max() / scale)
+    pe = 0.0
+    for l, lv in enumerate(ref["planes"]):
+        for q, r in enumerate(lv):
+            scale = max(float(np.abs(r).max()), 1e-30)
+            pe = max(pe, float(np.abs(np.asarray(gpu["planes"][l][q], np.float64) - r).max() / scale))
+    errs["planes"] = pe
+    log(f"[deform bwd] {name}: " + " ".join(f"{k}={v:.1e}" for k, v in errs.items()))
+    bad = {k: v for k, v in errs.items() if v > tol}
+    assert not bad, bad
+
+
+def _gpu_deform_backward(sc, t, gout):
+    import torch
+    G, P, M = (g4d.DeviceGaussians(sc.gaussians, DEV), g4d.DevicePlanes(sc.planes, DEV),
+               g4d.DeviceMLP(sc.mlp, DEV))
+    go = g4d.DeviceSplatsGrad(G.n, G.sh_degree, DEV)
+    for k in og.SPLAT_KEYS:
+        getattr(go, k).copy_(torch.as_tensor(np.asarray(gout[k], np.float32)).reshape(getattr(go, k).shape))
+    d = g4d.DeviceDeformGrad(G, P, M, DEV)
+    g4d.deform_backward(G, P, M, t, go, d)
+    torch.cuda.synchronize()
+    out = {k: getattr(d, k).cpu().numpy() for k in og.CANON_KEYS}
+    out.update({k: v.cpu().numpy() for k, v in d.w.items() if v is not None})
+    out["planes"] = [[p.cpu().numpy() for p in lv] for lv in d.planes]
+    return out
+
+
+@pytest.mark.parametrize("case", ["tiny_h32", "small_config", "headline_shape", "heads_sh3"])
+def test_deform_backward_matches_oracle(dev, case):
+    if case == "tiny_h32":
+        sc = synth.tiny_scene(8, n=300)
+    elif case == "small_config":
+        sc = synth.config1(plane_dist="uniform", n=2000)
+    elif case == "headline_shape":
+        sc = synth.config2(plane_dist="uniform", n=3000)
+    else:
+        sc = synth.tiny_scene(9, n=500, sh_degree=3, colour_opacity=True)
+    g = sc.gaussians
+    rng = np.random.default_rng(21)
+    gout = {"means": rng.normal(size=(3, g.n)), "scales": rng.normal(size=(3, g.n)),
+            "quats": rng.normal(size=(4, g.n)), "opacity": rng.normal(size=g.n),
+            "sh": rng.normal(size=np.shape(g.sh))}
+    t = 0.37
+    # Gaussians with a hidden unit at the ReLU threshold (within binary32
+    # rounding of zero) carry no loss: there the two sides' masks may differ
+    flag = og.relu_flags(g, sc.planes, sc.mlp, t)
+    log(f"[deform bwd] {case}: {int(flag.sum())} of {g.n} Gaussians at a ReLU threshold")
+    assert flag.mean() < 0.01
+    gout = {k: (v * ~flag).astype(np.float32).astype(np.float64) for k, v in gout.items()}
+    gpu = _gpu_deform_backward(sc, t, gout)
+    ref = og.deform_grads(g, sc.planes, sc.mlp, t, gout)
+    _deform_compare(gpu, ref, case, 1e-4)
+
+
+def test_training_step_gradients_match_oracle(dev):
+    """The whole chain on the training configuration's 500-Gaussian 64x64
+    subset: GPU deform + render, then render backward and deform backward,
+    against the FP64 oracle's gradient of the same loss (every canonical
+    parameter, every plane cell, every decoder weight)."""
+    import torch
+    sc = synth.config1(plane_dist="uniform", n=500)
+    cam = synth.look_at_camera((0.0, 0.0, 4.0), (0.0, 0.0, 0.0), 64, 64, 50.0)
+    t = 0.5
+    assert not og.relu_flags(sc.gaussians, sc.planes, sc.mlp, t).any()   # no hidden unit at the ReLU threshold
+    G, P, M = (g4d.DeviceGaussians(sc.gaussians, DEV), g4d.DevicePlanes(sc.planes, DEV),
+               g4d.DeviceMLP(sc.mlp, DEV))
+    S = g4d.DeviceSplats(G.n, G.sh_degree, G.sh, DEV)
+    g4d.deform(G, P, M, t, S)
+    ws = g4d.RenderWorkspace(G.n, 64, 64, 64 * G.n + 4096, DEV)
+    img = torch.empty((3, 64, 64), device=DEV)
+    T = torch.empty((64, 64), device=DEV)
+    nc = torch.empty((64, 64), dtype=torch.int32, device=DEV)
+    g4d.render(S, cam, ws, img, T, nc)
+    torch.cuda.synchronize()
+    host = type("H", (), {k: getattr(S, k).cpu().numpy() for k in ("means", "scales", "quats", "opacity")})
+    s32 = oracle.to_splats32(host, sc.gaussians.sh, 0)
+    r = oracle.render(s32, cam)
+    w = _weights(r, 5)
+    gs = g4d.DeviceSplatsGrad(G.n, G.sh_degree, DEV)
+    g4d.render_backward(S, cam, ws, T, nc, torch.as_tensor(w, dtype=torch.float32).to(DEV), gs)
+    d = g4d.DeviceDeformGrad(G, P, M, DEV)
+    g4d.deform_backward(G, P, M, t, gs, d)
+    torch.cuda.synchronize()
+    gpu = {k: getattr(d, k).cpu().numpy() for k in og.CANON_KEYS}
+    gpu.update({k: v.cpu().numpy() for k, v in d.w.items() if v is not None})
+    gpu["planes"] = [[p.cpu().numpy() for p in lv] for lv in d.planes]
+    _, ref = og.deform_render_grads(sc.gaussians, sc.planes, sc.mlp, t, cam, r.ranges, r.vals, w)
+    _deform_compare(gpu, ref, "training step C1 500 @ 64x64", 2e-4)
