@@ -356,6 +356,13 @@ typedef struct {
 g4d_status g4d_deform_backward(const g4d_gaussians *G, const g4d_planes *P, const g4d_mlp *M, float t,
                                const g4d_splats_grad *grad_out, const g4d_deform_grad *grad, void *stream);
 
+/* The image term of the training loss (Eq. 9): loss = mean |image - target|
+ * over `count` values (a device scalar, cleared by the call; may be NULL)
+ * and grad = dloss/dimage = sign(image - target) / count (0 where equal;
+ * may be NULL).  Device pointers. */
+g4d_status g4d_l1_loss(const float *image, const float *target, int64_t count, float *loss, float *grad,
+                       void *stream);
+
 /* -------------------------------------------------------------- utilities */
 
 const char *g4d_status_string(int32_t status);

@@ -134,6 +134,7 @@ SIGNATURES = {
                                     ctypes.POINTER(SplatsGrad), ctypes.POINTER(DeformGrad), c_p]),
     "g4d_render_backward": (c_i32, [ctypes.POINTER(Splats), ctypes.POINTER(Camera), ctypes.POINTER(Workspace),
                                     c_p, c_p, c_p, ctypes.POINTER(SplatsGrad), c_p]),
+    "g4d_l1_loss": (c_i32, [c_p, c_p, c_i64, c_p, c_p, c_p]),
     "g4d_read_status": (c_i32, [ctypes.POINTER(Workspace), ctypes.POINTER(DeviceStatus), c_p]),
     "g4d_render_export": (c_i32, [ctypes.POINTER(Workspace), c_i32, c_i32, c_i64, c_p, c_sz, c_p]),
     "g4d_set_stage_events": (c_i32, [ctypes.POINTER(c_p), c_i32]),
@@ -446,6 +447,13 @@ def deform_backward(G: DeviceGaussians, P: DevicePlanes, M: DeviceMLP, t: float,
     gs, ps, ms, go, gd = G.struct(), P.struct(), M.struct(), grad_out.struct(), grad.struct()
     check(load().g4d_deform_backward(ctypes.byref(gs), ctypes.byref(ps), ctypes.byref(ms), float(t),
                                      ctypes.byref(go), ctypes.byref(gd), _stream(stream)), "g4d_deform_backward")
+
+
+def l1_loss(image, target, loss=None, grad=None, stream=None):
+    """mean |image - target| into the device scalar ``loss`` and its gradient
+    sign(image - target) / count into ``grad`` (either may be None)."""
+    check(load().g4d_l1_loss(_ptr(image), _ptr(target), int(image.numel()), _ptr(loss), _ptr(grad),
+                             _stream(stream)), "g4d_l1_loss")
 
 
 def read_status(ws: RenderWorkspace, stream=None) -> DeviceStatus:

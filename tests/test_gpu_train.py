@@ -1,0 +1,95 @@
+"""The training direction end to end: the autograd binding's gradients
+against the FP64 oracle, the L1 loss kernel against its definition, and a
+short optimisation that fits a target rendered from perturbed parameters
+(the training configuration's set-up, at reduced size)."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import grad as og
+from paper_2310_08528_amd import autograd as ga
+from paper_2310_08528_amd import g4d, synth
+from tests.gpu_util import gpu_deform, log
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def test_l1_loss_kernel_matches_its_definition(dev):
+    import torch
+    rng = np.random.default_rng(0)
+    a = rng.uniform(size=(3, 37, 53)).astype(np.float32)
+    b = rng.uniform(size=(3, 37, 53)).astype(np.float32)
+    b[0, 0, :5] = a[0, 0, :5]                      # equal values: zero gradient
+    ta, tb = torch.as_tensor(a).to(DEV), torch.as_tensor(b).to(DEV)
+    loss = torch.empty((), device=DEV)
+    grad = torch.empty_like(ta)
+    g4d.l1_loss(ta, tb, loss, grad)
+    torch.cuda.synchronize()
+    d = a.astype(np.float64) - b
+    assert abs(float(loss) - np.abs(d).mean()) <= 1e-6 * np.abs(d).mean()
+    np.testing.assert_array_equal(grad.cpu().numpy(), (np.sign(d) / d.size).astype(np.float32))
+
+
+def test_autograd_gradients_match_oracle(dev):
+    import torch
+    sc = synth.config1(plane_dist="uniform", n=500)
+    cam = synth.look_at_camera((0.0, 0.0, 4.0), (0.0, 0.0, 0.0), 64, 64, 50.0)
+    t = 0.5
+    scene = ga.Scene4D(sc.gaussians, sc.planes, sc.mlp, DEV)
+    ws = g4d.RenderWorkspace(scene.n, 64, 64, 64 * scene.n + 4096, DEV)
+    img = ga.render_image(scene, cam, t, ws)
+    # the oracle's structure and flags on the GPU's deformed set (same inputs)
+    host, _ = gpu_deform(sc, t)
+    s32 = oracle.to_splats32(host, sc.gaussians.sh, 0)
+    r = oracle.render(s32, cam)
+    w = np.random.default_rng(7).choice([-1.0, 1.0], size=r.image.shape) * (r.flag == 0)[None]
+    loss = (img * torch.as_tensor(w, dtype=torch.float32).to(DEV)).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    _, ref = og.deform_render_grads(sc.gaussians, sc.planes, sc.mlp, t, cam, r.ranges, r.vals, w)
+    worst = 0.0
+    for k in og.CANON_KEYS:
+        got = scene.canon[k].grad.cpu().numpy().astype(np.float64)
+        worst = max(worst, np.abs(got - ref[k]).max() / max(np.abs(ref[k]).max(), 1e-30))
+    for l, lv in enumerate(scene.planes):
+        for q, p in enumerate(lv):
+            rq = ref["planes"][l][q]
+            worst = max(worst, np.abs(p.grad.cpu().numpy() - rq).max() / max(np.abs(rq).max(), 1e-30))
+    for k, v in scene.mlp.items():
+        if v is not None:
+            worst = max(worst, np.abs(v.grad.cpu().numpy() - ref[k]).max() / max(np.abs(ref[k]).max(), 1e-30))
+    log(f"[autograd] worst relative gradient error {worst:.2e}")
+    assert worst <= 2e-4
+
+
+def test_fitting_a_perturbed_target_lowers_the_loss(dev):
+    """Render a target from the scene, perturb the canonical means, opacity
+    and colour, and take Adam steps on the L1 loss: the loss must fall by
+    more than half."""
+    import torch
+    sc = synth.config1(plane_dist="uniform", n=1000)
+    cam = synth.look_at_camera((0.0, 0.0, 4.0), (0.0, 0.0, 0.0), 96, 96, 50.0)
+    t = 0.5
+    scene = ga.Scene4D(sc.gaussians, sc.planes, sc.mlp, DEV)
+    ws = g4d.RenderWorkspace(scene.n, 96, 96, 128 * scene.n + 4096, DEV)
+    with torch.no_grad():
+        target = ga.render_image(scene, cam, t, ws).clone()
+        rng = np.random.default_rng(3)
+        scene.canon["means"] += torch.as_tensor(rng.normal(0, 0.03, size=(3, scene.n)), dtype=torch.float32,
+                                                device=DEV)
+        scene.canon["opacity_logits"] += torch.as_tensor(rng.normal(0, 0.5, size=scene.n), dtype=torch.float32,
+                                                         device=DEV)
+        scene.canon["sh"] += torch.as_tensor(rng.normal(0, 0.3, size=tuple(scene.canon["sh"].shape)),
+                                             dtype=torch.float32, device=DEV)
+    opt = torch.optim.Adam([scene.canon["means"], scene.canon["opacity_logits"], scene.canon["sh"]], lr=5e-3)
+    losses = []
+    for it in range(60):
+        opt.zero_grad()
+        loss = ga.l1_loss(ga.render_image(scene, cam, t, ws), target)
+        loss.backward()
+        opt.step()
+        losses.append(loss.item())
+    log(f"[fit] L1 {losses[0]:.4f} -> {losses[-1]:.4f}")
+    assert losses[-1] < 0.5 * losses[0]
