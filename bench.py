@@ -312,11 +312,72 @@ def time_composition(steps, warmup, n_each=50_000):
             "instances_max": kmax}
 
 
+def time_training_step(steps, warmup):
+    """One training step of the small configuration's scene (2000 Gaussians,
+    SH0, planes 32 x t8 F16, MLP 16-64-10) at 800x800: deform + render, the
+    L1 loss and its gradient against a target frame, render backward and
+    deform backward (gradients of every canonical parameter, plane cell and
+    decoder weight).  The optimiser update is not part of it."""
+    import torch
+    from paper_2310_08528_amd import g4d, synth
+    dev = "cuda:0"
+    ev = HipEvents()
+    sc = synth.config1()
+    cam = g4d.camera_struct(synth.look_at_camera((0.0, 0.0, 4.0), (0.0, 0.0, 0.0), 800, 800, 50.0))
+    G, P, M = g4d.DeviceGaussians(sc.gaussians, dev), g4d.DevicePlanes(sc.planes, dev), g4d.DeviceMLP(sc.mlp, dev)
+    S = g4d.DeviceSplats(G.n, G.sh_degree, G.sh, dev)
+    ws = g4d.RenderWorkspace(G.n, 800, 800, 256 * G.n + 4096, dev)
+    img = torch.empty((3, 800, 800), device=dev)
+    T = torch.empty((800, 800), device=dev)
+    nc = torch.empty((800, 800), dtype=torch.int32, device=dev)
+    g4d.deform(G, P, M, 0.0, S)
+    g4d.render(S, cam, ws, img, T, nc)
+    target = img.clone()
+    loss = torch.empty((), device=dev)
+    gimg = torch.empty_like(img)
+    gs = g4d.DeviceSplatsGrad(G.n, G.sh_degree, dev)
+    gd = g4d.DeviceDeformGrad(G, P, M, dev)
+    ts = [0.05 + 0.9 * k / 19 for k in range(20)]
+    sp = torch.cuda.current_stream().cuda_stream
+
+    def step(k, marks=None):
+        t = ts[k % len(ts)]
+        if marks: ev.record(marks[0], sp)
+        g4d.deform(G, P, M, t, S)
+        g4d.render(S, cam, ws, img, T, nc)
+        if marks: ev.record(marks[1], sp)
+        g4d.l1_loss(img, target, loss, gimg)
+        if marks: ev.record(marks[2], sp)
+        g4d.render_backward(S, cam, ws, T, nc, gimg, gs)
+        if marks: ev.record(marks[3], sp)
+        g4d.deform_backward(G, P, M, t, gs, gd)
+        if marks: ev.record(marks[4], sp)
+    for k in range(warmup):
+        step(k)
+    torch.cuda.synchronize()
+    assert g4d.read_status(ws).overflow == 0
+    t0 = time.perf_counter()
+    for k in range(steps):
+        step(k)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    marks = [[ev.create() for _ in range(5)] for _ in range(min(steps, 50))]
+    for k, m in enumerate(marks):
+        step(k, m)
+    torch.cuda.synchronize()
+    st = lambda i: round(float(np.mean([ev.elapsed(m[i], m[i + 1]) for m in marks])), 4)
+    return {"workload": "training step, 2000 Gaussians (SH0, planes 32 x t8 F16, MLP 16-64-10), 800x800, "
+                        "L1 loss; gradients of every canonical parameter, plane cell and decoder weight",
+            "steps": steps, "steps_per_s": round(steps / wall, 2), "ms_per_step": round(1e3 * wall / steps, 4),
+            "stages_ms": {"forward": st(0), "loss": st(1), "render_backward": st(2), "deform_backward": st(3)}}
+
+
 def extra_measurements(steps, warmup):
     """The large configuration (300k Gaussians, planes 64/128/256 x t150,
     MLP 96-128-10, 1352x1014) with the FP32 and the BF16-input MFMA MLP, the
-    100k workload with the colour and opacity heads, the composition
-    workload, and the 100k workload's generator swept over N at 800x800."""
+    100k workload with the colour and opacity heads, a training step of the
+    small configuration at 800x800, the composition workload, and the 100k
+    workload's generator swept over N at 800x800."""
     from paper_2310_08528_amd import g4d, synth
     out = {}
     log("extra: large configuration")
@@ -331,6 +392,8 @@ def extra_measurements(steps, warmup):
         "workload": "100k Gaussians, SH3, the 100k configuration's field; decoder with the colour "
                     "(48 rows) and opacity heads, 800x800",
         "fp32_mlp": time_scene(synth.config2(colour_opacity=True), g4d.MLP_F32, steps, warmup)}
+    log("extra: training step")
+    out["training_step"] = time_training_step(steps, warmup)
     log("extra: composition")
     out["composition"] = time_composition(steps, warmup)
     out["sweep_n"] = {}

@@ -1,7 +1,8 @@
 // Photometric L1 loss of Eq. 9 (its image term): L = mean |I_hat - I| over
 // the 3 x H x W values, and dL/dI_hat = sign(I_hat - I) / count (0 where the
 // two are equal).  One pass: each block reduces its partial sum in LDS and
-// adds it to the scalar with one atomic.
+// adds it to the scalar with one atomic; the grid is held to one block per
+// CU, since atomics on one word serialise (~2048 of them cost ~30 us).
 #include "g4d_internal.h"
 
 namespace g4d {
@@ -34,7 +35,7 @@ extern "C" g4d_status g4d_l1_loss(const float *image, const float *target, int64
     if (!image || !target || count < 1 || (!loss && !grad)) return G4D_EINVAL;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     if (loss) hipLaunchKernelGGL(g4d::k_zero1, dim3(1), dim3(1), 0, s, loss);
-    const int blocks = (int)std::min<int64_t>((count + 255) / 256, 2048);
+    const int blocks = (int)std::min<int64_t>((count + 255) / 256, 256);
     hipLaunchKernelGGL(g4d::k_l1, dim3(blocks), dim3(256), 0, s, image, target, (size_t)count, 1.0f / (float)count,
                        loss, grad);
     G4D_HIP_CHECK(hipGetLastError());
