@@ -313,11 +313,12 @@ def time_composition(steps, warmup, n_each=50_000):
 
 
 def time_training_step(steps, warmup):
-    """One training step of the small configuration's scene (2000 Gaussians,
-    SH0, planes 32 x t8 F16, MLP 16-64-10) at 800x800: deform + render, the
-    L1 loss and its gradient against a target frame, render backward and
-    deform backward (gradients of every canonical parameter, plane cell and
-    decoder weight).  The optimiser update is not part of it."""
+    """One training iteration of the small configuration's scene (2000
+    Gaussians, SH0, planes 32 x t8 F16, MLP 16-64-10) at 800x800: deform +
+    render, the L1 loss and its gradient against a target frame, render
+    backward and deform backward (gradients of every canonical parameter,
+    plane cell and decoder weight), the grid TV term, and the Adam update of
+    every trainable tensor."""
     import torch
     from paper_2310_08528_amd import g4d, synth
     dev = "cuda:0"
@@ -339,6 +340,16 @@ def time_training_step(steps, warmup):
     gd = g4d.DeviceDeformGrad(G, P, M, dev)
     ts = [0.05 + 0.9 * k / 19 for k in range(20)]
     sp = torch.cuda.current_stream().cuda_stream
+    tvl = torch.empty((), device=dev)
+    params = [G.means, G.log_scales, G.quats, G.opacity_logits, G.sh] + [p for lv in P.tensors for p in lv] + \
+             [v for v in M.w.values() if v is not None]
+    grads = [gd.means, gd.log_scales, gd.quats, gd.opacity_logits, gd.sh] + [p for lv in gd.planes for p in lv] + \
+            [v for v in gd.w.values() if v is not None]
+    lrs = [1.6e-3] * (len(params) - sum(1 for v in M.w.values() if v is not None)) + \
+          [1.6e-4] * sum(1 for v in M.w.values() if v is not None)
+    moments = [(torch.zeros_like(p), torch.zeros_like(p)) for p in params]
+    adam = list(zip(params, grads, [m for m, _ in moments], [v for _, v in moments], lrs))
+    n_step = [0]
 
     def step(k, marks=None):
         t = ts[k % len(ts)]
@@ -352,6 +363,10 @@ def time_training_step(steps, warmup):
         if marks: ev.record(marks[3], sp)
         g4d.deform_backward(G, P, M, t, gs, gd)
         if marks: ev.record(marks[4], sp)
+        g4d.tv_loss(P, 1.0, tvl, gd)
+        n_step[0] += 1
+        g4d.adam_step(adam, n_step[0])
+        if marks: ev.record(marks[5], sp)
     for k in range(warmup):
         step(k)
     torch.cuda.synchronize()
@@ -361,15 +376,17 @@ def time_training_step(steps, warmup):
         step(k)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    marks = [[ev.create() for _ in range(5)] for _ in range(min(steps, 50))]
+    marks = [[ev.create() for _ in range(6)] for _ in range(min(steps, 50))]
     for k, m in enumerate(marks):
         step(k, m)
     torch.cuda.synchronize()
     st = lambda i: round(float(np.mean([ev.elapsed(m[i], m[i + 1]) for m in marks])), 4)
-    return {"workload": "training step, 2000 Gaussians (SH0, planes 32 x t8 F16, MLP 16-64-10), 800x800, "
-                        "L1 loss; gradients of every canonical parameter, plane cell and decoder weight",
+    return {"workload": "training iteration, 2000 Gaussians (SH0, planes 32 x t8 F16, MLP 16-64-10), 800x800, "
+                        "L1 + grid TV; gradients of every canonical parameter, plane cell and decoder weight; "
+                        "Adam update of all of them",
             "steps": steps, "steps_per_s": round(steps / wall, 2), "ms_per_step": round(1e3 * wall / steps, 4),
-            "stages_ms": {"forward": st(0), "loss": st(1), "render_backward": st(2), "deform_backward": st(3)}}
+            "stages_ms": {"forward": st(0), "loss": st(1), "render_backward": st(2), "deform_backward": st(3),
+                          "tv_and_adam": st(4)}}
 
 
 def extra_measurements(steps, warmup):

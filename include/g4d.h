@@ -363,6 +363,34 @@ g4d_status g4d_deform_backward(const g4d_gaussians *G, const g4d_planes *P, cons
 g4d_status g4d_l1_loss(const float *image, const float *target, int64_t count, float *loss, float *grad,
                        void *stream);
 
+/* The grid total-variation term of Eq. 9 on the HexPlane cells.  The paper
+ * names the term without a formula or weight; this is the K-Planes form:
+ * for every plane [n_b][n_a][F] of every scale, the mean squared difference
+ * of neighbouring cells along a plus the same along b, summed over planes,
+ * times `weight` (1 in Eq. 9).  Writes the value into the device scalar
+ * `loss` (cleared by the call; may be NULL) and ADDS weight x dtv/dcell to
+ * grad->plane (may be NULL), so it follows g4d_deform_backward.  Device
+ * pointers. */
+g4d_status g4d_tv_loss(const g4d_planes *P, float weight, float *loss, g4d_deform_grad *grad, void *stream);
+
+/* One trainable tensor of an Adam update: count FP32 values of param, their
+ * gradient and the two moment buffers (zero before the first step), and the
+ * tensor's learning rate. */
+typedef struct {
+    float *param;
+    const float *grad;
+    float *m, *v;
+    int64_t count;              /* 0 .. 2^32 - 1 */
+    float lr;
+} g4d_adam_tensor;
+
+/* Adam (the optimiser the method trains with): for step >= 1,
+ * m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+ * param -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps),
+ * for 1 <= n <= 64 tensors in one launch.  Device pointers. */
+g4d_status g4d_adam_step(const g4d_adam_tensor *tensors, int32_t n, float beta1, float beta2, float eps,
+                         int32_t step, void *stream);
+
 /* -------------------------------------------------------------- utilities */
 
 const char *g4d_status_string(int32_t status);

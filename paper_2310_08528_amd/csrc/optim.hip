@@ -1,0 +1,148 @@
+// The rest of a training iteration: the grid total-variation term of Eq. 9
+// on the HexPlane cells, and an Adam update of every trainable tensor.
+//
+// TV: for each plane [n_b][n_a][F] of each scale, the mean squared difference
+// of neighbouring cells along a plus that along b,
+//   tv = sum_planes ( mean (R[i, j+1] - R[i, j])^2 + mean (R[i+1, j] - R[i, j])^2 ),
+// loss += weight * tv, and dtv/dR[i, j] = 2/N_a (2 R[i,j] - R[i,j-1] -
+// R[i,j+1]) + 2/N_b (...) with the missing neighbours left out at the edges
+// (N_a = n_b (n_a - 1) F, N_b = (n_b - 1) n_a F differences).  One thread per
+// cell; each block reduces its loss terms and adds them with one atomic.
+//
+// Adam (Kingma & Ba): m <- b1 m + (1 - b1) g, v <- b2 v + (1 - b2) g^2,
+// p <- p - lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps); up to 64
+// tensors per launch, one grid-stride pass each.
+#include "g4d_internal.h"
+
+namespace g4d {
+namespace {
+
+struct TvPlanes {
+    const float *plane[18];
+    float *grad[18];
+    int na[18], nb[18];
+    int n_planes, feat;
+    float weight;
+};
+
+__global__ __launch_bounds__(256) void k_tv(TvPlanes P, float *__restrict__ loss) {
+    __shared__ float s_part[4];
+    const int p = blockIdx.y;
+    const int na = P.na[p], nb = P.nb[p], F = P.feat;
+    const float *R = P.plane[p];
+    float *G = P.grad[p];
+    const size_t cells = (size_t)na * nb * F;
+    const float ia = 1.0f / (float)((size_t)nb * (na - 1) * F);
+    const float ib = 1.0f / (float)((size_t)(nb - 1) * na * F);
+    float acc = 0.0f;
+    for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (size_t)gridDim.x * blockDim.x) {
+        const int j = (int)((c / F) % na), i = (int)(c / ((size_t)F * na));
+        const float r = R[c];
+        float g = 0.0f;
+        if (j + 1 < na) {
+            const float d = R[c + F] - r;
+            acc += d * d * ia;
+            g -= 2.0f * d * ia;
+        }
+        if (j > 0) g += 2.0f * (r - R[c - F]) * ia;
+        if (i + 1 < nb) {
+            const float d = R[c + (size_t)na * F] - r;
+            acc += d * d * ib;
+            g -= 2.0f * d * ib;
+        }
+        if (i > 0) g += 2.0f * (r - R[c - (size_t)na * F]) * ib;
+        if (G) G[c] += P.weight * g;
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0 && loss)
+        atomicAdd(loss, P.weight * ((s_part[0] + s_part[1]) + (s_part[2] + s_part[3])));
+}
+
+struct AdamList {
+    float *param[64];
+    const float *grad[64];
+    float *m[64], *v[64];
+    uint32_t count[64];
+    float lr[64];
+    int n;
+    float b1, b2, eps, c1, c2;   // c1 = 1 / (1 - b1^t), c2 = 1 / (1 - b2^t)
+};
+
+__global__ __launch_bounds__(256) void k_adam(AdamList A) {
+    const int a = blockIdx.y;
+    if (a >= A.n) return;
+    float *p = A.param[a], *m = A.m[a], *v = A.v[a];
+    const float *g = A.grad[a];
+    const float lr = A.lr[a];
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < A.count[a]; i += gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = A.b1 * m[i] + (1.0f - A.b1) * gi;
+        const float vi = A.b2 * v[i] + (1.0f - A.b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        p[i] -= lr * (mi * A.c1) / (sqrtf(vi * A.c2) + A.eps);
+    }
+}
+
+__global__ void k_zero_scalar(float *p) { *p = 0.0f; }
+
+}  // namespace
+}  // namespace g4d
+
+extern "C" g4d_status g4d_tv_loss(const g4d_planes *P, float weight, float *loss, g4d_deform_grad *grad,
+                                  void *stream) {
+    if (!P || P->n_scales < 1 || P->n_scales > 3 || (P->feat != 16 && P->feat != 32)) return G4D_EINVAL;
+    if (!loss && !grad) return G4D_EINVAL;
+    static const int ax[6][2] = {{0, 1}, {0, 2}, {1, 2}, {0, 3}, {1, 3}, {2, 3}};
+    g4d::TvPlanes T{};
+    size_t max_cells = 0;
+    for (int l = 0; l < P->n_scales; ++l)
+        for (int p = 0; p < 6; ++p) {
+            const int q = l * 6 + p;
+            if (!P->plane[l][p] || (grad && !grad->plane[l][p])) return G4D_EINVAL;
+            T.plane[q] = P->plane[l][p];
+            T.grad[q] = grad ? grad->plane[l][p] : nullptr;
+            T.na[q] = P->res[l][ax[p][0]];
+            T.nb[q] = P->res[l][ax[p][1]];
+            if (T.na[q] < 2 || T.nb[q] < 2) return G4D_EINVAL;
+            max_cells = std::max(max_cells, (size_t)T.na[q] * T.nb[q] * P->feat);
+        }
+    T.n_planes = P->n_scales * 6;
+    T.feat = P->feat;
+    T.weight = weight;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (loss) hipLaunchKernelGGL(g4d::k_zero_scalar, dim3(1), dim3(1), 0, s, loss);
+    // few blocks per plane: the loss adds one atomic per block
+    const unsigned bx = (unsigned)std::min<size_t>((max_cells + 255) / 256, 32);
+    hipLaunchKernelGGL(g4d::k_tv, dim3(bx, (unsigned)T.n_planes), dim3(256), 0, s, T, loss);
+    G4D_HIP_CHECK(hipGetLastError());
+    return G4D_OK;
+}
+
+extern "C" g4d_status g4d_adam_step(const g4d_adam_tensor *t, int32_t n, float beta1, float beta2, float eps,
+                                    int32_t step, void *stream) {
+    if (!t || n < 1 || n > 64 || step < 1 || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f))
+        return G4D_EINVAL;
+    g4d::AdamList A{};
+    uint32_t most = 0;
+    for (int i = 0; i < n; ++i) {
+        if (!t[i].param || !t[i].grad || !t[i].m || !t[i].v || t[i].count < 0 || t[i].count > 0xffffffffLL)
+            return G4D_EINVAL;
+        A.param[i] = t[i].param; A.grad[i] = t[i].grad; A.m[i] = t[i].m; A.v[i] = t[i].v;
+        A.count[i] = (uint32_t)t[i].count;
+        A.lr[i] = t[i].lr;
+        most = std::max(most, A.count[i]);
+    }
+    A.n = n;
+    A.b1 = beta1; A.b2 = beta2; A.eps = eps;
+    A.c1 = (float)(1.0 / (1.0 - std::pow((double)beta1, step)));
+    A.c2 = (float)(1.0 / (1.0 - std::pow((double)beta2, step)));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const unsigned bx = (unsigned)std::max<uint32_t>(1, std::min<uint32_t>((most + 255) / 256, 256));
+    hipLaunchKernelGGL(g4d::k_adam, dim3(bx, (unsigned)n), dim3(256), 0, s, A);
+    G4D_HIP_CHECK(hipGetLastError());
+    return G4D_OK;
+}

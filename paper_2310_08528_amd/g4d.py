@@ -61,6 +61,10 @@ class DeformGrad(ctypes.Structure):
                 ("bs", c_p), ("wc", c_p), ("bc", c_p), ("wa", c_p), ("ba", c_p)]
 
 
+class AdamTensor(ctypes.Structure):
+    _fields_ = [("param", c_p), ("grad", c_p), ("m", c_p), ("v", c_p), ("count", c_i64), ("lr", c_f32)]
+
+
 class Camera(ctypes.Structure):
     _fields_ = [("width", c_i32), ("height", c_i32), ("viewmat", c_f32 * 12), ("fx", c_f32),
                 ("fy", c_f32), ("cx", c_f32), ("cy", c_f32), ("tan_half_fov_x", c_f32),
@@ -135,6 +139,8 @@ SIGNATURES = {
     "g4d_render_backward": (c_i32, [ctypes.POINTER(Splats), ctypes.POINTER(Camera), ctypes.POINTER(Workspace),
                                     c_p, c_p, c_p, ctypes.POINTER(SplatsGrad), c_p]),
     "g4d_l1_loss": (c_i32, [c_p, c_p, c_i64, c_p, c_p, c_p]),
+    "g4d_tv_loss": (c_i32, [ctypes.POINTER(Planes), c_f32, c_p, ctypes.POINTER(DeformGrad), c_p]),
+    "g4d_adam_step": (c_i32, [ctypes.POINTER(AdamTensor), c_i32, c_f32, c_f32, c_f32, c_i32, c_p]),
     "g4d_read_status": (c_i32, [ctypes.POINTER(Workspace), ctypes.POINTER(DeviceStatus), c_p]),
     "g4d_render_export": (c_i32, [ctypes.POINTER(Workspace), c_i32, c_i32, c_i64, c_p, c_sz, c_p]),
     "g4d_set_stage_events": (c_i32, [ctypes.POINTER(c_p), c_i32]),
@@ -454,6 +460,25 @@ def l1_loss(image, target, loss=None, grad=None, stream=None):
     sign(image - target) / count into ``grad`` (either may be None)."""
     check(load().g4d_l1_loss(_ptr(image), _ptr(target), int(image.numel()), _ptr(loss), _ptr(grad),
                              _stream(stream)), "g4d_l1_loss")
+
+
+def tv_loss(P: DevicePlanes, weight: float, loss=None, grad: Optional["DeviceDeformGrad"] = None, stream=None):
+    """Grid total variation of the planes into ``loss``; adds its gradient to
+    grad.planes."""
+    ps = P.struct()
+    gd = grad.struct() if grad is not None else None
+    check(load().g4d_tv_loss(ctypes.byref(ps), float(weight), _ptr(loss),
+                             ctypes.byref(gd) if gd is not None else None, _stream(stream)), "g4d_tv_loss")
+
+
+def adam_step(tensors, step: int, beta1=0.9, beta2=0.999, eps=1e-15, stream=None):
+    """tensors: list of (param, grad, m, v, lr) device tensors (FP32,
+    contiguous, same sizes)."""
+    arr = (AdamTensor * len(tensors))()
+    for i, (p, g, m, v, lr) in enumerate(tensors):
+        arr[i] = AdamTensor(_ptr(p), _ptr(g), _ptr(m), _ptr(v), int(p.numel()), float(lr))
+    check(load().g4d_adam_step(arr, len(tensors), float(beta1), float(beta2), float(eps), int(step),
+                               _stream(stream)), "g4d_adam_step")
 
 
 def read_status(ws: RenderWorkspace, stream=None) -> DeviceStatus:

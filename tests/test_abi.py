@@ -63,7 +63,7 @@ _STRUCTS = {
     "g4d_device_status": g4d.DeviceStatus, "g4d_deform_job": g4d.DeformJob,
     "g4d_server_config": g4d.ServerConfig, "g4d_server_stats": g4d.ServerStats,
     "g4d_sim_config": g4d.SimConfig, "g4d_sim_result": g4d.SimResult,
-    "g4d_splats_grad": g4d.SplatsGrad, "g4d_deform_grad": g4d.DeformGrad, "g4d_placement": g4d.Placement, "g4d_compose_item": g4d.ComposeItem,
+    "g4d_splats_grad": g4d.SplatsGrad, "g4d_deform_grad": g4d.DeformGrad, "g4d_adam_tensor": g4d.AdamTensor, "g4d_placement": g4d.Placement, "g4d_compose_item": g4d.ComposeItem,
 }
 
 

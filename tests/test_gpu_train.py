@@ -93,3 +93,99 @@ def test_fitting_a_perturbed_target_lowers_the_loss(dev):
         losses.append(loss.item())
     log(f"[fit] L1 {losses[0]:.4f} -> {losses[-1]:.4f}")
     assert losses[-1] < 0.5 * losses[0]
+
+
+def test_tv_kernel_matches_oracle(dev):
+    import torch
+    from oracle import train as ot
+    sc = synth.config2(plane_dist="uniform", n=500)
+    G, P, M = (g4d.DeviceGaussians(sc.gaussians, DEV), g4d.DevicePlanes(sc.planes, DEV),
+               g4d.DeviceMLP(sc.mlp, DEV))
+    d = g4d.DeviceDeformGrad(G, P, M, DEV)
+    rng = np.random.default_rng(2)
+    base = [[rng.normal(size=tuple(p.shape)).astype(np.float32) for p in lv] for lv in d.planes]
+    for lv, bl in zip(d.planes, base):
+        for p, b in zip(lv, bl):
+            p.copy_(torch.as_tensor(b))
+    loss = torch.empty((), device=DEV)
+    g4d.tv_loss(P, 0.25, loss, d)
+    torch.cuda.synchronize()
+    v, g = ot.tv_loss(sc.planes.planes, 0.25)
+    log(f"[tv] {float(loss):.6f} vs {v:.6f}")
+    assert abs(float(loss) - v) <= 1e-5 * abs(v)
+    for l, lv in enumerate(d.planes):
+        for q, p in enumerate(lv):
+            ref = base[l][q] + g[l][q]      # the kernel adds to what is there
+            np.testing.assert_allclose(p.cpu().numpy(), ref, rtol=0, atol=1e-6 * np.abs(ref).max())
+
+
+def test_adam_kernel_matches_oracle(dev):
+    import torch
+    from oracle import train as ot
+    rng = np.random.default_rng(3)
+    sizes = [1, 33, 5000, 70001]
+    ps = [rng.normal(size=s).astype(np.float32) for s in sizes]
+    dp = [torch.as_tensor(p).to(DEV) for p in ps]
+    dm = [torch.zeros_like(p) for p in dp]
+    dv = [torch.zeros_like(p) for p in dp]
+    ref = [(p.astype(np.float64), np.zeros(s), np.zeros(s)) for p, s in zip(ps, sizes)]
+    lrs = [1e-3, 2e-2, 1.6e-3, 1.6e-4]
+    for step in range(1, 4):
+        gs = [rng.normal(size=s).astype(np.float32) for s in sizes]
+        dg = [torch.as_tensor(g).to(DEV) for g in gs]
+        g4d.adam_step(list(zip(dp, dg, dm, dv, lrs)), step)
+        ref = [ot.adam(p, g, m, v, lr, step) for (p, m, v), g, lr in zip(ref, gs, lrs)]
+    torch.cuda.synchronize()
+    for x, (p, _, _) in zip(dp, ref):
+        np.testing.assert_allclose(x.cpu().numpy(), p, rtol=0, atol=1e-6 * max(1.0, np.abs(p).max()))
+
+
+def test_training_iteration_with_tv_and_adam_kernels(dev):
+    """Forward, L1 + TV, backward and the Adam kernel on every trainable
+    tensor (learning rates of the appendix: 1.6e-3 for the planes, 1.6e-4 for
+    the decoder): the image loss falls."""
+    import torch
+    sc = synth.config1(plane_dist="uniform", n=1000)
+    cam = synth.look_at_camera((0.0, 0.0, 4.0), (0.0, 0.0, 0.0), 96, 96, 50.0)
+    t = 0.5
+    scene = ga.Scene4D(sc.gaussians, sc.planes, sc.mlp, DEV)
+    ws = g4d.RenderWorkspace(scene.n, 96, 96, 128 * scene.n + 4096, DEV)
+    with torch.no_grad():
+        target = ga.render_image(scene, cam, t, ws).clone()
+        rng = np.random.default_rng(4)
+        scene.canon["sh"] += torch.as_tensor(rng.normal(0, 0.3, size=tuple(scene.canon["sh"].shape)),
+                                             dtype=torch.float32, device=DEV)
+        for lv in scene.planes:
+            for p in lv:
+                p.mul_(torch.as_tensor(rng.uniform(0.9, 1.1, size=tuple(p.shape)), dtype=torch.float32,
+                                       device=DEV))
+    params = scene.parameters()
+    lrs = [1.6e-3] * 5 + [1.6e-3] * sum(len(lv) for lv in scene.planes) + \
+          [1.6e-4] * sum(1 for v in scene.mlp.values() if v is not None)
+    moments = [(torch.zeros_like(p), torch.zeros_like(p)) for p in params]
+    P = g4d.DevicePlanes.__new__(g4d.DevicePlanes)
+    P.n_scales, P.feat, P.res, P.bmin, P.bmax, P.tensors = (scene.n_scales, scene.feat, scene.res, scene.bmin,
+                                                            scene.bmax, scene.planes)
+    tvl = torch.empty((), device=DEV)
+    losses = []
+    for step in range(1, 41):
+        for p in params:
+            p.grad = None
+        loss = ga.l1_loss(ga.render_image(scene, cam, t, ws), target)
+        loss.backward()
+        grad = type("D", (), {})()
+        grad.struct = lambda: _plane_grad_struct(scene)
+        g4d.tv_loss(P, 0.01, tvl, grad)
+        with torch.no_grad():
+            g4d.adam_step([(p, p.grad, m, v, lr) for p, (m, v), lr in zip(params, moments, lrs)], step)
+        losses.append(loss.item())
+    log(f"[iteration] L1 {losses[0]:.4f} -> {losses[-1]:.4f}, TV {float(tvl):.3e}")
+    assert losses[-1] < 0.7 * losses[0]
+
+
+def _plane_grad_struct(scene):
+    d = g4d.DeformGrad()
+    for l, lv in enumerate(scene.planes):
+        for q, p in enumerate(lv):
+            d.plane[l][q] = p.grad.data_ptr()
+    return d
