@@ -11,9 +11,15 @@
 //                     per-pixel lists are stored.  A wave takes 64 entries at
 //                     a time, keeps those that can reach its quadrant (the
 //                     forward's conservative cull), and for each kept entry
-//                     sums the 64 pixels' contributions across the wave and
-//                     adds them to the Gaussian's 2D gradient (u, v, conic,
-//                     colour, opacity) with one atomic per component.
+//                     sums the 64 pixels' contributions across the wave.  The
+//                     four waves walk the same 64-entry chunks: their sums
+//                     meet in an LDS accumulator (LDS atomics), and the block
+//                     then adds each entry's 2D gradient (u, v, conic, colour,
+//                     opacity) to the Gaussian with one global atomic per
+//                     component, spread over all 256 threads.  The wave sums
+//                     are DPP butterflies inside each 16-lane row plus four
+//                     readlanes (lane shuffles through the LDS crossbar cost
+//                     twice as much here).
 //   k_preprocess_bwd  per Gaussian: the 2D gradient back through the conic
 //                     inverse, Sigma' = J W Sigma W^T J^T (with J's
 //                     dependence on the camera-space mean and the frustum
@@ -73,6 +79,25 @@ __global__ void k_fill_zero(float *__restrict__ p, size_t n) {
 
 constexpr int kG2 = 9;   // 2D gradient components per Gaussian
 
+// Sum over the 64 lanes of a wave (every lane active): butterflies inside
+// each row of 16 lanes with DPP (quad permutes, half-row and row mirrors,
+// all on the VALU), then the four row sums read into scalars.
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float wave_sum(float v) {
+    v += dpp<0xb1>(v);    // quad_perm [1, 0, 3, 2]: lane ^ 1
+    v += dpp<0x4e>(v);    // quad_perm [2, 3, 0, 1]: lane ^ 2
+    v += dpp<0x141>(v);   // row_half_mirror: the other quad of the half-row
+    v += dpp<0x140>(v);   // row_mirror: the other half of the row
+    const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+    const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+    const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+    const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+    return (r0 + r1) + (r2 + r3);
+}
+
 __global__ __launch_bounds__(256) void k_blend_bwd(const uint4 *__restrict__ order, const uint32_t *__restrict__ gids,
                                                    uint32_t gmask, const float4 *__restrict__ recA,
                                                    const float4 *__restrict__ recB, const float *__restrict__ recC,
@@ -83,7 +108,10 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const uint4 *__restrict__ ord
                                                    int n) {
     constexpr int NW = 4;
     __shared__ float4 sR[NW][64 * 3];
-    __shared__ uint32_t sG[NW][64];
+    __shared__ uint32_t sSlot[NW][64];     // chunk index of each packed entry
+    __shared__ float sAcc[64 * kG2];       // the chunk's entries: the four quadrants' sums
+    __shared__ uint32_t sGid[64];
+    __shared__ int sMax[NW];
     const int b = (int)blockIdx.x;
     if (b >= n_tiles) return;
     const uint4 ord = order[b];
@@ -107,15 +135,22 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const uint4 *__restrict__ ord
     const float g2 = inside ? grad_image[2 * plane + pix] : 0.0f;
     const float tnbg = T * ((cam.bg[0] * g0 + cam.bg[1] * g1) + cam.bg[2] * g2);
     float S0 = 0.0f, S1 = 0.0f, S2 = 0.0f;
+    // the tile's highest contributing position (all waves walk the same chunks)
     int pmax = last;
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) pmax = max(pmax, __shfl_xor(pmax, o, 64));
+    if (lane == 0) sMax[wave] = pmax;
+    for (int i = tid; i < 64 * kG2; i += 256) sAcc[i] = 0.0f;
+    __syncthreads();
+    pmax = max(max(sMax[0], sMax[1]), max(sMax[2], sMax[3]));
     const float a_min = 1.0f / 255.0f;
     const uint64_t lt = lanemask_lt();
     float4 *__restrict__ R = sR[wave];
-    uint32_t *__restrict__ Gs = sG[wave];
+    uint32_t *__restrict__ Sl = sSlot[wave];
     for (int hi = pmax; hi >= 1; hi -= 64) {
-        const int pos1 = hi - lane;   // lane 0 holds the highest position
+        // every wave loads the chunk's 64 entries (lane 0: the highest position)
+        // and keeps those that can reach its quadrant
+        const int pos1 = hi - lane;
         bool keep = false;
         float4 A4 = make_float4(0.f, 0.f, 0.f, 0.f), B4 = A4;
         float C1 = 0.0f;
@@ -131,13 +166,14 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const uint4 *__restrict__ ord
             const float thr = 2.0f * (__logf(B4.y) + 5.541263545158426f);
             keep = may_reach(A4.x, A4.y, A, Bc, C, iA, iC, thr, x_lo, x_hi, y_lo, y_hi);
         }
+        if (wave == 0) sGid[lane] = gid;
         const uint64_t km = __builtin_amdgcn_ballot_w64(keep);
         if (keep) {
             const int slot = (int)__popcll(km & lt);
             R[3 * slot] = A4;
             R[3 * slot + 1] = make_float4(B4.x, __log2f(B4.y), B4.z, B4.w);
             R[3 * slot + 2] = make_float4(C1, __int_as_float(pos1), B4.y, 0.0f);
-            Gs[slot] = gid;
+            Sl[slot] = (uint32_t)lane;
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -182,22 +218,28 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const uint4 *__restrict__ ord
                 }
             }
             if (__builtin_amdgcn_ballot_w64(act) != 0) {
+                float sum[kG2];
 #pragma unroll
-                for (int k = 0; k < kG2; ++k) {
+                for (int k = 0; k < kG2; ++k) sum[k] = wave_sum(v[k]);
+                // lane k adds component k of the wave's sum into the chunk
+                // accumulator (LDS atomics: the four quadrants meet here)
+                float mine = sum[0];
 #pragma unroll
-                    for (int o = 32; o >= 1; o >>= 1) v[k] += __shfl_xor(v[k], o, 64);
-                }
-                if (lane == 0) {
-                    const uint32_t g = Gs[j];
-#pragma unroll
-                    for (int k = 0; k < kG2; ++k)
-                        if (v[k] != 0.0f) atomicAdd(&g2d[(size_t)k * n + g], v[k]);
-                }
+                for (int k = 1; k < kG2; ++k) mine = lane == k ? sum[k] : mine;
+                if (lane < kG2 && mine != 0.0f) atomicAdd(&sAcc[Sl[j] * kG2 + lane], mine);
             }
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        __syncthreads();
+        // one global atomic per (entry, component) of the tile, all threads
+        for (int i = tid; i < 64 * kG2; i += 256) {
+            const float val = sAcc[i];
+            if (val != 0.0f) {
+                const int e = i / kG2, k = i - e * kG2;
+                atomicAdd(&g2d[(size_t)k * n + sGid[e]], val);
+                sAcc[i] = 0.0f;
+            }
+        }
+        __syncthreads();
     }
 }
 
