@@ -468,6 +468,8 @@ def main():
                     help="frames in flight for the reported throughput (1 = one frame at a time)")
     ap.add_argument("--extra", action="store_true",
                     help="also time the large configuration (FP32 and BF16 MLP) and a sweep over N")
+    ap.add_argument("--training", action="store_true",
+                    help="only time the training iteration (2000 Gaussians, 800x800) and print its record")
     ap.add_argument("--serve-seconds", type=float, default=20.0)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-slots", type=int, default=3)
@@ -483,6 +485,9 @@ def main():
     dev = "cuda:0"
     torch.cuda.set_device(0)
     ev = HipEvents()
+    if args.training:
+        print(json.dumps({"training_step": time_training_step(args.steps, args.warmup)}), flush=True)
+        return
 
     sc = synth.config2(n=args.n)
     frames = [(k % len(sc.cameras), float(sc.timestamps[(k // len(sc.cameras)) % len(sc.timestamps)]))
