@@ -287,13 +287,19 @@ MLP_KEYS = ("w1", "b1", "wx", "bx", "wr", "br", "ws", "bs", "wc", "bc", "wa", "b
 CANON_KEYS = ("means", "log_scales", "quats", "opacity_logits", "sh")
 
 
-def deform_render_grads(g, planes, mlp, t, cam, ranges, vals, weight):
+def deform_render_grads(g, planes, mlp, t, cam, ranges, vals, weight, frozen=None):
     """Gradient of L = sum(weight * image) of the deform-then-render path
     with respect to the canonical Gaussians, every plane cell and the
     decoder weights, FP64.  Returns (image, grads) with grads["planes"] a
-    list over scales of six arrays shaped like the planes."""
+    list over scales of six arrays shaped like the planes.  ``frozen``
+    (bool [n], optional): Gaussians whose deformed values pass no gradient
+    back (they still render), e.g. those relu_flags marks."""
     p, pl, m = _leaf_inputs(g, planes, mlp)
     d = deform_torch(p, pl, m, t, planes.bmin, planes.bmax)
+    if frozen is not None:
+        keep = torch.as_tensor(~np.asarray(frozen, bool))
+        for k in SPLAT_KEYS:
+            d[k] = torch.where(keep, d[k], d[k].detach())
     d["sh_degree"] = int(g.sh_degree)
     img = render_torch(d, cam, ranges, vals)
     loss = (torch.as_tensor(np.asarray(weight, np.float64)) * img).sum()
