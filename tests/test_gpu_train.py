@@ -189,3 +189,31 @@ def _plane_grad_struct(scene):
         for q, p in enumerate(lv):
             d.plane[l][q] = p.grad.data_ptr()
     return d
+
+
+def test_autograd_with_colour_and_opacity_heads(dev):
+    """The chain with the appendix's heads: the render's SH and opacity
+    gradients reach the colour and opacity heads through the deformation."""
+    import torch
+    sc = synth.tiny_scene(34, n=400, width=64, height=64, sh_degree=1, colour_opacity=True)
+    cam, t = sc.cameras[0], 0.3
+    assert not og.relu_flags(sc.gaussians, sc.planes, sc.mlp, t).any()   # no hidden unit at the ReLU threshold
+    scene = ga.Scene4D(sc.gaussians, sc.planes, sc.mlp, DEV)
+    ws = g4d.RenderWorkspace(scene.n, 64, 64, 64 * scene.n + 4096, DEV)
+    img = ga.render_image(scene, cam, t, ws)
+    host, _ = gpu_deform(sc, t)
+    s32 = oracle.to_splats32(host, host.sh, 1)
+    r = oracle.render(s32, cam)
+    w = np.random.default_rng(8).choice([-1.0, 1.0], size=r.image.shape) * (r.flag == 0)[None]
+    (img * torch.as_tensor(w, dtype=torch.float32).to(DEV)).sum().backward()
+    torch.cuda.synchronize()
+    _, ref = og.deform_render_grads(sc.gaussians, sc.planes, sc.mlp, t, cam, r.ranges, r.vals, w)
+    worst = {}
+    for k in og.CANON_KEYS:
+        got = scene.canon[k].grad.cpu().numpy().astype(np.float64)
+        worst[k] = np.abs(got - ref[k]).max() / max(np.abs(ref[k]).max(), 1e-30)
+    for k in ("wc", "bc", "wa", "ba", "w1"):
+        got = scene.mlp[k].grad.cpu().numpy().astype(np.float64)
+        worst[k] = np.abs(got - ref[k]).max() / max(np.abs(ref[k]).max(), 1e-30)
+    log("[autograd heads] " + " ".join(f"{k}={v:.1e}" for k, v in worst.items()))
+    assert max(worst.values()) <= 2e-4, worst
