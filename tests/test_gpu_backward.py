@@ -188,3 +188,46 @@ def test_training_step_gradients_match_oracle(dev):
     gpu["planes"] = [[p.cpu().numpy() for p in lv] for lv in d.planes]
     _, ref = og.deform_render_grads(sc.gaussians, sc.planes, sc.mlp, t, cam, r.ranges, r.vals, w)
     _deform_compare(gpu, ref, "training step C1 500 @ 64x64", 2e-4)
+
+
+def test_training_step_gradients_full_size(dev):
+    """The training configuration at its full size (2000 Gaussians, 800x800),
+    in the launch configuration the benchmark times: every gradient against
+    the FP64 oracle.  Gaussians at a ReLU threshold pass no gradient back on
+    either side; flagged pixels carry no loss."""
+    import time
+    import torch
+    sc = synth.config1(plane_dist="uniform")
+    cam = synth.look_at_camera((0.0, 0.0, 4.0), (0.0, 0.0, 0.0), 800, 800, 50.0)
+    t = 0.5
+    frozen = og.relu_flags(sc.gaussians, sc.planes, sc.mlp, t)
+    G, P, M = (g4d.DeviceGaussians(sc.gaussians, DEV), g4d.DevicePlanes(sc.planes, DEV),
+               g4d.DeviceMLP(sc.mlp, DEV))
+    S = g4d.DeviceSplats(G.n, G.sh_degree, G.sh, DEV)
+    g4d.deform(G, P, M, t, S)
+    ws = g4d.RenderWorkspace(G.n, 800, 800, 256 * G.n + 4096, DEV)
+    img = torch.empty((3, 800, 800), device=DEV)
+    T = torch.empty((800, 800), device=DEV)
+    nc = torch.empty((800, 800), dtype=torch.int32, device=DEV)
+    g4d.render(S, cam, ws, img, T, nc)
+    torch.cuda.synchronize()
+    host = type("H", (), {k: getattr(S, k).cpu().numpy() for k in ("means", "scales", "quats", "opacity")})
+    s32 = oracle.to_splats32(host, sc.gaussians.sh, 0)
+    r = oracle.render(s32, cam)
+    w = _weights(r, 6)
+    gs = g4d.DeviceSplatsGrad(G.n, G.sh_degree, DEV)
+    g4d.render_backward(S, cam, ws, T, nc, torch.as_tensor(w, dtype=torch.float32).to(DEV), gs)
+    fz = torch.as_tensor(frozen).to(DEV)
+    for k in og.SPLAT_KEYS:
+        getattr(gs, k)[..., fz] = 0.0
+    d = g4d.DeviceDeformGrad(G, P, M, DEV)
+    g4d.deform_backward(G, P, M, t, gs, d)
+    torch.cuda.synchronize()
+    gpu = {k: getattr(d, k).cpu().numpy() for k in og.CANON_KEYS}
+    gpu.update({k: v.cpu().numpy() for k, v in d.w.items() if v is not None})
+    gpu["planes"] = [[p.cpu().numpy() for p in lv] for lv in d.planes]
+    t0 = time.time()
+    _, ref = og.deform_render_grads(sc.gaussians, sc.planes, sc.mlp, t, cam, r.ranges, r.vals, w, frozen)
+    log(f"[training full size] oracle gradient in {time.time() - t0:.1f} s; {int(frozen.sum())} Gaussians at a "
+        f"ReLU threshold, {int((r.flag != 0).sum())} flagged pixels")
+    _deform_compare(gpu, ref, "training step C1 2000 @ 800x800", 2e-4)
