@@ -41,8 +41,10 @@ PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
 PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
-# Algorithmic work per unit (measurement section)
-BLEND_FLOP_PER_EVAL = 15          # binary32 ops per evaluated (pixel, Gaussian) pair
+# Algorithmic work per unit: an evaluated (pixel, Gaussian) pair of the blend
+# costs 2 (offset) + 8 (quadratic form) + 2 (o exp) + 1 (min) + 2 (T (1 - alpha))
+# binary32 operations
+BLEND_FLOP_PER_EVAL = 15
 STAGES = ["clear", "preprocess", "depth_sort", "offsets", "emit", "tile_sort", "ranges", "blend"]
 
 
@@ -477,7 +479,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the render shards by requests or image tiles; see DESIGN.md)", file=sys.stderr)
+              "(the render would shard by requests or by image tiles)", file=sys.stderr)
         sys.exit(2)
 
     import torch
