@@ -16,8 +16,11 @@
 //                         grid coordinates receive the bilinear slopes
 //                         (zero at and beyond the box border, as the border
 //                         clamp of the query has no slope there).
-// Weights are read from global memory (L1/L2-resident: every block reads
-// them); f_h, h, the deltas and dz live in LDS.
+// W1 is read from global memory (L1/L2-resident: every block reads it); the
+// head weights, their biases and the per-row gradient pointers are staged in
+// LDS once per block (the heads are selected by a runtime row index, which
+// in the inner loops would be a dependent kernel-argument load per step);
+// f_h, h, the deltas and dz live in LDS.
 #include "g4d_internal.h"
 
 #include <vector>
@@ -84,9 +87,30 @@ __global__ __launch_bounds__(kThreads) void k_deform_bwd(BwdJob J, int rows) {
     float *s_dz = s_h + kGB * HH;        // [64][HID+1]: dL/d(pre-activation)
     float *s_dd = s_dz + kGB * HH;       // [64][65]: head outputs, then their gradients
     float *s_dm = s_dd + kGB * DS;       // [64][3]: dL/d canonical mean
+    float *s_w2 = s_dm + kGB * 3;        // [rows][HID+1]: head weights
+    float *s_b2 = s_w2 + rows * HH;      // [rows]
+    __shared__ float *s_dw[64];          // gradient row of head row r (null: padding)
+    __shared__ float *s_db[64];
     const int tid = threadIdx.x;
     const int g0 = blockIdx.x * kGB;
     const int n = J.n;
+    if (tid < rows) {
+        int hq, k;
+        if (head_of(J, tid, hq, k)) {
+            s_dw[tid] = J.d_hw[hq] + (size_t)k * HID;
+            s_db[tid] = J.d_hb[hq] + k;
+            s_b2[tid] = J.hb[hq][k];
+        } else {
+            s_dw[tid] = nullptr;
+            s_db[tid] = nullptr;
+            s_b2[tid] = 0.0f;
+        }
+    }
+    for (int idx = tid; idx < rows * HID; idx += kThreads) {
+        const int r = idx / HID, j = idx - r * HID;
+        int hq, k;
+        s_w2[r * HH + j] = head_of(J, r, hq, k) ? J.hw[hq][(size_t)k * HID + j] : 0.0f;
+    }
 
     // ---- A. encoder (as in the forward)
     constexpr int LPG = F / 4;
@@ -137,16 +161,12 @@ __global__ __launch_bounds__(kThreads) void k_deform_bwd(BwdJob J, int rows) {
         s_h[g * HH + j] = fmaxf(acc, 0.0f);
     }
     __syncthreads();
-    // ---- C. head outputs delta = W2 h + b2
+    // ---- C. head outputs delta = W2 h + b2 (padding rows: zero weights)
     for (int idx = tid; idx < kGB * rows; idx += kThreads) {
         const int g = idx % kGB, r = idx / kGB;
-        int hq, k;
-        float acc = 0.0f;
-        if (head_of(J, r, hq, k)) {
-            acc = J.hb[hq][k];
-            const float *w = J.hw[hq] + (size_t)k * HID;
-            for (int j = 0; j < HID; ++j) acc += w[j] * s_h[g * HH + j];
-        }
+        float acc = s_b2[r];
+        const float *w = s_w2 + r * HH;
+        for (int j = 0; j < HID; ++j) acc += w[j] * s_h[g * HH + j];
         s_dd[g * DS + r] = acc;
     }
     __syncthreads();
@@ -212,24 +232,20 @@ __global__ __launch_bounds__(kThreads) void k_deform_bwd(BwdJob J, int rows) {
     for (int idx = tid; idx < kGB * HID; idx += kThreads) {
         const int g = idx % kGB, j = idx / kGB;
         float acc = 0.0f;
-        for (int r = 0; r < rows; ++r) {
-            int hq, k;
-            if (head_of(J, r, hq, k)) acc += J.hw[hq][(size_t)k * HID + j] * s_dd[g * DS + r];
-        }
+        for (int r = 0; r < rows; ++r) acc += s_w2[r * HH + j] * s_dd[g * DS + r];
         s_dz[g * HH + j] = s_h[g * HH + j] > 0.0f ? acc : 0.0f;
     }
     // dW2 += ddelta h^T, db2 += ddelta (sums over the block's Gaussians)
     for (int idx = tid; idx < rows * (HID + 1); idx += kThreads) {
         const int r = idx / (HID + 1), j = idx % (HID + 1);
-        int hq, k;
-        if (!head_of(J, r, hq, k)) continue;
+        if (!s_dw[r]) continue;
         float acc = 0.0f;
         if (j < HID) {
             for (int g = 0; g < kGB; ++g) acc += s_dd[g * DS + r] * s_h[g * HH + j];
-            if (acc != 0.0f) atomicAdd(&J.d_hw[hq][(size_t)k * HID + j], acc);
+            if (acc != 0.0f) atomicAdd(s_dw[r] + j, acc);
         } else {
             for (int g = 0; g < kGB; ++g) acc += s_dd[g * DS + r];
-            if (acc != 0.0f) atomicAdd(&J.d_hb[hq][k], acc);
+            if (acc != 0.0f) atomicAdd(s_db[r], acc);
         }
     }
     __syncthreads();
@@ -396,7 +412,10 @@ const BwdEntry kBwdKernels[] = {
     G4D_BWD_ENTRY(32, 3, 64), G4D_BWD_ENTRY(32, 3, 128),
 };
 
-size_t bwd_smem(int K, int HID) { return ((size_t)kGB * (K + 1) + 2 * (size_t)kGB * (HID + 1) + kGB * 65 + kGB * 3) * 4; }
+size_t bwd_smem(int K, int HID, int rows) {
+    return ((size_t)kGB * (K + 1) + 2 * (size_t)kGB * (HID + 1) + kGB * 65 + kGB * 3 + (size_t)rows * (HID + 1) +
+            rows) * 4;
+}
 
 }  // namespace
 
@@ -473,12 +492,13 @@ g4d_status deform_backward(const g4d_gaussians *G, const g4d_planes *P, const g4
     J.t = t;
     hipLaunchKernelGGL(k_fill_list, dim3(64, (unsigned)fl.n), dim3(256), 0, s, fl);
     if (n > 0) {
-        const size_t smem = bwd_smem(K, hid);
+        const size_t smem = bwd_smem(K, hid, rows);
         static bool attr_done[sizeof(kBwdKernels) / sizeof(kBwdKernels[0])] = {};
         const size_t idx = (size_t)(ke - kBwdKernels);
-        if (!attr_done[idx]) {
+        if (!attr_done[idx]) {   // the largest head count: 64 rows
             G4D_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void *>(ke->fn),
-                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+                                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                                              (int)bwd_smem(K, hid, 64)));
             attr_done[idx] = true;
         }
         hipLaunchKernelGGL(ke->fn, dim3((n + kGB - 1) / kGB), dim3(kThreads), smem, s, J, rows);
