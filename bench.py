@@ -45,6 +45,7 @@ PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # costs 2 (offset) + 8 (quadratic form) + 2 (o exp) + 1 (min) + 2 (T (1 - alpha))
 # binary32 operations
 BLEND_FLOP_PER_EVAL = 15
+BWD_OPS_PER_EVAL = 55             # backward walk, per re-evaluated pair (an upper estimate of the work)
 STAGES = ["clear", "preprocess", "depth_sort", "offsets", "emit", "tile_sort", "ranges", "blend"]
 
 
@@ -382,13 +383,24 @@ def time_training_step(steps, warmup):
     for k, m in enumerate(marks):
         step(k, m)
     torch.cuda.synchronize()
-    st = lambda i: round(float(np.mean([ev.elapsed(m[i], m[i + 1]) for m in marks])), 4)
+    # medians: an event interval also holds any host delay before the next launch
+    st = lambda i: round(float(np.median([ev.elapsed(m[i], m[i + 1]) for m in marks])), 4)
+    evals = int(g4d.read_status(ws).blend_evals)
+    rb_ms = float(np.median([ev.elapsed(m[2], m[3]) for m in marks]))
     return {"workload": "training iteration, 2000 Gaussians (SH0, planes 32 x t8 F16, MLP 16-64-10), 800x800, "
                         "L1 + grid TV; gradients of every canonical parameter, plane cell and decoder weight; "
                         "Adam update of all of them",
             "steps": steps, "steps_per_s": round(steps / wall, 2), "ms_per_step": round(1e3 * wall / steps, 4),
             "stages_ms": {"forward": st(0), "loss": st(1), "render_backward": st(2), "deform_backward": st(3),
-                          "tv_and_adam": st(4)}}
+                          "tv_and_adam": st(4)},
+            # the backward walk re-evaluates the forward's (pixel, Gaussian) pairs; ~55 binary32
+            # ops per contributing pair (alpha as in the forward, T / (1 - alpha), the colour,
+            # opacity, position and conic terms); the stage also holds two small kernels
+            "render_backward_roofline": {"bound": "alu", "evaluated_pairs": evals, "ops_per_pair": BWD_OPS_PER_EVAL,
+                                         "achieved": round(evals * BWD_OPS_PER_EVAL / (rb_ms * 1e-3) / 1e12, 3),
+                                         "peak": round(PEAK_VALU_TOPS, 2), "unit": "T op/s",
+                                         "frac": round(evals * BWD_OPS_PER_EVAL / (rb_ms * 1e-3) / 1e12
+                                                       / PEAK_VALU_TOPS, 4)}}
 
 
 def extra_measurements(steps, warmup):
