@@ -132,3 +132,19 @@ def test_compose_rejects_bad_arguments(dev):
     bad[1] = bad[1][:4] + (g4d.placement(rotation=(0, 0, 0, 0)),)
     assert status(bad, g4d.DeviceSplats(n, 3, None, DEV)) == g4d.EINVAL
     torch.cuda.synchronize()
+
+
+def test_composition_workload_full_size(dev):
+    """The composition workload the benchmark times (2 x 50k Gaussians,
+    two kernel variants, placed, 800x800): the composed set against the
+    oracle's compose under the deformation bar, and its frame under the
+    render bars (keys bit-exact, image within 1e-4)."""
+    items, cams, ts = synth.composition()
+    items = [(g, pl, m, float(ts[7]), place) for g, pl, m, place in items]
+    host, _, _ = _compose(items, 3)
+    ref = oracle.compose(items, 3)
+    errs = _max_errors(host, ref)
+    log("[compose full size] " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+    assert max(errs.values()) <= max(def_tol(it[1]) for it in items), errs
+    s = oracle.to_splats32(host, host.sh, 3)
+    _check_render(s, cams[3], "composition 2 x 50k 800x800", capacity=16 << 20)
