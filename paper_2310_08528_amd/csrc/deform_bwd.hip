@@ -16,6 +16,11 @@
 //                         grid coordinates receive the bilinear slopes
 //                         (zero at and beyond the box border, as the border
 //                         clamp of the query has no slope there).
+// The three time planes (xt, yt, zt) take every Gaussian's update in the two
+// rows of the frame's t: when those rows fit (2 x res x F per plane and
+// scale, at most kTimeLds bytes in all), a block sums its updates to them in
+// LDS and adds the sums to the plane gradients once (the spatial planes
+// scatter straight to global memory).
 // W1 is read from global memory (L1/L2-resident: every block reads it); the
 // head weights, their biases and the per-row gradient pointers are staged in
 // LDS once per block (the heads are selected by a runtime row index, which
@@ -48,7 +53,12 @@ struct BwdJob {
     float bmin[3], bmax[3];
     int n, n_sh_rows;                    // n_sh_rows: 3 (d+1)^2 of the Gaussians
     float t;
+    int tp_floats;                       // LDS floats of the time-plane rows (0: scatter to global)
+    int tp_off[kMaxScalesB][3];          // offset of plane (l, xt/yt/zt) in that region
 };
+
+constexpr int kTimeLds = 32 * 1024;
+constexpr size_t kLdsMax = 160 * 1024;   // LDS per CU (and per block) on gfx950
 
 __device__ constexpr int axis_a(int p) { return p == 2 ? 1 : (p == 5 ? 2 : (p == 4 ? 1 : 0)); }
 __device__ constexpr int axis_b(int p) { return p == 0 ? 1 : (p == 1 || p == 2 ? 2 : 3); }
@@ -89,6 +99,7 @@ __global__ __launch_bounds__(kThreads) void k_deform_bwd(BwdJob J, int rows) {
     float *s_dm = s_dd + kGB * DS;       // [64][3]: dL/d canonical mean
     float *s_w2 = s_dm + kGB * 3;        // [rows][HID+1]: head weights
     float *s_b2 = s_w2 + rows * HH;      // [rows]
+    float *s_tp = s_b2 + rows;           // [tp_floats]: time-plane rows of this frame's t
     __shared__ float *s_dw[64];          // gradient row of head row r (null: padding)
     __shared__ float *s_db[64];
     const int tid = threadIdx.x;
@@ -111,6 +122,7 @@ __global__ __launch_bounds__(kThreads) void k_deform_bwd(BwdJob J, int rows) {
         int hq, k;
         s_w2[r * HH + j] = head_of(J, r, hq, k) ? J.hw[hq][(size_t)k * HID + j] : 0.0f;
     }
+    for (int idx = tid; idx < J.tp_floats; idx += kThreads) s_tp[idx] = 0.0f;
 
     // ---- A. encoder (as in the forward)
     constexpr int LPG = F / 4;
@@ -337,9 +349,12 @@ __global__ __launch_bounds__(kThreads) void k_deform_bwd(BwdJob J, int rows) {
                     const float wa = wa_[p], wb = wb_[p];
                     const float w00 = (1.0f - wa) * (1.0f - wb), w10 = wa * (1.0f - wb);
                     const float w01 = (1.0f - wa) * wb, w11 = wa * wb;
-                    float *gb = J.d_planes[l * 6 + p] + off[p];
                     const size_t rowF = (size_t)na_[p] * F;
                     const float dvv[4] = {dv.x, dv.y, dv.z, dv.w};
+                    // time planes: rows ib and ib + 1 of the LDS copy (same t for every Gaussian)
+                    const bool in_lds = p >= 3 && J.tp_floats > 0;
+                    float *gb = in_lds ? s_tp + J.tp_off[l][p - 3] + (off[p] % rowF)
+                                       : J.d_planes[l * 6 + p] + off[p];
 #pragma unroll
                     for (int c = 0; c < 4; ++c) {
                         if (dvv[c] == 0.0f) continue;
@@ -384,6 +399,26 @@ __global__ __launch_bounds__(kThreads) void k_deform_bwd(BwdJob J, int rows) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) J.d_means[(size_t)k * n + g0 + tid] = s_dm[tid * 3 + k];
     }
+    if (J.tp_floats > 0) {
+        // the block's time-plane sums, one global atomic per touched value
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            int ib;
+            float wb;
+            grid_coord(J.t, J.gscale[l][3], J.res[l][3], ib, wb);
+#pragma unroll
+            for (int p = 3; p < 6; ++p) {
+                const int na = J.res[l][axis_a(p)];
+                const int cnt = 2 * na * F;
+                const float *src = s_tp + J.tp_off[l][p - 3];
+                float *dst = J.d_planes[l * 6 + p] + (size_t)ib * na * F;   // rows ib, ib + 1
+                for (int i = tid; i < cnt; i += kThreads) {
+                    const float v = src[i];
+                    if (v != 0.0f) atomicAdd(dst + i, v);
+                }
+            }
+        }
+    }
 }
 
 // Up to 40 arrays cleared in one launch.
@@ -412,9 +447,9 @@ const BwdEntry kBwdKernels[] = {
     G4D_BWD_ENTRY(32, 3, 64), G4D_BWD_ENTRY(32, 3, 128),
 };
 
-size_t bwd_smem(int K, int HID, int rows) {
+size_t bwd_smem(int K, int HID, int rows, int tp_floats) {
     return ((size_t)kGB * (K + 1) + 2 * (size_t)kGB * (HID + 1) + kGB * 65 + kGB * 3 + (size_t)rows * (HID + 1) +
-            rows) * 4;
+            rows + tp_floats) * 4;
 }
 
 }  // namespace
@@ -490,15 +525,25 @@ g4d_status deform_backward(const g4d_gaussians *G, const g4d_planes *P, const g4
     J.n = n;
     J.n_sh_rows = n_sh;
     J.t = t;
+    {
+        int tp = 0;
+        for (int l = 0; l < P->n_scales; ++l)
+            for (int a = 0; a < 3; ++a) {   // xt, yt, zt: spatial axis a, time rows
+                J.tp_off[l][a] = tp;
+                tp += 2 * P->res[l][a] * P->feat;
+            }
+        J.tp_floats = (size_t)tp * 4 <= (size_t)kTimeLds ? tp : 0;
+        if (bwd_smem(K, hid, rows, J.tp_floats) > kLdsMax) J.tp_floats = 0;
+    }
     hipLaunchKernelGGL(k_fill_list, dim3(64, (unsigned)fl.n), dim3(256), 0, s, fl);
     if (n > 0) {
-        const size_t smem = bwd_smem(K, hid, rows);
+        const size_t smem = bwd_smem(K, hid, rows, J.tp_floats);
         static bool attr_done[sizeof(kBwdKernels) / sizeof(kBwdKernels[0])] = {};
         const size_t idx = (size_t)(ke - kBwdKernels);
         if (!attr_done[idx]) {   // the largest head count: 64 rows
             G4D_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void *>(ke->fn),
                                               hipFuncAttributeMaxDynamicSharedMemorySize,
-                                              (int)bwd_smem(K, hid, 64)));
+                                              (int)std::min(bwd_smem(K, hid, 64, kTimeLds / 4), kLdsMax)));
             attr_done[idx] = true;
         }
         hipLaunchKernelGGL(ke->fn, dim3((n + kGB - 1) / kGB), dim3(kThreads), smem, s, J, rows);
