@@ -14,10 +14,24 @@ __global__ __launch_bounds__(1024) void k_l1(const float *__restrict__ img, cons
                                             float *__restrict__ grad) {
     __shared__ float s_part[16];
     float acc = 0.0f;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    const size_t first = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    auto sgn = [&](float d) { return d > 0.0f ? inv_count : (d < 0.0f ? -inv_count : 0.0f); };
+    // four values per load where the arrays allow it (16-byte aligned)
+    const bool vec = ((reinterpret_cast<uintptr_t>(img) | reinterpret_cast<uintptr_t>(target) |
+                       reinterpret_cast<uintptr_t>(grad)) & 15) == 0;
+    const size_t n4 = vec ? count / 4 : 0;
+    for (size_t i = first; i < n4; i += stride) {
+        const float4 a = reinterpret_cast<const float4 *>(img)[i];
+        const float4 b = reinterpret_cast<const float4 *>(target)[i];
+        const float4 d = make_float4(a.x - b.x, a.y - b.y, a.z - b.z, a.w - b.w);
+        acc += (fabsf(d.x) + fabsf(d.y)) + (fabsf(d.z) + fabsf(d.w));
+        if (grad) reinterpret_cast<float4 *>(grad)[i] = make_float4(sgn(d.x), sgn(d.y), sgn(d.z), sgn(d.w));
+    }
+    for (size_t i = 4 * n4 + first; i < count; i += stride) {
         const float d = img[i] - target[i];
         acc += fabsf(d);
-        if (grad) grad[i] = d > 0.0f ? inv_count : (d < 0.0f ? -inv_count : 0.0f);
+        if (grad) grad[i] = sgn(d);
     }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
