@@ -17,9 +17,10 @@
 //                     then adds each entry's 2D gradient (u, v, conic, colour,
 //                     opacity) to the Gaussian with one global atomic per
 //                     component, spread over all 256 threads.  The wave sums
-//                     are DPP butterflies inside each 16-lane row plus four
-//                     readlanes (lane shuffles through the LDS crossbar cost
-//                     twice as much here).
+//                     are DPP butterflies inside each 16-lane row, whose four
+//                     row sums go to the accumulator by LDS atomics (lane
+//                     shuffles through the LDS crossbar cost twice as much,
+//                     and readlanes across the rows about as much again).
 //   k_preprocess_bwd  per Gaussian: the 2D gradient back through the conic
 //                     inverse, Sigma' = J W Sigma W^T J^T (with J's
 //                     dependence on the camera-space mean and the frustum
@@ -86,16 +87,13 @@ template <int CTRL>
 __device__ __forceinline__ float dpp(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
 }
-__device__ __forceinline__ float wave_sum(float v) {
+// Sum over each row of 16 lanes; every lane of the row receives it.
+__device__ __forceinline__ float row_sum(float v) {
     v += dpp<0xb1>(v);    // quad_perm [1, 0, 3, 2]: lane ^ 1
     v += dpp<0x4e>(v);    // quad_perm [2, 3, 0, 1]: lane ^ 2
     v += dpp<0x141>(v);   // row_half_mirror: the other quad of the half-row
     v += dpp<0x140>(v);   // row_mirror: the other half of the row
-    const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
-    const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
-    const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
-    const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
-    return (r0 + r1) + (r2 + r3);
+    return v;
 }
 
 __global__ __launch_bounds__(256) void k_blend_bwd(const uint4 *__restrict__ order, const uint32_t *__restrict__ gids,
@@ -220,13 +218,15 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const uint4 *__restrict__ ord
             if (__builtin_amdgcn_ballot_w64(act) != 0) {
                 float sum[kG2];
 #pragma unroll
-                for (int k = 0; k < kG2; ++k) sum[k] = wave_sum(v[k]);
-                // lane k adds component k of the wave's sum into the chunk
-                // accumulator (LDS atomics: the four quadrants meet here)
+                for (int k = 0; k < kG2; ++k) sum[k] = row_sum(v[k]);
+                // lane k of each row adds component k of its row's sum into the
+                // chunk accumulator (LDS atomics: the rows and the four
+                // quadrants meet there)
+                const int rk = lane & 15;
                 float mine = sum[0];
 #pragma unroll
-                for (int k = 1; k < kG2; ++k) mine = lane == k ? sum[k] : mine;
-                if (lane < kG2 && mine != 0.0f) atomicAdd(&sAcc[Sl[j] * kG2 + lane], mine);
+                for (int k = 1; k < kG2; ++k) mine = rk == k ? sum[k] : mine;
+                if (rk < kG2 && mine != 0.0f) atomicAdd(&sAcc[Sl[j] * kG2 + rk], mine);
             }
         }
         __syncthreads();
