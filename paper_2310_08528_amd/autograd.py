@@ -147,15 +147,25 @@ def _function():
 _FN = None
 
 
-def render_image(scene: Scene4D, cam, t: float, ws: g4d.RenderWorkspace):
+def render_image(scene: Scene4D, cam, t: float, ws: g4d.RenderWorkspace, check: bool = True):
     """The frame of ``scene`` at time t through ``cam`` ([3][H][W], FP32),
     differentiable with respect to scene.parameters().  The workspace holds
     the frame's sorted lists until the backward: do not render with it in
-    between."""
+    between.  With ``check`` (one stream synchronisation) a frame whose tile
+    instances exceeded the workspace capacity raises G4DError(ECAPACITY)
+    instead of returning an image and gradients of truncated lists."""
     global _FN
     if _FN is None:
         _FN = _function()
-    return _FN.apply(scene, cam, float(t), ws, *scene.parameters())
+    img = _FN.apply(scene, cam, float(t), ws, *scene.parameters())
+    if check:
+        st = g4d.read_status(ws)
+        if st.overflow:
+            raise g4d.G4DError(g4d.ECAPACITY, f"render_image: {st.instances} instances, capacity "
+                                              f"{ws.capacity}")
+        if st.sort_error:
+            raise g4d.G4DError(g4d.EDEVICE, "render_image: sort")
+    return img
 
 
 def l1_loss(image, target):

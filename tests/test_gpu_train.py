@@ -217,3 +217,13 @@ def test_autograd_with_colour_and_opacity_heads(dev):
         worst[k] = np.abs(got - ref[k]).max() / max(np.abs(ref[k]).max(), 1e-30)
     log("[autograd heads] " + " ".join(f"{k}={v:.1e}" for k, v in worst.items()))
     assert max(worst.values()) <= 2e-4, worst
+
+
+def test_render_image_reports_capacity_overflow(dev):
+    sc = synth.config1(plane_dist="uniform", n=500)
+    cam = synth.look_at_camera((0.0, 0.0, 4.0), (0.0, 0.0, 0.0), 64, 64, 50.0)
+    scene = ga.Scene4D(sc.gaussians, sc.planes, sc.mlp, DEV)
+    ws = g4d.RenderWorkspace(scene.n, 64, 64, 100, DEV)      # far too few instances
+    with pytest.raises(g4d.G4DError) as e:
+        ga.render_image(scene, cam, 0.5, ws)
+    assert e.value.status == g4d.ECAPACITY
