@@ -406,9 +406,8 @@ def time_training_step(steps, warmup):
 def extra_measurements(steps, warmup):
     """The large configuration (300k Gaussians, planes 64/128/256 x t150,
     MLP 96-128-10, 1352x1014) with the FP32 and the BF16-input MFMA MLP, the
-    100k workload with the colour and opacity heads, a training step of the
-    small configuration at 800x800, the composition workload, and the 100k
-    workload's generator swept over N at 800x800."""
+    100k workload with the colour and opacity heads, the composition
+    workload, and the 100k workload's generator swept over N at 800x800."""
     from paper_2310_08528_amd import g4d, synth
     out = {}
     log("extra: large configuration")
@@ -423,8 +422,6 @@ def extra_measurements(steps, warmup):
         "workload": "100k Gaussians, SH3, the 100k configuration's field; decoder with the colour "
                     "(48 rows) and opacity heads, 800x800",
         "fp32_mlp": time_scene(synth.config2(colour_opacity=True), g4d.MLP_F32, steps, warmup)}
-    log("extra: training step")
-    out["training_step"] = time_training_step(steps, warmup)
     log("extra: composition")
     out["composition"] = time_composition(steps, warmup)
     out["sweep_n"] = {}
@@ -684,6 +681,9 @@ def main():
     log("stages done")
     if not args.no_serve:
         out["serving"] = serving_bench(args.serve_seconds, args.serve_rate, args.serve_budget_gb, args.serve_slots)
+    # the training direction on its own workload (a few seconds; not part of `value`)
+    log("training iteration")
+    out["training"] = time_training_step(200, 20)
     if args.extra:
         out["extra"] = extra_measurements(min(K, 200), 20)
     if not args.no_cpu_baseline:
