@@ -323,7 +323,10 @@ g4d_status g4d_set_stage_events(void *const *events, int32_t count);
  * last contributing entry, redoing the forward's binary32 alpha (so skip and
  * stop decisions are the forward's); alpha clamped at 0.99 passes no
  * gradient to opacity or position.  Gradients with respect to the camera are
- * not computed.  Device pointers; the call allocates nothing. */
+ * not computed.  A render that overflowed its instance capacity (see
+ * g4d_read_status) has truncated lists, and so do these gradients.
+ * G4D_EINVAL for a null argument or sizes outside the workspace's maxima.
+ * Device pointers; the call allocates nothing. */
 g4d_status g4d_render_backward(const g4d_splats *G, const g4d_camera *C, const g4d_workspace *ws,
                                const float *final_T, const int32_t *n_contrib, const float *grad_image,
                                const g4d_splats_grad *grad, void *stream);
@@ -351,15 +354,18 @@ typedef struct {
  * an atomic scatter of the bilinear weights; the grid coordinates carry the
  * bilinear slopes, zero for a mean on or outside the box border (where the
  * query is clamped) and for the time axis (t is not a parameter).
- * FP32 decoder only (G4D_EUNSUPPORTED for G4D_MLP_BF16).  Device pointers;
- * the call allocates nothing. */
+ * FP32 decoder only (G4D_EUNSUPPORTED for G4D_MLP_BF16, and for a
+ * (feat, n_scales, hidden) outside the compiled set); G4D_EINVAL for a
+ * null argument, a head weight without its bias or gradient array, or t
+ * outside [0, 1].  Device pointers; the call allocates nothing. */
 g4d_status g4d_deform_backward(const g4d_gaussians *G, const g4d_planes *P, const g4d_mlp *M, float t,
                                const g4d_splats_grad *grad_out, const g4d_deform_grad *grad, void *stream);
 
 /* The image term of the training loss (Eq. 9): loss = mean |image - target|
  * over `count` values (a device scalar, cleared by the call; may be NULL)
  * and grad = dloss/dimage = sign(image - target) / count (0 where equal;
- * may be NULL).  Device pointers. */
+ * may be NULL).  G4D_EINVAL for null inputs, count < 1 or both outputs
+ * NULL.  Device pointers. */
 g4d_status g4d_l1_loss(const float *image, const float *target, int64_t count, float *loss, float *grad,
                        void *stream);
 
@@ -369,8 +375,10 @@ g4d_status g4d_l1_loss(const float *image, const float *target, int64_t count, f
  * of neighbouring cells along a plus the same along b, summed over planes,
  * times `weight` (1 in Eq. 9).  Writes the value into the device scalar
  * `loss` (cleared by the call; may be NULL) and ADDS weight x dtv/dcell to
- * grad->plane (may be NULL), so it follows g4d_deform_backward.  Device
- * pointers. */
+ * grad->plane (may be NULL), so it follows g4d_deform_backward.
+ * G4D_EINVAL for a plane set outside the supported shapes (1-3 scales, F 16
+ * or 32, resolutions >= 2), a null plane or gradient plane, or both outputs
+ * NULL.  Device pointers. */
 g4d_status g4d_tv_loss(const g4d_planes *P, float weight, float *loss, g4d_deform_grad *grad, void *stream);
 
 /* One trainable tensor of an Adam update: count FP32 values of param, their
@@ -387,7 +395,9 @@ typedef struct {
 /* Adam (the optimiser the method trains with): for step >= 1,
  * m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
  * param -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps),
- * for 1 <= n <= 64 tensors in one launch.  Device pointers. */
+ * for 1 <= n <= 64 tensors in one launch.  G4D_EINVAL for a null pointer,
+ * n or a count out of range, step < 1 or a beta outside [0, 1).  Device
+ * pointers. */
 g4d_status g4d_adam_step(const g4d_adam_tensor *tensors, int32_t n, float beta1, float beta2, float eps,
                          int32_t step, void *stream);
 
