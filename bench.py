@@ -102,8 +102,9 @@ def host_cores() -> int:
     return max(1, min(n, int(os.environ.get("OMP_NUM_THREADS", n))))
 
 
-def cpu_baseline(sc, frames, n_frames: int):
-    """The CPU oracle (FP64 deform + render) on the first n_frames frames."""
+def cpu_baseline(sc, frames, n_frames: int, single_frames: int = 1):
+    """The CPU oracle (FP64 deform + render) on the first n_frames frames on
+    all host cores, then on the first single_frames frames on one thread."""
     import oracle
     cores = host_cores()
     oracle.set_threads(cores)
@@ -112,9 +113,20 @@ def cpu_baseline(sc, frames, n_frames: int):
     for (ci, t) in frames[:n_frames]:
         oracle.deform_render(sc.gaussians, sc.planes, sc.mlp, t, sc.cameras[ci])
     dt = time.perf_counter() - t0
-    return {"value": n_frames / dt, "unit": "frames/s", "cores": cores, "kind": "oracle",
-            "sample": f"{n_frames} full frames (deform + render, 100k Gaussians, 800x800) of the same "
-                      f"frame sequence; {dt:.1f} s on {cores} threads of {cpu_model()}"}
+    out = {"value": n_frames / dt, "unit": "frames/s", "cores": cores, "kind": "oracle",
+           "sample": f"{n_frames} full frames (deform + render, 100k Gaussians, 800x800) of the same "
+                     f"frame sequence; {dt:.1f} s on {cores} threads of {cpu_model()}"}
+    if single_frames > 0:
+        # the same oracle on one thread (its scaling over the host cores)
+        oracle.set_threads(1)
+        t0 = time.perf_counter()
+        for (ci, t) in frames[:single_frames]:
+            oracle.deform_render(sc.gaussians, sc.planes, sc.mlp, t, sc.cameras[ci])
+        d1 = time.perf_counter() - t0
+        oracle.set_threads(cores)
+        out["single_thread"] = {"value": single_frames / d1, "unit": "frames/s", "cores": 1,
+                                "sample": f"the first {single_frames} of those frames; {d1:.1f} s"}
+    return out
 
 
 def serving_bench(seconds: float, rate: float, budget_gb: float, slots: int, warm_s: float = 2.0,
@@ -471,6 +483,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-frames", type=int, default=20)
+    ap.add_argument("--cpu-single-frames", type=int, default=1)
     ap.add_argument("--n", type=int, default=100_000)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -688,7 +701,7 @@ def main():
         out["extra"] = extra_measurements(min(K, 200), 20)
     if not args.no_cpu_baseline:
         log("cpu baseline")
-        out["cpu_baseline"] = cpu_baseline(sc, frames, args.cpu_frames)
+        out["cpu_baseline"] = cpu_baseline(sc, frames, args.cpu_frames, args.cpu_single_frames)
     for e in blend_ev:
         ev.destroy(e[0]); ev.destroy(e[1])
     print(json.dumps(out), flush=True)
