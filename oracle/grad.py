@@ -225,8 +225,12 @@ def render_grads(splats, cam, ranges, vals, weight):
     s["sh_degree"] = int(splats.sh_degree)
     img = render_torch(s, cam, ranges, vals)
     loss = (torch.as_tensor(np.asarray(weight, np.float64)) * img).sum()
-    loss.backward()
-    return img.detach().numpy(), {k: s[k].grad.numpy() for k in SPLAT_KEYS}
+    # a frame that no Gaussian reaches is the background alone (Eq. 4 over
+    # empty lists): the loss is constant and every gradient is zero
+    if loss.requires_grad:
+        loss.backward()
+    return img.detach().numpy(), {k: (s[k].grad.numpy() if s[k].grad is not None else np.zeros(tuple(s[k].shape)))
+                                  for k in SPLAT_KEYS}
 
 
 def _leaf_inputs(g, planes, mlp):

@@ -146,3 +146,34 @@ def test_deform_render_gradient_matches_central_differences():
         big = np.unravel_index(np.argsort(np.abs(gq), axis=None)[-2:], gq.shape)
         picks += [(f"plane0_{q}", tuple(int(i[k]) for i in big)) for k in range(2)]
     _fd_check(f, params, flat, picks, eps=1e-6, rtol=5e-5)
+
+
+def test_culled_gaussians_carry_no_gradient():
+    """A frame no Gaussian reaches is the background alone: every gradient
+    is zero.  With one visible Gaussian added, the culled ones still get zero
+    and the visible one gets what it gets alone (they share no list)."""
+    from tests.helpers import axis_camera, splats
+    cam = axis_camera(width=40, height=24, cx=19.5, cy=11.5, bg=(0.1, 0.2, 0.3))
+    culled = ([[0, 0, -2.0], [0, 0, 0.1], [500.0, 0, 3.0]], [[0.1] * 3] * 3, [[1, 0, 0, 0]] * 3, [0.9] * 3)
+    s = splats(*culled, colours=[[1, 1, 1]] * 3)
+    r = oracle.render(s, cam)
+    w = np.random.default_rng(7).choice([-1.0, 1.0], size=r.image.shape)
+    img, g = og.render_grads(s, cam, r.ranges, r.vals, w)
+    assert r.K == 0
+    np.testing.assert_array_equal(img, np.broadcast_to(np.float32([0.1, 0.2, 0.3]).astype(np.float64)[:, None, None], img.shape))
+    for k in og.SPLAT_KEYS:
+        assert not np.abs(g[k]).any(), k
+    vis = ([[0.05, -0.02, 2.0]], [[0.08, 0.05, 0.06]], [[0.9, 0.1, 0.3, 0.2]], [0.7])
+    q = np.array(vis[2][0]) / np.linalg.norm(vis[2][0])
+    vis = (vis[0], vis[1], [q.tolist()], vis[3])
+    both = splats(*[a + b for a, b in zip(culled, vis)], colours=[[1, 1, 1]] * 3 + [[0.2, 0.6, 0.9]])
+    alone = splats(*vis, colours=[[0.2, 0.6, 0.9]])
+    rb, ra = oracle.render(both, cam), oracle.render(alone, cam)
+    assert rb.K == ra.K > 0
+    wb = w * (rb.flag == 0)[None] * (ra.flag == 0)[None]
+    _, gb = og.render_grads(both, cam, rb.ranges, rb.vals, wb)
+    _, ga = og.render_grads(alone, cam, ra.ranges, ra.vals, wb)
+    for k in og.SPLAT_KEYS:
+        assert not np.abs(gb[k][..., :3]).any(), k
+        np.testing.assert_allclose(gb[k][..., 3:], ga[k], rtol=1e-12, atol=1e-15)
+    assert np.abs(ga["means"]).max() > 0
