@@ -93,6 +93,56 @@ def test_render_backward_small_config_subset(dev):
     assert max(errs.values()) <= GRAD_TOL, errs
 
 
+def test_backward_empty_and_fully_culled(dev):
+    """No Gaussians: both backward calls succeed and the deformation
+    backward still clears every plane and decoder gradient.  Every Gaussian
+    culled (behind the camera, inside the near plane, NaN, off-screen): every
+    splat gradient is exactly zero, as the oracle's is."""
+    import dataclasses
+    import torch
+    from tests.helpers import axis_camera, splats
+    cam = axis_camera(width=40, height=24, cx=19.5, cy=11.5, bg=(0.1, 0.2, 0.3))
+    log("[bwd edge] everything culled")
+    s = splats([[0, 0, -2.0], [0, 0, 0.1], [np.nan, 0, 3.0], [500.0, 0, 3.0]], [[0.1] * 3] * 4,
+               [[1, 0, 0, 0]] * 4, [0.9] * 4, colours=[[1, 1, 1]] * 4)
+    S, ws, img, T, nc = _gpu_forward(s, cam)
+    r = oracle.render(s, cam)
+    assert r.K == 0
+    w = _weights(r, 7)
+    grad = g4d.DeviceSplatsGrad(S.n, S.sh_degree, DEV)
+    for k in og.SPLAT_KEYS:
+        getattr(grad, k).fill_(float("nan"))
+    g4d.render_backward(S, cam, ws, T, nc, torch.as_tensor(w, dtype=torch.float32).to(DEV), grad)
+    torch.cuda.synchronize()
+    _, ref = og.render_grads(s, cam, r.ranges, r.vals, w)
+    for k in og.SPLAT_KEYS:
+        np.testing.assert_array_equal(getattr(grad, k).cpu().numpy().reshape(ref[k].shape), 0.0)
+        assert not np.abs(ref[k]).max() > 0.0, k
+
+    log("[bwd edge] empty set")
+    sc = synth.tiny_scene(5, n=40, sh_degree=1)
+    g = sc.gaussians
+    g0 = dataclasses.replace(g, means=g.means[:, :0], log_scales=g.log_scales[:, :0], quats=g.quats[:, :0],
+                             opacity_logits=g.opacity_logits[:0], sh=g.sh[..., :0])
+    G, P, M = g4d.DeviceGaussians(g0, DEV), g4d.DevicePlanes(sc.planes, DEV), g4d.DeviceMLP(sc.mlp, DEV)
+    assert G.n == 0
+    S0 = g4d.DeviceSplats(0, 1, G.sh, DEV)
+    ws0 = g4d.RenderWorkspace(1, cam.width, cam.height, 4096, DEV)
+    g4d.deform(G, P, M, 0.4, S0)
+    g4d.render(S0, cam, ws0, img, T, nc)
+    gs = g4d.DeviceSplatsGrad(0, 1, DEV)
+    g4d.render_backward(S0, cam, ws0, T, nc, torch.zeros_like(img), gs)
+    gd = g4d.DeviceDeformGrad(G, P, M, DEV)
+    outs = [x for lv in gd.planes for x in lv] + [v for v in gd.w.values() if v is not None]
+    for x in outs:
+        x.fill_(float("nan"))
+    g4d.deform_backward(G, P, M, 0.4, gs, gd)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(T.cpu().numpy(), 1.0)
+    for x in outs:
+        assert x.numel() > 0 and not torch.any(x != 0).item()
+
+
 # ---------------------------------------------------------------- deformation
 
 def _deform_compare(gpu, ref, name, tol):
