@@ -579,13 +579,10 @@ g4d_status launch(DeformBatch &B, const KernelEntry *ke, hipStream_t s) {
     }
     if (blocks == 0) return G4D_OK;
     B.n_blocks = blocks;
-    static bool attr_done[sizeof(kDeformKernels) / sizeof(kDeformKernels[0])] = {};
-    size_t idx = (size_t)(ke - kDeformKernels);
-    if (!attr_done[idx]) {
-        G4D_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void *>(ke->fn),
-                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)ke->smem));
-        attr_done[idx] = true;
-    }
+    static std::atomic<uint64_t> attr_done[sizeof(kDeformKernels) / sizeof(kDeformKernels[0])];
+    const size_t idx = (size_t)(ke - kDeformKernels);
+    if (g4d_status st = ensure_max_lds(reinterpret_cast<const void *>(ke->fn), attr_done[idx], (int)ke->smem))
+        return st;
     hipLaunchKernelGGL(ke->fn, dim3(8 * ((blocks + 7) / 8)), dim3(kThreads), ke->smem, s, B);
     G4D_HIP_CHECK(hipGetLastError());
     return G4D_OK;

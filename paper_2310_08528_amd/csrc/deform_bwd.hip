@@ -538,14 +538,12 @@ g4d_status deform_backward(const g4d_gaussians *G, const g4d_planes *P, const g4
     hipLaunchKernelGGL(k_fill_list, dim3(64, (unsigned)fl.n), dim3(256), 0, s, fl);
     if (n > 0) {
         const size_t smem = bwd_smem(K, hid, rows, J.tp_floats);
-        static bool attr_done[sizeof(kBwdKernels) / sizeof(kBwdKernels[0])] = {};
+        static std::atomic<uint64_t> attr_done[sizeof(kBwdKernels) / sizeof(kBwdKernels[0])];
         const size_t idx = (size_t)(ke - kBwdKernels);
-        if (!attr_done[idx]) {   // the largest head count: 64 rows
-            G4D_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void *>(ke->fn),
-                                              hipFuncAttributeMaxDynamicSharedMemorySize,
-                                              (int)std::min(bwd_smem(K, hid, 64, kTimeLds / 4), kLdsMax)));
-            attr_done[idx] = true;
-        }
+        // the largest head count (64 rows) sets the limit
+        if (g4d_status st = ensure_max_lds(reinterpret_cast<const void *>(ke->fn), attr_done[idx],
+                                           (int)std::min(bwd_smem(K, hid, 64, kTimeLds / 4), kLdsMax)))
+            return st;
         hipLaunchKernelGGL(ke->fn, dim3((n + kGB - 1) / kGB), dim3(kThreads), smem, s, J, rows);
     }
     G4D_HIP_CHECK(hipGetLastError());

@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <atomic>
 #include <type_traits>
 
 #include "../../include/g4d.h"
@@ -170,3 +171,20 @@ hipEvent_t stage_event(int i);
             return G4D_EHIP;                                  \
         }                                                     \
     } while (0)
+
+namespace g4d {
+
+// Raises a kernel's dynamic-LDS limit to `bytes` once per device (the
+// attribute is held per device); `done` holds one bit per device id and may
+// be shared by concurrent callers.
+inline g4d_status ensure_max_lds(const void *fn, std::atomic<uint64_t> &done, int bytes) {
+    int dev = 0;
+    G4D_HIP_CHECK(hipGetDevice(&dev));
+    const uint64_t bit = (dev >= 0 && dev < 64) ? (1ull << dev) : 0ull;
+    if (bit && (done.load(std::memory_order_acquire) & bit)) return G4D_OK;
+    G4D_HIP_CHECK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+    if (bit) done.fetch_or(bit, std::memory_order_release);
+    return G4D_OK;
+}
+
+}  // namespace g4d
