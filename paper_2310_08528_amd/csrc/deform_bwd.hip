@@ -1,6 +1,7 @@
 // Backward of the Gaussian deformation field on gfx950 (Sec. 4.2, Eq. 7-8).
 //
-// One 256-thread block per 64 Gaussians, FP32 decoder.  The block first
+// One 256-thread block per 64 Gaussians (16 up to 8192 Gaussians, so that
+// small sets still spread over the compute units), FP32 decoder.  The block first
 // recomputes the forward (encoder f_h, hidden h, head outputs) in LDS, then:
 //   Eq. 8 + activations   d(X + dX) -> dX and dX_canonical; d exp(log s + ds)
 //                         -> d log s = d ds = ds' s'; d normalise(r + dr) ->
@@ -33,7 +34,9 @@
 namespace g4d {
 namespace {
 
-constexpr int kGB = 64;
+constexpr int kGB = 64;        // Gaussians per block
+constexpr int kGBSmall = 16;   // ... when 64 would leave most compute units idle
+constexpr int kSmallN = 8192;  // up to this many Gaussians (128 blocks of 64)
 constexpr int kThreads = 256;
 constexpr int kMaxScalesB = 3;
 
@@ -87,23 +90,23 @@ __device__ __forceinline__ bool head_of(const BwdJob &J, int r, int &h, int &k) 
     return false;
 }
 
-template <int F, int L, int HID>
+template <int F, int L, int HID, int GB>
 __global__ __launch_bounds__(kThreads) void k_deform_bwd(BwdJob J, int rows) {
     constexpr int K = F * L;
     constexpr int FH = K + 1, HH = HID + 1, DS = 65;
     extern __shared__ __attribute__((aligned(16))) float smem[];
-    float *s_fh = smem;                  // [64][K+1]: f_h, later df_h
-    float *s_h = s_fh + kGB * FH;        // [64][HID+1]: h (after ReLU)
-    float *s_dz = s_h + kGB * HH;        // [64][HID+1]: dL/d(pre-activation)
-    float *s_dd = s_dz + kGB * HH;       // [64][65]: head outputs, then their gradients
-    float *s_dm = s_dd + kGB * DS;       // [64][3]: dL/d canonical mean
-    float *s_w2 = s_dm + kGB * 3;        // [rows][HID+1]: head weights
+    float *s_fh = smem;                  // [GB][K+1]: f_h, later df_h
+    float *s_h = s_fh + GB * FH;        // [GB][HID+1]: h (after ReLU)
+    float *s_dz = s_h + GB * HH;        // [GB][HID+1]: dL/d(pre-activation)
+    float *s_dd = s_dz + GB * HH;       // [GB][65]: head outputs, then their gradients
+    float *s_dm = s_dd + GB * DS;       // [GB][3]: dL/d canonical mean
+    float *s_w2 = s_dm + GB * 3;        // [rows][HID+1]: head weights
     float *s_b2 = s_w2 + rows * HH;      // [rows]
     float *s_tp = s_b2 + rows;           // [tp_floats]: time-plane rows of this frame's t
     __shared__ float *s_dw[64];          // gradient row of head row r (null: padding)
     __shared__ float *s_db[64];
     const int tid = threadIdx.x;
-    const int g0 = blockIdx.x * kGB;
+    const int g0 = blockIdx.x * GB;
     const int n = J.n;
     if (tid < rows) {
         int hq, k;
@@ -127,10 +130,12 @@ __global__ __launch_bounds__(kThreads) void k_deform_bwd(BwdJob J, int rows) {
     // ---- A. encoder (as in the forward)
     constexpr int LPG = F / 4;
     constexpr int GPP = kThreads / LPG;
+    constexpr int NPASS = (GB + GPP - 1) / GPP;   // a block of fewer Gaussians than GPP leaves threads idle
 #pragma unroll
-    for (int pass = 0; pass < kGB / GPP; ++pass) {
+    for (int pass = 0; pass < NPASS; ++pass) {
         const int gl = pass * GPP + tid / LPG, c4 = tid % LPG, g = g0 + gl;
-        const bool valid = g < n;
+        const bool in_blk = gl < GB;
+        const bool valid = in_blk && g < n;
         float x[4];
 #pragma unroll
         for (int k = 0; k < 3; ++k) x[k] = valid ? J.means[(size_t)k * n + g] - J.bmin[k] : 0.0f;
@@ -159,14 +164,16 @@ __global__ __launch_bounds__(kThreads) void k_deform_bwd(BwdJob J, int rows) {
                 prod.w *= w00 * v00.w + w10 * v10.w + w01 * v01.w + w11 * v11.w;
             }
             if (!valid) prod = make_float4(0.f, 0.f, 0.f, 0.f);
-            float *dst = s_fh + gl * FH + l * F + 4 * c4;
-            dst[0] = prod.x; dst[1] = prod.y; dst[2] = prod.z; dst[3] = prod.w;
+            if (in_blk) {
+                float *dst = s_fh + gl * FH + l * F + 4 * c4;
+                dst[0] = prod.x; dst[1] = prod.y; dst[2] = prod.z; dst[3] = prod.w;
+            }
         }
     }
     __syncthreads();
     // ---- B. h = ReLU(W1 f_h + b1); Gaussian fastest, so a weight is one broadcast load
-    for (int idx = tid; idx < kGB * HID; idx += kThreads) {
-        const int g = idx % kGB, j = idx / kGB;
+    for (int idx = tid; idx < GB * HID; idx += kThreads) {
+        const int g = idx % GB, j = idx / GB;
         float acc = J.b1[j];
         const float *w = J.w1 + (size_t)j * K;
         for (int i = 0; i < K; ++i) acc += w[i] * s_fh[g * FH + i];
@@ -174,8 +181,8 @@ __global__ __launch_bounds__(kThreads) void k_deform_bwd(BwdJob J, int rows) {
     }
     __syncthreads();
     // ---- C. head outputs delta = W2 h + b2 (padding rows: zero weights)
-    for (int idx = tid; idx < kGB * rows; idx += kThreads) {
-        const int g = idx % kGB, r = idx / kGB;
+    for (int idx = tid; idx < GB * rows; idx += kThreads) {
+        const int g = idx % GB, r = idx / GB;
         float acc = s_b2[r];
         const float *w = s_w2 + r * HH;
         for (int j = 0; j < HID; ++j) acc += w[j] * s_h[g * HH + j];
@@ -184,7 +191,7 @@ __global__ __launch_bounds__(kThreads) void k_deform_bwd(BwdJob J, int rows) {
     __syncthreads();
     // ---- Eq. 8 + activations, backward (one Gaussian per thread of wave 0);
     // the other waves copy the SH gradient (C' = C [+ dC]: dL/dC = dL/dC')
-    if (tid < kGB) {
+    if (tid < GB) {
         const int gl = tid, g = g0 + gl;
         float *dd = s_dd + gl * DS;
         if (g < n) {
@@ -234,15 +241,15 @@ __global__ __launch_bounds__(kThreads) void k_deform_bwd(BwdJob J, int rows) {
             for (int k = 0; k < 3; ++k) s_dm[gl * 3 + k] = 0.0f;
         }
     } else if (J.d_sh) {
-        for (int idx = tid - kGB; idx < kGB * J.n_sh_rows; idx += kThreads - kGB) {
-            const int gl = idx % kGB, r = idx / kGB, g = g0 + gl;
+        for (int idx = tid - GB; idx < GB * J.n_sh_rows; idx += kThreads - GB) {
+            const int gl = idx % GB, r = idx / GB, g = g0 + gl;
             if (g < n) J.d_sh[(size_t)r * n + g] = J.g_sh[(size_t)r * n + g];
         }
     }
     __syncthreads();
     // ---- heads backward: dz = (W2^T ddelta) * [h > 0]
-    for (int idx = tid; idx < kGB * HID; idx += kThreads) {
-        const int g = idx % kGB, j = idx / kGB;
+    for (int idx = tid; idx < GB * HID; idx += kThreads) {
+        const int g = idx % GB, j = idx / GB;
         float acc = 0.0f;
         for (int r = 0; r < rows; ++r) acc += s_w2[r * HH + j] * s_dd[g * DS + r];
         s_dz[g * HH + j] = s_h[g * HH + j] > 0.0f ? acc : 0.0f;
@@ -253,10 +260,10 @@ __global__ __launch_bounds__(kThreads) void k_deform_bwd(BwdJob J, int rows) {
         if (!s_dw[r]) continue;
         float acc = 0.0f;
         if (j < HID) {
-            for (int g = 0; g < kGB; ++g) acc += s_dd[g * DS + r] * s_h[g * HH + j];
+            for (int g = 0; g < GB; ++g) acc += s_dd[g * DS + r] * s_h[g * HH + j];
             if (acc != 0.0f) atomicAdd(s_dw[r] + j, acc);
         } else {
-            for (int g = 0; g < kGB; ++g) acc += s_dd[g * DS + r];
+            for (int g = 0; g < GB; ++g) acc += s_dd[g * DS + r];
             if (acc != 0.0f) atomicAdd(s_db[r], acc);
         }
     }
@@ -266,17 +273,17 @@ __global__ __launch_bounds__(kThreads) void k_deform_bwd(BwdJob J, int rows) {
         const int j = idx / (K + 1), i = idx % (K + 1);
         float acc = 0.0f;
         if (i < K) {
-            for (int g = 0; g < kGB; ++g) acc += s_dz[g * HH + j] * s_fh[g * FH + i];
+            for (int g = 0; g < GB; ++g) acc += s_dz[g * HH + j] * s_fh[g * FH + i];
             if (acc != 0.0f) atomicAdd(&J.d_w1[(size_t)j * K + i], acc);
         } else {
-            for (int g = 0; g < kGB; ++g) acc += s_dz[g * HH + j];
+            for (int g = 0; g < GB; ++g) acc += s_dz[g * HH + j];
             if (acc != 0.0f) atomicAdd(&J.d_b1[j], acc);
         }
     }
     __syncthreads();
     // df_h = W1^T dz (overwrites f_h)
-    for (int idx = tid; idx < kGB * K; idx += kThreads) {
-        const int g = idx % kGB, i = idx / kGB;
+    for (int idx = tid; idx < GB * K; idx += kThreads) {
+        const int g = idx % GB, i = idx / GB;
         float acc = 0.0f;
         for (int j = 0; j < HID; ++j) acc += J.w1[(size_t)j * K + i] * s_dz[g * HH + j];
         s_fh[g * FH + i] = acc;
@@ -284,9 +291,9 @@ __global__ __launch_bounds__(kThreads) void k_deform_bwd(BwdJob J, int rows) {
     __syncthreads();
     // ---- encoder backward (Eq. 7)
 #pragma unroll
-    for (int pass = 0; pass < kGB / GPP; ++pass) {
+    for (int pass = 0; pass < NPASS; ++pass) {
         const int gl = pass * GPP + tid / LPG, c4 = tid % LPG, g = g0 + gl;
-        const bool valid = g < n;
+        const bool valid = gl < GB && g < n;
         float x[4];
         bool inner[3];
 #pragma unroll
@@ -395,7 +402,7 @@ __global__ __launch_bounds__(kThreads) void k_deform_bwd(BwdJob J, int rows) {
         }
     }
     __syncthreads();
-    if (tid < kGB && g0 + tid < n) {
+    if (tid < GB && g0 + tid < n) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) J.d_means[(size_t)k * n + g0 + tid] = s_dm[tid * 3 + k];
     }
@@ -438,18 +445,18 @@ __global__ void k_fill_list(FillList f) {
 using BwdKernel = void (*)(BwdJob, int);
 struct BwdEntry {
     int feat, scales, hidden;
-    BwdKernel fn;
+    BwdKernel fn, fn_small;   // kGB and kGBSmall Gaussians per block
 };
-#define G4D_BWD_ENTRY(F, L, H) {F, L, H, k_deform_bwd<F, L, H>}
+#define G4D_BWD_ENTRY(F, L, H) {F, L, H, k_deform_bwd<F, L, H, kGB>, k_deform_bwd<F, L, H, kGBSmall>}
 const BwdEntry kBwdKernels[] = {
     G4D_BWD_ENTRY(16, 1, 32), G4D_BWD_ENTRY(16, 1, 64), G4D_BWD_ENTRY(16, 1, 128), G4D_BWD_ENTRY(16, 2, 64),
     G4D_BWD_ENTRY(16, 3, 64), G4D_BWD_ENTRY(32, 1, 64), G4D_BWD_ENTRY(32, 2, 64), G4D_BWD_ENTRY(32, 2, 128),
     G4D_BWD_ENTRY(32, 3, 64), G4D_BWD_ENTRY(32, 3, 128),
 };
 
-size_t bwd_smem(int K, int HID, int rows, int tp_floats) {
-    return ((size_t)kGB * (K + 1) + 2 * (size_t)kGB * (HID + 1) + kGB * 65 + kGB * 3 + (size_t)rows * (HID + 1) +
-            rows + tp_floats) * 4;
+size_t bwd_smem(int gb, int K, int HID, int rows, int tp_floats) {
+    return ((size_t)gb * (K + 1) + 2 * (size_t)gb * (HID + 1) + (size_t)gb * 65 + (size_t)gb * 3 +
+            (size_t)rows * (HID + 1) + rows + tp_floats) * 4;
 }
 
 }  // namespace
@@ -533,18 +540,21 @@ g4d_status deform_backward(const g4d_gaussians *G, const g4d_planes *P, const g4
                 tp += 2 * P->res[l][a] * P->feat;
             }
         J.tp_floats = (size_t)tp * 4 <= (size_t)kTimeLds ? tp : 0;
-        if (bwd_smem(K, hid, rows, J.tp_floats) > kLdsMax) J.tp_floats = 0;
+        if (bwd_smem(kGB, K, hid, rows, J.tp_floats) > kLdsMax) J.tp_floats = 0;   // either block size
     }
     hipLaunchKernelGGL(k_fill_list, dim3(64, (unsigned)fl.n), dim3(256), 0, s, fl);
     if (n > 0) {
-        const size_t smem = bwd_smem(K, hid, rows, J.tp_floats);
-        static std::atomic<uint64_t> attr_done[sizeof(kBwdKernels) / sizeof(kBwdKernels[0])];
+        const bool small = n <= kSmallN;
+        const int gb = small ? kGBSmall : kGB;
+        const BwdKernel fn = small ? ke->fn_small : ke->fn;
+        const size_t smem = bwd_smem(gb, K, hid, rows, J.tp_floats);
+        static std::atomic<uint64_t> attr_done[2][sizeof(kBwdKernels) / sizeof(kBwdKernels[0])];
         const size_t idx = (size_t)(ke - kBwdKernels);
         // the largest head count (64 rows) sets the limit
-        if (g4d_status st = ensure_max_lds(reinterpret_cast<const void *>(ke->fn), attr_done[idx],
-                                           (int)std::min(bwd_smem(K, hid, 64, kTimeLds / 4), kLdsMax)))
+        if (g4d_status st = ensure_max_lds(reinterpret_cast<const void *>(fn), attr_done[small][idx],
+                                           (int)std::min(bwd_smem(gb, K, hid, 64, kTimeLds / 4), kLdsMax)))
             return st;
-        hipLaunchKernelGGL(ke->fn, dim3((n + kGB - 1) / kGB), dim3(kThreads), smem, s, J, rows);
+        hipLaunchKernelGGL(fn, dim3((n + gb - 1) / gb), dim3(kThreads), smem, s, J, rows);
     }
     G4D_HIP_CHECK(hipGetLastError());
     return G4D_OK;

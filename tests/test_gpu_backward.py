@@ -178,9 +178,13 @@ def _gpu_deform_backward(sc, t, gout):
     return out
 
 
-@pytest.mark.parametrize("case", ["tiny_h32", "small_config", "headline_shape", "heads_sh3"])
+@pytest.mark.parametrize("case", ["tiny_h32", "small_config", "headline_shape", "heads_sh3", "blocks_of_64"])
 def test_deform_backward_matches_oracle(dev, case):
-    if case == "tiny_h32":
+    """Up to 8192 Gaussians the kernel takes 16 per block, above it 64
+    (the last case)."""
+    if case == "blocks_of_64":
+        sc = synth.config1(plane_dist="uniform", n=9000)
+    elif case == "tiny_h32":
         sc = synth.tiny_scene(8, n=300)
     elif case == "small_config":
         sc = synth.config1(plane_dist="uniform", n=2000)
