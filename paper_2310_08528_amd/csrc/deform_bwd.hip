@@ -1,6 +1,6 @@
 // Backward of the Gaussian deformation field on gfx950 (Sec. 4.2, Eq. 7-8).
 //
-// One 256-thread block per 64 Gaussians (16 up to 8192 Gaussians, so that
+// One 256-thread block per 64 Gaussians (16 up to 4096 Gaussians, so that
 // small sets still spread over the compute units), FP32 decoder.  The block first
 // recomputes the forward (encoder f_h, hidden h, head outputs) in LDS, then:
 //   Eq. 8 + activations   d(X + dX) -> dX and dX_canonical; d exp(log s + ds)
@@ -36,7 +36,7 @@ namespace {
 
 constexpr int kGB = 64;        // Gaussians per block
 constexpr int kGBSmall = 16;   // ... when 64 would leave most compute units idle
-constexpr int kSmallN = 8192;  // up to this many Gaussians (128 blocks of 64)
+constexpr int kSmallN = 4096;  // up to this many Gaussians (64 blocks of 64; measured crossover)
 constexpr int kThreads = 256;
 constexpr int kMaxScalesB = 3;
 

@@ -180,7 +180,7 @@ def _gpu_deform_backward(sc, t, gout):
 
 @pytest.mark.parametrize("case", ["tiny_h32", "small_config", "headline_shape", "heads_sh3", "blocks_of_64"])
 def test_deform_backward_matches_oracle(dev, case):
-    """Up to 8192 Gaussians the kernel takes 16 per block, above it 64
+    """Up to 4096 Gaussians the kernel takes 16 per block, above it 64
     (the last case)."""
     if case == "blocks_of_64":
         sc = synth.config1(plane_dist="uniform", n=9000)
