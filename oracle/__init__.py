@@ -54,6 +54,7 @@ def _load():
     lib.orc_deform.argtypes = [i32, P, P, P, P, i32, i32, P, P, P, P, i32, i32,
                                P, P, P, P, P, P, P, P, f64, i32, P, P, P, P, P, P,
                                i32, P, P, P, P, P, P]
+    lib.orc_to_bf16.argtypes = [i64, P, P]
     lib.orc_sh_basis.argtypes = [i32, i32, f64, f64, f64]
     lib.orc_sh_basis.restype = f64
     lib.orc_project.argtypes = [i32, i32, P, P, P, P, P, P, P, i32, i32, P, P, P, P, P]
@@ -62,7 +63,7 @@ def _load():
     lib.orc_emit_instances.argtypes = [i32, P, P, i32, P, P]
     lib.orc_sort_instances.argtypes = [i64, P, P]
     lib.orc_tile_ranges.argtypes = [i64, P, i32, P]
-    lib.orc_blend.argtypes = [i32, i32, P, P, P, P, P, P, f64, P, P, P, P, P]
+    lib.orc_blend.argtypes = [i32, i32, P, P, P, P, P, P, f64, P, P, P, P, P, P]
     _lib = lib
     return lib
 
@@ -93,6 +94,15 @@ def bilinear(plane: np.ndarray, ua: float, ub: float) -> np.ndarray:
     nb, na, F = plane.shape
     out = np.zeros(F, dtype=np.float64)
     _load().orc_bilinear(_p(plane), na, nb, F, float(ua), float(ub), _p(out))
+    return out
+
+
+def to_bf16(x) -> np.ndarray:
+    """The BF16-emulation mode's rounding: x rounded to binary32, then to
+    bfloat16 (nearest, ties to even), returned as float64."""
+    x = _c(x, np.float64)
+    out = np.zeros_like(x)
+    _load().orc_to_bf16(int(x.size), _p(x), _p(out))
     return out
 
 
@@ -266,6 +276,7 @@ def blend(cam, ranges, vals, opacity, proj, margin: float = 1e-5):
     img = np.zeros((3, H, W)); T = np.zeros((H, W))
     nc = np.zeros((H, W), dtype=np.int32); fl = np.zeros((H, W), dtype=np.int32)
     ev = np.zeros((H, W), dtype=np.int32)
+    used = np.zeros((H, W, 2), dtype=np.int64)
     ranges = _c(ranges, np.int64)
     vals = _c(vals, np.uint32)
     if vals.size == 0:
@@ -273,8 +284,8 @@ def blend(cam, ranges, vals, opacity, proj, margin: float = 1e-5):
     opacity = _c(opacity, np.float32)
     bg = _c(cam.bg, np.float32)
     lib.orc_blend(W, H, _p(ranges), _p(vals), _p(opacity), _p(_c(proj.f32, np.float32)),
-                  _p(_c(proj.f64, np.float64)), _p(bg), float(margin), _p(img), _p(T), _p(nc), _p(fl), _p(ev))
-    return img, T, nc, fl, ev
+                  _p(_c(proj.f64, np.float64)), _p(bg), float(margin), _p(img), _p(T), _p(nc), _p(fl), _p(ev), _p(used))
+    return img, T, nc, fl, ev, used
 
 
 def render(s, cam, margin: float = 1e-5):
@@ -284,8 +295,8 @@ def render(s, cam, margin: float = 1e-5):
     tx, ty = tiles_xy(cam.width, cam.height)
     inst = instances(proj.rect, proj.depth_bits, tx)
     rng = tile_ranges(inst.keys, tx * ty)
-    img, T, nc, fl, ev = blend(cam, rng, inst.vals, s.opacity, proj, margin)
-    return types.SimpleNamespace(image=img, final_T=T, n_contrib=nc, flag=fl, evals=ev, proj=proj,
+    img, T, nc, fl, ev, used = blend(cam, rng, inst.vals, s.opacity, proj, margin)
+    return types.SimpleNamespace(image=img, final_T=T, n_contrib=nc, flag=fl, evals=ev, used=used, proj=proj,
                                  K=inst.K, keys=inst.keys, vals=inst.vals, ranges=rng,
                                  tiles_x=tx, tiles_y=ty)
 

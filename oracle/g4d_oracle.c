@@ -79,8 +79,11 @@ void orc_bilinear(const float *plane, int na, int nb, int F, double ua, double u
     bilinear(plane, na, nb, F, ua, ub, out);
 }
 
-/* Round a binary32 value to bfloat16 (round to nearest, ties to even),
- * returned as a double.  Used only by the BF16-emulation mode. */
+/* Round to bfloat16 (round to nearest, ties to even), returned as a
+ * double.  The argument is first rounded to binary32: the emulation models
+ * a decoder that holds f_h and h as binary32 values (its own FP32
+ * arithmetic) and rounds those to bfloat16 for the matrix products.
+ * Infinities and NaN pass through.  Used only by the BF16-emulation mode. */
 static double to_bf16(double x)
 {
     float f = (float)x;
@@ -91,6 +94,12 @@ static double to_bf16(double x)
     u = (u + 0x7fffu + lsb) & 0xffff0000u;
     memcpy(&f, &u, 4);
     return (double)f;
+}
+
+/* Exported for tests: to_bf16 over an array. */
+void orc_to_bf16(int64_t n, const double *x, double *out)
+{
+    for (int64_t i = 0; i < n; ++i) out[i] = to_bf16(x[i]);
 }
 
 /* ------------------------------------------------------------------ */
@@ -544,7 +553,12 @@ void orc_tile_ranges(int64_t k, const uint64_t *keys, int n_tiles, int64_t *rang
 /* Output colour + T * bg, the final T, the number of list entries      */
 /* visited up to the last contributor, and (if evals is not null) the   */
 /* number of list entries the pixel evaluates: up to and including the  */
-/* entry that stops it, else the whole list.                             */
+/* entry that stops it, else the whole list.  If used is not null, the  */
+/* pixel's decision signature is written there: used[2p] = number of     */
+/* Gaussians composited, used[2p+1] = a polynomial hash of their indices */
+/* in compositing order; two renders whose signatures agree composited  */
+/* the same Gaussians in the same order at that pixel (a test aid: the  */
+/* hash takes no part in the image).                                    */
 /* Decisions are taken in binary32 (values f32 from orc_project); the   */
 /* colour and T are accumulated in FP64 from the FP64 values.  flag[p]  */
 /* counts binary32 decisions within `margin` (relative) of their        */
@@ -555,7 +569,8 @@ void orc_blend(int width, int height, const int64_t *ranges, const uint32_t *val
                const float *opacity, const float *f32v /* [n][8] */, const double *f64v /* [n][8] */,
                const float *bg, double margin,
                double *image /* [3][H][W] */, double *final_T /* [H][W] */,
-               int32_t *n_contrib /* [H][W] */, int32_t *flag /* [H][W] */, int32_t *evals /* [H][W] or NULL */)
+               int32_t *n_contrib /* [H][W] */, int32_t *flag /* [H][W] */, int32_t *evals /* [H][W] or NULL */,
+               int64_t *used /* [H][W][2] or NULL */)
 {
     const int tiles_x = (width + ORC_TILE - 1) / ORC_TILE;
     const float a_min = 1.0f / 255.0f;
@@ -569,6 +584,8 @@ void orc_blend(int width, int height, const int64_t *ranges, const uint32_t *val
             double T = 1.0, C[3] = {0.0, 0.0, 0.0};
             float T32 = 1.0f;
             int last = 0, fl = 0;
+            int64_t n_used = 0;
+            uint64_t seq_hash = 0;
             int ev = (int)(e - b);
             const float fpx = (float)px, fpy = (float)py;
             for (int64_t i = b; i < e; ++i) {
@@ -603,6 +620,8 @@ void orc_blend(int width, int height, const int64_t *ranges, const uint32_t *val
                 T *= (1.0 - alpha);
                 T32 = test32;
                 last = (int)(i - b) + 1;
+                ++n_used;
+                seq_hash = seq_hash * 1000003u + (uint64_t)g + 1u;
             }
             size_t pix = (size_t)py * width + px;
             for (int ch = 0; ch < 3; ++ch)
@@ -611,6 +630,10 @@ void orc_blend(int width, int height, const int64_t *ranges, const uint32_t *val
             n_contrib[pix] = last;
             flag[pix] = fl;
             if (evals) evals[pix] = ev;
+            if (used) {
+                used[2 * pix] = n_used;
+                used[2 * pix + 1] = (int64_t)seq_hash;
+            }
         }
     }
 }

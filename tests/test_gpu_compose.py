@@ -7,8 +7,9 @@ import pytest
 
 import oracle
 from paper_2310_08528_amd import g4d, synth
-from tests.gpu_util import log
-from tests.test_gpu_parity import _check_render, def_tol
+from tests.gpu_util import gpu_render, log
+from tests.parity_util import e2e_compare
+from tests.test_gpu_parity import IMG_TOL, _check_render, def_tol
 
 pytestmark = pytest.mark.gpu
 
@@ -43,6 +44,20 @@ def _max_errors(host, ref):
         got = np.asarray(getattr(host, k), dtype=np.float64).reshape(r.shape)
         errs[k] = float((np.abs(got - r) / (1.0 + np.abs(r))).max())
     return errs
+
+
+def _composed_frame(items, host, cam, name, capacity, ref=None):
+    """The oracle's composed set under the render bars (keys bit-exact,
+    image within 1e-4), then the GPU's compose + render against the
+    oracle's compose + render on every pixel whose decisions agree."""
+    ref = ref if ref is not None else oracle.compose(items, 3)
+    own_s = oracle.to_splats32(ref, ref.sh, 3)
+    _, own = _check_render(own_s, cam, name, capacity=capacity)
+    gpu = gpu_render(host, cam, capacity=capacity, want_intermediates=False)
+    on_gpu = oracle.render(oracle.to_splats32(host, host.sh, 3), cam)
+    c = e2e_compare(gpu.image, own, on_gpu)
+    log(f"   e2e: max|dimg| {c.max_img:.3g} on unflagged pixels, flagged {c.flagged}/{c.pixels}")
+    assert c.flagged <= 0.02 * c.pixels and c.max_img <= IMG_TOL
 
 
 def _mixed_items():
@@ -106,8 +121,7 @@ def test_composed_frame_meets_the_render_bars(dev):
     items, cams, ts = synth.composition(n_each=20_000, width=400, height=400)
     items = [(g, pl, m, float(ts[5]), place) for g, pl, m, place in items]
     host, _, _ = _compose(items, 3)
-    s = oracle.to_splats32(host, host.sh, 3)
-    _check_render(s, cams[2], "composed frame 2 x 20k", capacity=4 << 20)
+    _composed_frame(items, host, cams[2], "composed frame 2 x 20k", 4 << 20)
 
 
 def test_compose_rejects_bad_arguments(dev):
@@ -146,5 +160,4 @@ def test_composition_workload_full_size(dev):
     errs = _max_errors(host, ref)
     log("[compose full size] " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
     assert max(errs.values()) <= max(def_tol(it[1]) for it in items), errs
-    s = oracle.to_splats32(host, host.sh, 3)
-    _check_render(s, cams[3], "composition 2 x 50k 800x800", capacity=16 << 20)
+    _composed_frame(items, host, cams[3], "composition 2 x 50k 800x800", 16 << 20, ref)

@@ -6,6 +6,7 @@ import pytest
 
 import oracle
 from paper_2310_08528_amd import g4d, synth
+from tests.parity_util import e2e_compare
 from tests.gpu_util import compare_images, log
 
 pytestmark = pytest.mark.gpu
@@ -104,17 +105,18 @@ def test_served_image_matches_oracle(dev):
     srv.close()
     for (s, c, t), img in zip(reqs, imgs):
         g, pl, mlp, _ = scenes[s]
-        # oracle render of the GPU-deformed set (the deformation is checked elsewhere)
+        # the oracle's deform + render; pixels whose discrete decisions differ
+        # between the oracle's and the GPU's deformed set are excluded
         import torch
         G, P, M = dev_objs[s]
         S = g4d.DeviceSplats(G.n, G.sh_degree, G.sh, DEV)
         g4d.deform(G, P, M, t, S)
         torch.cuda.synchronize()
         host = type("D", (), {k: getattr(S, k).cpu().numpy() for k in ("means", "scales", "quats", "opacity")})
-        orc = oracle.render(oracle.to_splats32(host, g.sh, g.sh_degree), c)
-        gpu = type("R", (), {"image": img, "final_T": orc.final_T, "n_contrib": orc.n_contrib})
-        cmp = compare_images(gpu, orc)
-        assert cmp.max_img <= 1e-4, cmp.max_img
+        _, own = oracle.deform_render(g, pl, mlp, t, c)
+        on_gpu = oracle.render(oracle.to_splats32(host, g.sh, g.sh_degree), c)
+        cmp = e2e_compare(img, own, on_gpu)
+        assert cmp.flagged <= 0.02 * cmp.pixels and cmp.max_img <= 1e-4, (cmp.max_img, cmp.flagged)
 
 
 def test_capacity_overflow_is_retried(dev):

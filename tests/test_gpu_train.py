@@ -10,6 +10,7 @@ from oracle import grad as og
 from paper_2310_08528_amd import autograd as ga
 from paper_2310_08528_amd import g4d, synth
 from tests.gpu_util import gpu_deform, log
+from tests.parity_util import chain_reference
 
 pytestmark = pytest.mark.gpu
 
@@ -40,11 +41,10 @@ def test_autograd_gradients_match_oracle(dev):
     scene = ga.Scene4D(sc.gaussians, sc.planes, sc.mlp, DEV)
     ws = g4d.RenderWorkspace(scene.n, 64, 64, 64 * scene.n + 4096, DEV)
     img = ga.render_image(scene, cam, t, ws)
-    # the oracle's structure and flags on the GPU's deformed set (same inputs)
+    # the oracle's own structure; pixels whose decisions differ on the GPU's deformed set carry no loss
     host, _ = gpu_deform(sc, t)
-    s32 = oracle.to_splats32(host, sc.gaussians.sh, 0)
-    r = oracle.render(s32, cam)
-    w = np.random.default_rng(7).choice([-1.0, 1.0], size=r.image.shape) * (r.flag == 0)[None]
+    d = oracle.deform(sc.gaussians, sc.planes, sc.mlp, t)
+    r, w, _ = chain_reference(d, sc.gaussians.sh, 0, host, cam, 7)
     loss = (img * torch.as_tensor(w, dtype=torch.float32).to(DEV)).sum()
     loss.backward()
     torch.cuda.synchronize()
@@ -202,9 +202,8 @@ def test_autograd_with_colour_and_opacity_heads(dev):
     ws = g4d.RenderWorkspace(scene.n, 64, 64, 64 * scene.n + 4096, DEV)
     img = ga.render_image(scene, cam, t, ws)
     host, _ = gpu_deform(sc, t)
-    s32 = oracle.to_splats32(host, host.sh, 1)
-    r = oracle.render(s32, cam)
-    w = np.random.default_rng(8).choice([-1.0, 1.0], size=r.image.shape) * (r.flag == 0)[None]
+    d = oracle.deform(sc.gaussians, sc.planes, sc.mlp, t)
+    r, w, _ = chain_reference(d, d.sh, 1, host, cam, 8)
     (img * torch.as_tensor(w, dtype=torch.float32).to(DEV)).sum().backward()
     torch.cuda.synchronize()
     _, ref = og.deform_render_grads(sc.gaussians, sc.planes, sc.mlp, t, cam, r.ranges, r.vals, w)

@@ -110,6 +110,75 @@ def test_decoder_matches_numpy_matmul():
     np.testing.assert_allclose(d.delta, np.concatenate([dx, dr, ds], 1), rtol=1e-12, atol=1e-13)
 
 
+def _torch_bf16(x):
+    """Library rounding: float32 -> torch.bfloat16 (round to nearest, ties to
+    even) -> float64."""
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+
+
+def test_bf16_rounding_matches_torch_bit_for_bit():
+    """The BF16-emulation rounding against torch's float32 -> bfloat16
+    conversion, bit for bit: random values over many binades, exact ties
+    (low half-word 0x8000) with both parities of the kept last bit, values
+    one unit either side of a tie, signed zeros, subnormals, infinities and
+    NaN."""
+    rng = np.random.default_rng(17)
+    r = (rng.standard_normal(20000) * np.exp(rng.uniform(-40, 40, 20000))).astype(np.float32)
+    hi = rng.integers(0, 1 << 16, 4000, dtype=np.uint32) << np.uint32(16)
+    ties = (hi | np.uint32(0x8000)).view(np.float32)                  # both parities of bit 16
+    near = np.concatenate([(hi | np.uint32(0x7fff)).view(np.float32), (hi | np.uint32(0x8001)).view(np.float32)])
+    sub = (rng.integers(1, 1 << 23, 2000, dtype=np.uint32)).view(np.float32)    # subnormals, both signs below
+    special = np.array([0.0, -0.0, np.inf, -np.inf, np.float32(3.4e38), np.float32(-1.17549435e-38)],
+                       dtype=np.float32)
+    x = np.concatenate([r, ties, near, sub, -sub, special]).astype(np.float32)
+    x = x[np.isfinite(x) | np.isinf(x)]
+    got = oracle.to_bf16(x.astype(np.float64)).astype(np.float32)
+    ref = _torch_bf16(x).astype(np.float32)
+    np.testing.assert_array_equal(got.view(np.uint32), ref.view(np.uint32))
+    # ties go to the even neighbour: 1 + 2^-8 (a tie) -> 1, 1 + 3 * 2^-8 -> 1 + 2^-6
+    assert oracle.to_bf16([1.0 + 2.0 ** -8])[0] == 1.0
+    assert oracle.to_bf16([1.0 + 3 * 2.0 ** -8])[0] == 1.0 + 2.0 ** -6
+    assert np.isnan(oracle.to_bf16([np.nan])[0])
+    # a float64 argument is first rounded to binary32 (the emulated decoder
+    # holds f_h and h as binary32 values), then to bfloat16
+    y = rng.standard_normal(5000) * 3.0
+    np.testing.assert_array_equal(oracle.to_bf16(y), _torch_bf16(y.astype(np.float32)))
+
+
+def test_bf16_emulation_matches_numpy_decoder_on_rounded_operands():
+    """The BF16-emulation mode of the decoder equals float64 numpy products of
+    operands rounded by torch: f_h (binary32, then bfloat16), W1, h (binary32,
+    then bfloat16) and the head weights; biases stay binary32.  A decoder
+    that rounded a bias, skipped the rounding of h, or rounded f_h directly
+    from float64 without its binary32 value would fail."""
+    sc = synth.tiny_scene(3, n=256, plane_dist="uniform", sh_degree=0)
+    g, planes, mlp = sc.gaussians, sc.planes, sc.mlp
+    rng = np.random.default_rng(21)
+    rows, hid = synth.sh_rows(0), mlp.hidden
+    m = _with_heads(mlp, rng.uniform(-0.3, 0.3, (rows, hid)), rng.uniform(-0.2, 0.2, rows),
+                    rng.uniform(-0.3, 0.3, (1, hid)), rng.uniform(-0.2, 0.2, 1))
+    t = 0.55
+    emu = oracle.deform(g, planes, m, t, bf16_emulate=True, want_features=True)
+    f = emu.features                                   # float64 f_h (unrounded)
+    fb = _torch_bf16(f.astype(np.float32))
+    h = np.maximum(fb @ _torch_bf16(m.w1).T + m.b1.astype(np.float64), 0.0)
+    hb = _torch_bf16(h.astype(np.float32))
+    heads = np.concatenate([m.wx, m.wr, m.ws], 0)
+    bias = np.concatenate([m.bx, m.br, m.bs], 0).astype(np.float64)
+    delta = hb @ _torch_bf16(heads).T + bias
+    np.testing.assert_allclose(emu.delta, delta, rtol=1e-12, atol=1e-13)
+    dC = hb @ _torch_bf16(m.wc).T + m.bc.astype(np.float64)
+    np.testing.assert_allclose((emu.sh - g.sh.astype(np.float64)).reshape(rows, g.n), dC.T, rtol=1e-12, atol=1e-13)
+    da = hb @ _torch_bf16(m.wa)[0] + float(m.ba[0])
+    np.testing.assert_allclose(emu.opacity, 1 / (1 + np.exp(-(g.opacity_logits.astype(np.float64) + da))),
+                               rtol=1e-12)
+    # the FP64 mode differs from the emulation by the bfloat16 rounding only
+    d64 = oracle.deform(g, planes, m, t, want_features=True)
+    np.testing.assert_array_equal(d64.features, f)
+    rel = np.abs(d64.delta - emu.delta) / (1 + np.abs(d64.delta))
+    assert 1e-5 < rel.max() < 0.1
+
+
 def test_zero_field_zero_bias_is_static_activation():
     """Zero planes and zero biases give zero deformation: the deformed set is
     the canonical set after activation (the static warm-up render, Sec. 4.3)."""
@@ -537,6 +606,7 @@ def test_alpha_clamp_skip_and_early_stop_rules():
     r = oracle.render(splats([[0, 0, 4.0]], [[0.1] * 3], [[1, 0, 0, 0]], [0.003], colours=[[1, 1, 1]]), cam)
     assert r.image[0, 64, 64] == 0.0 and r.final_T[64, 64] == 1.0
     assert r.evals[64, 64] == 1                         # no stop: the whole (one-entry) list
+    assert tuple(r.used[64, 64]) == (0, 0)              # nothing composited
     # five stacked Gaussians with alpha 0.95: T = 0.05, 0.0025, 1.25e-4, and the
     # fourth would take T below 1e-4, so compositing stops after three
     s = splats([[0, 0, 2.0 + i] for i in range(5)], [[0.1] * 3] * 5, [[1, 0, 0, 0]] * 5, [0.95] * 5,
@@ -548,6 +618,11 @@ def test_alpha_clamp_skip_and_early_stop_rules():
     assert abs(r.final_T[64, 64] - (1 - a) ** 3) < 1e-12
     assert r.n_contrib[64, 64] == 3
     assert r.evals[64, 64] == 4                         # the fourth entry is evaluated and stops it
+    # decision signature: three Gaussians composited, indices 0, 1, 2 in that order
+    h = 0
+    for gid in range(3):
+        h = (h * 1000003 + gid + 1) % (1 << 64)
+    assert r.used[64, 64, 0] == 3 and int(np.uint64(r.used[64, 64, 1].astype(np.int64).view(np.uint64))) == h
 
 
 def _brute_force(s, cam, proj, use_rect=True):
