@@ -44,7 +44,7 @@ typedef enum {
     G4D_ECAPACITY = -3,     /* tile instances exceeded the workspace capacity */
     G4D_EHIP = -4,          /* a HIP runtime call failed; see g4d_last_hip_error */
     G4D_EBUSY = -5,         /* serving: no slot or memory free right now */
-    G4D_ENOMEM = -6,        /* serving: request larger than the memory budget */
+    G4D_ENOMEM = -6,        /* request larger than the memory budget (serving) or the fixed array (g4d_render_noalloc) */
     G4D_ENOTFOUND = -7,     /* serving: unknown scene or ticket */
     G4D_EDEVICE = -8        /* a device-side consistency check failed */
 } g4d_status;
@@ -279,6 +279,34 @@ size_t g4d_render_workspace_bytes(int32_t n, int32_t width, int32_t height,
  * allocation, fixed launch shapes for fixed arguments). */
 g4d_status g4d_render(const g4d_splats *G, const g4d_camera *C, const g4d_workspace *ws,
                       float *image, float *final_T, int32_t *n_contrib, void *stream);
+
+/* Bytes of the library's own device array that g4d_render_noalloc uses as
+ * its workspace (128 MiB; one copy per GPU, held until the process ends). */
+#define G4D_NOALLOC_SCRATCH_BYTES (128u << 20)
+
+/* g4d_render without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops and harnesses
+ * that forbid hipMalloc).  The workspace is a fixed device array of the
+ * library, G4D_NOALLOC_SCRATCH_BYTES per GPU; the instance capacity of a call
+ * is the largest cap with g4d_render_workspace_bytes(max(n, 1), width, height,
+ * cap) <= G4D_NOALLOC_SCRATCH_BYTES (about 7.2 million instances for 100k
+ * Gaussians at 800x800).  Same kernels, arguments and outputs as g4d_render.
+ * The call allocates nothing (no hipMalloc, hipFree or allocating library
+ * call); the first call on a device looks up that device's copy of the
+ * array.  Every call on one GPU shares that GPU's array: calls that overlap on
+ * one device (other streams or threads) race and must be serialised by the
+ * caller.  Nothing carries over between calls (the render clears what it
+ * needs at zero).
+ *   status  NULL: asynchronous, as g4d_render (an overflowed frame is then
+ *           not reported).  Non-NULL: the call waits for `stream` and fills
+ *           it (blend_evals is -1, not counted here); returns G4D_ECAPACITY
+ *           if the frame needed more instances than the array holds
+ *           (status->instances gives the count; the image is incomplete) and
+ *           G4D_EDEVICE if a bounded wait in the sort gave up.
+ * G4D_ENOMEM, before any device work, if (n, width, height) leaves no room
+ * in the array for even one instance; G4D_EINVAL as g4d_render. */
+g4d_status g4d_render_noalloc(const g4d_splats *G, const g4d_camera *C, float *image, float *final_T,
+                              int32_t *n_contrib, g4d_device_status *status, void *stream);
 
 /* Copies the device status of the last render on `ws` to the host.  Waits
  * for `stream` to finish. */

@@ -46,7 +46,7 @@ extern "C" const char *g4d_status_string(int32_t status) {
         case G4D_ECAPACITY: return "instance capacity exceeded";
         case G4D_EHIP: return "HIP runtime error";
         case G4D_EBUSY: return "busy";
-        case G4D_ENOMEM: return "request exceeds memory budget";
+        case G4D_ENOMEM: return "request exceeds the memory budget or the fixed scratch array";
         case G4D_ENOTFOUND: return "not found";
         case G4D_EDEVICE: return "device-side check failed";
         default: return "unknown status";

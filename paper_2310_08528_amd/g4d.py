@@ -141,6 +141,8 @@ SIGNATURES = {
     "g4d_l1_loss": (c_i32, [c_p, c_p, c_i64, c_p, c_p, c_p]),
     "g4d_tv_loss": (c_i32, [ctypes.POINTER(Planes), c_f32, c_p, ctypes.POINTER(DeformGrad), c_p]),
     "g4d_adam_step": (c_i32, [ctypes.POINTER(AdamTensor), c_i32, c_f32, c_f32, c_f32, c_i32, c_p]),
+    "g4d_render_noalloc": (c_i32, [ctypes.POINTER(Splats), ctypes.POINTER(Camera), c_p, c_p, c_p,
+                                   ctypes.POINTER(DeviceStatus), c_p]),
     "g4d_read_status": (c_i32, [ctypes.POINTER(Workspace), ctypes.POINTER(DeviceStatus), c_p]),
     "g4d_render_export": (c_i32, [ctypes.POINTER(Workspace), c_i32, c_i32, c_i64, c_p, c_sz, c_p]),
     "g4d_set_stage_events": (c_i32, [ctypes.POINTER(c_p), c_i32]),
@@ -396,6 +398,19 @@ def render(S: DeviceSplats, cam, ws: RenderWorkspace, image, final_T=None, n_con
     cs = cam if isinstance(cam, Camera) else camera_struct(cam)
     check(load().g4d_render(ctypes.byref(ss), ctypes.byref(cs), ctypes.byref(ws.ws), _ptr(image), _ptr(final_T),
                             _ptr(n_contrib), _stream(stream)), "g4d_render")
+
+
+def render_noalloc(S: DeviceSplats, cam, image, final_T=None, n_contrib=None, status=True, stream=None):
+    """g4d_render with the library's fixed device array as its workspace (no
+    allocation).  status=True waits for the stream and returns the frame's
+    DeviceStatus (raising on an overflow); status=False only enqueues."""
+    ss = S.struct()
+    cs = cam if isinstance(cam, Camera) else camera_struct(cam)
+    st = DeviceStatus() if status else None
+    check(load().g4d_render_noalloc(ctypes.byref(ss), ctypes.byref(cs), _ptr(image), _ptr(final_T),
+                                    _ptr(n_contrib), ctypes.byref(st) if st is not None else None,
+                                    _stream(stream)), "g4d_render_noalloc")
+    return st
 
 
 class DeviceSplatsGrad:

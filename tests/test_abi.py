@@ -51,6 +51,13 @@ def test_host_validation_rejects_null_arguments_without_touching_the_device():
     ws = g4d.Workspace(None, 0, 10, 16, 16, 100)
     st = g4d.DeviceStatus()
     assert lib.g4d_read_status(ctypes.byref(ws), ctypes.byref(st), None) == g4d.EINVAL
+    # the allocation-free render refuses sizes beyond its fixed array before any HIP call
+    cam = g4d.Camera()
+    cam.width, cam.height = 4096, 4096
+    big = g4d.Splats(3_000_000, 0, None, None, None, None, None)
+    dummy = ctypes.c_void_p(256)
+    assert lib.g4d_render_noalloc(ctypes.byref(big), ctypes.byref(cam), dummy, None, None, None, None) == g4d.ENOMEM
+    assert lib.g4d_render_noalloc(None, ctypes.byref(cam), dummy, None, None, None, None) == g4d.EINVAL
     # a time outside [0, 1] is rejected before any launch
     G = g4d.Gaussians(0, 0, None, None, None, None, None)
     P = g4d.Planes()
