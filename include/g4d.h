@@ -172,7 +172,10 @@ typedef struct {
     int32_t sort_error;         /* nonzero if a bounded wait in the sort gave up */
     int32_t visible;            /* Gaussians that touched at least one tile */
     int32_t tiles;              /* tiles_x * tiles_y of the frame */
-    int64_t blend_evals;        /* (pixel, Gaussian) pairs the compositing loop evaluated */
+    int64_t blend_evals;        /* list entries the pixels visited up to their stop (-1: not counted) */
+    int64_t blend_composited;   /* of those, the ones the blend composited after its per-quadrant
+                                   cull (-1: not counted); both are counted by a render that writes
+                                   n_contrib or final_T */
 } g4d_device_status;
 
 /* ---------------------------------------------------------------- deform */
@@ -299,7 +302,8 @@ g4d_status g4d_render(const g4d_splats *G, const g4d_camera *C, const g4d_worksp
  * needs at zero).
  *   status  NULL: asynchronous, as g4d_render (an overflowed frame is then
  *           not reported).  Non-NULL: the call waits for `stream` and fills
- *           it (blend_evals is -1, not counted here); returns G4D_ECAPACITY
+ *           it (blend_evals and blend_composited are -1, not counted here);
+ *           returns G4D_ECAPACITY
  *           if the frame needed more instances than the array holds
  *           (status->instances gives the count; the image is incomplete) and
  *           G4D_EDEVICE if a bounded wait in the sort gave up.

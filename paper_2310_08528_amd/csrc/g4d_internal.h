@@ -42,7 +42,7 @@ struct DevStatus {
     uint32_t passes;
     uint32_t tile_counter[16];       // onesweep tile tickets, one per sort pass / scan
     uint32_t pack_bits;              // instances packed as (tile << pack_bits) | index; 0: two arrays
-    uint32_t reserved;
+    uint32_t tracked;                // the last blend counted its work (n_contrib / final_T requested)
 };
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -69,6 +69,7 @@ struct WsLayout {
     size_t tcnt, tdtot;  // instance sort: per-pass digit counts [256][nblk_k] and digit totals [256]
     size_t order;        // blend order of the tiles (longest list first): (tile, start, end, 0)
     size_t evals;        // per tile: (pixel, Gaussian) pairs the blend evaluated (u64)
+    size_t comp;         // per tile: kept (pixel, Gaussian) pairs the blend composited (u64)
     size_t grad2d;       // render backward: per Gaussian dL/d(u, v, conic A B C, colour r g b, opacity), [9][n]
     size_t total;
 };
@@ -95,7 +96,7 @@ inline bool make_layout(int32_t n, int32_t w, int32_t h, int64_t cap, WsLayout *
     L->cam = take(256);
     L->recA = take((size_t)nn * 16);
     L->recB = take((size_t)nn * 16);
-    L->recC = take((size_t)nn * 4);
+    L->recC = take((size_t)nn * 16);
     L->rect = take((size_t)nn * 8);
     L->touched = take((size_t)nn * 4);
     L->dgid = take((size_t)nn * 4);
@@ -112,6 +113,7 @@ inline bool make_layout(int32_t n, int32_t w, int32_t h, int64_t cap, WsLayout *
     L->tdtot = take((size_t)2 * 256 * 4);
     L->order = take((size_t)L->tiles_max * 16);
     L->evals = take((size_t)L->tiles_max * 8);
+    L->comp = take((size_t)L->tiles_max * 8);
     L->grad2d = take((size_t)nn * 9 * 4);
     L->total = o;
     return true;

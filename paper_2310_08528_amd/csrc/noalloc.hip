@@ -96,6 +96,7 @@ extern "C" g4d_status g4d_render_noalloc(const g4d_splats *G, const g4d_camera *
     status->visible = (int32_t)h.visible;
     status->tiles = (int32_t)h.tiles;
     status->blend_evals = -1;
+    status->blend_composited = -1;
     if (h.overflow) return G4D_ECAPACITY;
     if (h.sort_error) return G4D_EDEVICE;
     return G4D_OK;

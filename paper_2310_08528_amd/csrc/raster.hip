@@ -125,6 +125,43 @@ __device__ __forceinline__ float3 sh_colour(int deg, const float (&c)[16][3], fl
     return out;
 }
 
+// Blend cull bounds of a Gaussian (stored with its record): every pixel
+// offset d = (u - px, v - py) at which the blend can composite it (alpha >=
+// 1/255 and power <= 0, as the blend evaluates them in binary32) lies in the
+// ellipse q(d) = d^T K d <= thr_c, K the binary32 conic (A, B, C) and
+// thr_c = 2 ln(255 o) widened by a margin: 1e-3 (1 + |thr|) for the
+// exponential and logarithm roundings, and the factor (1 + 2 e) for the
+// binary32 evaluation of q (about nine roundings, each relative to
+// A dx^2 + 2|B dx dy| + C dy^2 <= q (1 + rho) / (1 - rho)), whose error is at
+// most e q(d) with e = 16 u (1 + rho) / (1 - rho), rho = |B| / sqrt(AC), u = 2^-24.  From that
+// ellipse: its half-extents hx = sqrt(thr_c (K^-1)_xx), hy = sqrt(thr_c
+// (K^-1)_yy), and the reach of a pixel square of half-side 3.5 (a blend
+// quadrant, inside a disc of radius r_b = 3.5 sqrt 2 about its centre c):
+// if some pixel of the square can be composited then, K-norms being norms,
+// sqrt(q(c)) <= sqrt(thr_c) + r_b sqrt(lambda_max(K)), so q(c) evaluated in
+// binary32 is at most reach = (sqrt(thr_c) + r_b sqrt(lambda_max))^2 (1 + 2 e).
+// Computed in double and rounded up.  A Gaussian that can never be
+// composited (thr_c < 0) gets reach -1; one whose conic is too elongated for
+// the bound (rho >= 0.999) is never culled (infinite bounds).
+__device__ __forceinline__ float4 cull_bounds(float b, float A, float B, float C, float o) {
+    const double thr = 2.0 * log(255.0 * (double)o);
+    const double thr_m = thr + 1e-3 * (1.0 + fabs(thr));
+    if (!(thr_m >= 0.0)) return make_float4(b, 0.0f, 0.0f, -1.0f);
+    const double a = A, bb = B, c = C;
+    const double rho = fabs(bb) / sqrt(a * c);
+    if (!(a > 0.0 && c > 0.0 && rho < 0.999)) return make_float4(b, INFINITY, INFINITY, INFINITY);
+    const double e = 16.0 * 0x1p-24 * (1.0 + rho) / (1.0 - rho);
+    const double thr_c = thr_m * (1.0 + 2.0 * e);
+    const double det = a * c - bb * bb;
+    const double hx = sqrt(thr_c * c / det), hy = sqrt(thr_c * a / det);
+    const double lmax = 0.5 * (a + c) + sqrt(0.25 * (a - c) * (a - c) + bb * bb);
+    const double rb = 4.949747468305833;   // 3.5 sqrt 2
+    const double r = sqrt(thr_c) + rb * sqrt(lmax);
+    const double reach = r * r * (1.0 + 2.0 * e);
+    return make_float4(b, (float)(hx * (1.0 + 1e-6) + 1e-3), (float)(hy * (1.0 + 1e-6) + 1e-3),
+                       (float)(reach * (1.0 + 1e-6) + 1e-6));
+}
+
 // 1024 threads per block: the per-block depth-digit histograms are folded
 // into the device-wide ones with device-scope atomics, whose count (and
 // contention on the few live top-digit bins) falls with the block count.
@@ -134,7 +171,7 @@ __global__ __launch_bounds__(1024) void k_preprocess(int n, int sh_degree, const
                                                     const float *__restrict__ opac, const float *__restrict__ sh,
                                                     const CamK *__restrict__ camd, float4 *__restrict__ recA,
                                                     float4 *__restrict__ recB,
-                                                    float *__restrict__ recC, uint2 *__restrict__ rect,
+                                                    float4 *__restrict__ recC, uint2 *__restrict__ rect,
                                                     uint32_t *__restrict__ touched, uint32_t *__restrict__ dkeys,
                                                     uint32_t *__restrict__ depth_hist, DevStatus *__restrict__ st) {
     __shared__ uint32_t h[4][256];
@@ -149,7 +186,7 @@ __global__ __launch_bounds__(1024) void k_preprocess(int n, int sh_degree, const
         uint32_t key = 0xffffffffu, cnt = 0;
         uint2 rc = make_uint2(0u, 0u);
         float4 A = make_float4(0.f, 0.f, 0.f, 0.f), B = A;
-        float Cb = 0.0f;
+        float4 Cb = make_float4(0.f, 0.f, 0.f, -1.0f);
         const float mx = means[g], my = means[(size_t)n + g], mz = means[2 * (size_t)n + g];
         const float sx = scales[g], sy = scales[(size_t)n + g], sz = scales[2 * (size_t)n + g];
         const float qw = quats[g], qx = quats[(size_t)n + g], qy = quats[2 * (size_t)n + g],
@@ -236,9 +273,10 @@ __global__ __launch_bounds__(1024) void k_preprocess(int n, int sh_degree, const
                         const float il = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
                         dx *= il; dy *= il; dz *= il;
                         const float3 col = sh_colour(sh_degree, coef, dx, dy, dz);
+                        const float o = opac[g];
                         A = make_float4(u, v, -0.5f * cA, -0.5f * cC);
-                        B = make_float4(-cB, opac[g], col.x, col.y);
-                        Cb = col.z;
+                        B = make_float4(-cB, o, col.x, col.y);
+                        Cb = cull_bounds(col.z, cA, cB, cC, o);
                     }
                 }
             }
@@ -272,51 +310,69 @@ __global__ __launch_bounds__(1024) void k_preprocess(int n, int sh_degree, const
 // counts through a decoupled look-back).  Each wave ranks a contiguous 1024-
 // key sub-tile: wave-wide digit matching with ballots, running per-wave digit
 // counters in LDS.  Waits are bounded; a wait that gives up sets sort_error.
+//
+// Depth sort routing: pass p of the four 8-bit passes over the per-Gaussian
+// depth keys.  A pass whose digit is the same for every key (its histogram
+// has one bin holding all n keys) is the identity permutation and is skipped
+// outright; the m passes that remain alternate between the two ping-pong
+// buffers so that the last one writes buffer 0 (the depth order), the first
+// reading the depth keys with the identity as values.  Every block derives
+// the same routing from the four histograms, which the preprocess completed.
+// With m = 0 (all keys equal) pass 3 writes the identity order itself.
 
 template <int ITEMS>
 __global__ __launch_bounds__(kSortThreads) void k_sort_pass(
-    const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
-    uint32_t *__restrict__ vout, const uint32_t *__restrict__ d_count, uint32_t count_max, int shift, int bits,
-    const uint32_t *__restrict__ ghist, uint32_t *__restrict__ lookback, uint32_t *__restrict__ ticket,
-    uint32_t *__restrict__ err, const uint32_t *__restrict__ skip) {
-    // an overflowed frame is invalid: its instance sort is skipped (every
-    // later read stays in bounds)
-    if (skip && *skip) return;
+    int n, int p, const uint32_t *__restrict__ dgid, uint32_t *__restrict__ dk0, uint32_t *__restrict__ dk1,
+    uint32_t *__restrict__ dv0, uint32_t *__restrict__ dv1, const uint32_t *__restrict__ hist4,
+    uint32_t *__restrict__ lookback, uint32_t *__restrict__ ticket, uint32_t *__restrict__ err) {
     __shared__ uint32_t s_wcnt[4][256];
     __shared__ uint32_t s_base[256];
     __shared__ uint32_t s_g[256];
     __shared__ uint32_t s_tile;
-    __shared__ int s_trivial;
+    __shared__ int s_triv[4];
     constexpr uint32_t TILE = kSortThreads * ITEMS;
+    constexpr int bits = 8;
+    const int shift = 8 * p;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int NB = 1 << bits;
     const uint32_t mask = (uint32_t)NB - 1u;
-    uint32_t count = count_max;
-    if (d_count) count = min(*d_count, count_max);
-    // the digit histogram is read while the ticket is taken
-    const uint32_t gh = tid < NB ? ghist[tid] : 0u;
-    if (tid == 0) {
-        s_tile = atomicAdd(ticket, 1u);
-        s_trivial = 0;
-    }
+    const uint32_t count = (uint32_t)n;
+    if (tid < 4) s_triv[tid] = 0;
     for (int i = tid; i < 4 * 256; i += kSortThreads) (&s_wcnt[0][0])[i] = 0;
     __syncthreads();
-    if (tid < NB) {
-        s_g[tid] = gh;
-        if (gh == count) s_trivial = 1;   // every key has this digit
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const uint32_t h = hist4[q * 256 + tid];
+        if (q == p) s_g[tid] = h;
+        if (h == count) s_triv[q] = 1;   // every key has this digit
     }
+    __syncthreads();
+    int m = 0, pidx = 0;   // non-trivial passes, and those before this one
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        m += !s_triv[q];
+        pidx += q < p && !s_triv[q];
+    }
+    uint32_t *bk[2] = {dk0, dk1};
+    uint32_t *bv[2] = {dv0, dv1};
+    if (s_triv[p]) {
+        if (m == 0 && p == 3) {
+            for (uint32_t i = blockIdx.x * kSortThreads + tid; i < count; i += gridDim.x * kSortThreads) {
+                dk0[i] = dgid[i];
+                dv0[i] = i;
+            }
+        }
+        return;
+    }
+    const uint32_t *kin = pidx == 0 ? dgid : bk[(m - pidx) & 1];
+    const uint32_t *vin = pidx == 0 ? nullptr : bv[(m - pidx) & 1];
+    uint32_t *kout = bk[(m - 1 - pidx) & 1];
+    uint32_t *vout = bv[(m - 1 - pidx) & 1];
+    if (tid == 0) s_tile = atomicAdd(ticket, 1u);
     __syncthreads();
     const uint32_t tile = s_tile;
     const uint32_t ntiles = (count + TILE - 1) / TILE;
     if (tile >= ntiles) return;
-    if (s_trivial) {
-        // the pass is the identity permutation: stream the tile through
-        for (uint32_t idx = tile * TILE + tid; idx < min(count, (tile + 1) * TILE); idx += kSortThreads) {
-            kout[idx] = kin[idx];
-            vout[idx] = vin ? vin[idx] : idx;
-        }
-        return;
-    }
 
     uint32_t keys[ITEMS], vals[ITEMS], rank[ITEMS];
     const uint32_t base_idx = tile * TILE + wave * (ITEMS * 64);
@@ -989,52 +1045,35 @@ __global__ __launch_bounds__(1024) void k_tile_order(const uint2 *__restrict__ r
 // One 256-thread block per 16x16 tile; wave w owns the 8x8 quadrant
 // (w & 1, w >> 1), lane l the pixel (l & 7, l >> 3) inside it.  The four
 // waves run independently (no block barrier until the end).  Per step a wave
-// takes the next 64 list entries, one per lane, and decides whether each can
-// reach alpha >= 1/255 at any pixel of its quadrant: the quadratic form
-// d^T Sigma'^-1 d is convex, so its minimum over the rectangle of pixel
-// centres is 0 if the centre lies inside, else the least of the four clamped
-// edge minima.  An entry that cannot reach the threshold in the quadrant is
-// skipped by every pixel of it anyway, so leaving it out changes no result;
-// the cut keeps a margin covering the binary32 rounding of both the cut and
-// the per-pixel value.  The kept entries are packed in list order into the
-// wave's LDS slots (list positions stored) and composited with a branch-free
-// body; the wave leaves once all its pixels are done.
-
-__device__ __forceinline__ float quad_form(float A, float B, float C, float dx, float dy) {
-    return (A * dx) * dx + (2.0f * B * dx) * dy + (C * dy) * dy;
-}
-
-// Can a Gaussian (centre u, v; conic A, B, C with reciprocals iA ~ 1/A,
-// iC ~ 1/C; cut threshold thr on the quadratic form) reach the threshold
-// inside [x_lo, x_hi] x [y_lo, y_hi]?  The edge minimisers are located with
-// hardware reciprocals: a misplaced minimiser only raises the edge value by
-// a second-order amount (C de^2 for an error de), far inside the margin.
-__device__ __forceinline__ bool rect_may_reach(float u, float v, float A, float B, float C, float iA, float iC,
-                                               float thr, float x_lo, float x_hi, float y_lo, float y_hi) {
-    if (x_hi < x_lo || y_hi < y_lo) return false;   // quadrant outside the image
-    const float dxl = u - x_hi, dxh = u - x_lo;
-    const float dyl = v - y_hi, dyh = v - y_lo;
-    if (dxl <= 0.0f && dxh >= 0.0f && dyl <= 0.0f && dyh >= 0.0f) return true;
-    const float ea = fminf(fmaxf(-(B * dxl) * iC, dyl), dyh);
-    const float eb = fminf(fmaxf(-(B * dxh) * iC, dyl), dyh);
-    const float ec = fminf(fmaxf(-(B * dyl) * iA, dxl), dxh);
-    const float ed = fminf(fmaxf(-(B * dyh) * iA, dxl), dxh);
-    const float qmin = fminf(fminf(quad_form(A, B, C, dxl, ea), quad_form(A, B, C, dxh, eb)),
-                             fminf(quad_form(A, B, C, ec, dyl), quad_form(A, B, C, ed, dyh)));
-    const float d2 = fmaxf(dxl * dxl, dxh * dxh) + fmaxf(dyl * dyl, dyh * dyh);
-    return !(qmin > thr + 1e-3f * (1.0f + fabsf(thr)) + 2e-6f * (A + C) * d2);
-}
+// takes the next 64 list entries, one per lane, and keeps those that can be
+// composited at some pixel of its quadrant, by two conservative tests on the
+// bounds the preprocess stored with each record (see cull_bounds): the
+// axis-aligned extent of the entry's alpha >= 1/255 ellipse must meet the
+// quadrant, and the binary32 quadratic form at the quadrant centre must not
+// exceed the entry's reach.  An entry that fails either is skipped by every
+// pixel of the quadrant anyway (alpha 0: no colour, no change of T, no stop),
+// so leaving it out changes no output bit.  The kept entries are packed in
+// list order into the wave's LDS slots (list positions stored) and
+// composited with a branch-free body; the wave leaves once all its pixels are
+// done.
+//
+// TRACK: also write n_contrib / final_T and count, per tile, the list
+// entries the pixels visit up to their stop (the evaluation count of the
+// method) and the kept entries they composite; without it the loop carries
+// none of that bookkeeping.
 
 constexpr int kBlendUnroll = 8;   // entries composited per step of the loop (power of two, <= 64)
 
+template <bool TRACK>
 __global__ __launch_bounds__(kTilePixels) void k_blend(const uint4 *__restrict__ order,
                                                        const uint32_t *__restrict__ gids, uint32_t gmask,
                                                        const float4 *__restrict__ recA,
                                                        const float4 *__restrict__ recB,
-                                                       const float *__restrict__ recC, int width, int height,
+                                                       const float4 *__restrict__ recC, int width, int height,
                                                        int tiles_x, int n_tiles, const CamK *__restrict__ camd,
                                                        DevStatus *__restrict__ st,
-                                                       unsigned long long *__restrict__ tile_evals, int passes,
+                                                       unsigned long long *__restrict__ tile_evals,
+                                                       unsigned long long *__restrict__ tile_comp, int passes,
                                                        int n) {
     constexpr int NW = kTilePixels / 64;   // waves = quadrants
     // per wave: a queue of packed records.  Each step appends its kept
@@ -1055,6 +1094,7 @@ __global__ __launch_bounds__(kTilePixels) void k_blend(const uint4 *__restrict__
         st->tiles = (uint32_t)n_tiles;
         st->passes = (uint32_t)passes;
         st->pack_bits = gmask == 0xffffffffu ? 0u : (uint32_t)__popc(gmask);
+        st->tracked = TRACK ? 1u : 0u;
     }
     const int qx0 = tx * kTile + (wave & 1) * 8, qy0 = ty * kTile + (wave >> 1) * 8;
     const int px = qx0 + (lane & 7), py = qy0 + (lane >> 3);
@@ -1062,14 +1102,17 @@ __global__ __launch_bounds__(kTilePixels) void k_blend(const uint4 *__restrict__
     const size_t pix = inside ? (size_t)py * width + px : 0;
     const int start = (int)ord.y, end = (int)ord.z;
     const float fpx = (float)px, fpy = (float)py;
-    // this quadrant's rectangle of pixel centres, clipped to the image
+    // this quadrant's rectangle of pixel centres, clipped to the image (empty
+    // if the quadrant lies outside), and the centre of the full quadrant
     const float x_lo = (float)qx0, y_lo = (float)qy0;
     const float x_hi = fminf(x_lo + 7.0f, (float)(width - 1));
     const float y_hi = fminf(y_lo + 7.0f, (float)(height - 1));
+    const bool quad_live = x_hi >= x_lo && y_hi >= y_lo;
+    const float qcx = x_lo + 3.5f, qcy = y_lo + 3.5f;
     float T = 1.0f, cr = 0.0f, cg = 0.0f, cbl = 0.0f;
-    float live = inside ? 1.0f : 0.0f;   // 0 once the pixel stopped (or outside)
-    int last = 0;
-    int evals = inside ? end - start : 0;   // list entries this pixel evaluates
+    bool live = inside;   // false once the pixel stopped (or outside)
+    int last = 0, evals = inside ? end - start : 0;   // TRACK only
+    unsigned comp = 0;                                // TRACK only
     const float a_min = 1.0f / 255.0f;
     const uint64_t lt = lanemask_lt64();
     float4 *__restrict__ R = sR[wave];
@@ -1084,8 +1127,7 @@ __global__ __launch_bounds__(kTilePixels) void k_blend(const uint4 *__restrict__
         const uint32_t g = w & gmask;
         return g < (uint32_t)n ? g : 0u;
     };
-    float4 nA = zero4, nB = zero4;
-    float nC = 0.0f;
+    float4 nA = zero4, nB = zero4, nC = zero4;
     if (start + lane < end) {
         const uint32_t g = safe(load_gid(start + lane));
         nA = recA[g];
@@ -1095,10 +1137,9 @@ __global__ __launch_bounds__(kTilePixels) void k_blend(const uint4 *__restrict__
     uint32_t g_next = load_gid(start + 64 + lane);
     int queued = 0;   // records carried over from the previous step (< kBlendUnroll)
     for (int b0 = start; b0 < end; b0 += 64) {
-        if (__builtin_amdgcn_ballot_w64(live > 0.0f) == 0) break;
+        if (__builtin_amdgcn_ballot_w64(live) == 0) break;
         const int i = b0 + lane;
-        const float4 A4 = nA, B4 = nB;
-        const float C1 = nC;
+        const float4 A4 = nA, B4 = nB, C4 = nC;
         if (i + 64 < end) {
             const uint32_t g = safe(g_next);
             nA = recA[g];
@@ -1107,13 +1148,15 @@ __global__ __launch_bounds__(kTilePixels) void k_blend(const uint4 *__restrict__
         }
         g_next = load_gid(i + 128);
         bool keep = false;
-        if (i < end) {
-            // conic from the stored halves: A = -2 ha, C = -2 hc, B = -nb
-            const float A = -2.0f * A4.z, C = -2.0f * A4.w, Bc = -B4.x;
-            const float iA = __builtin_amdgcn_rcpf(A), iC = __builtin_amdgcn_rcpf(C);
-            // alpha >= 1/255 needs q <= 2 ln(255 o)
-            const float thr = 2.0f * (__logf(B4.y) + 5.541263545158426f);
-            keep = rect_may_reach(A4.x, A4.y, A, Bc, C, iA, iC, thr, x_lo, x_hi, y_lo, y_hi);
+        if (i < end && quad_live) {
+            // extent of the alpha >= 1/255 ellipse against the quadrant (0.01
+            // pixel covers the rounding of u +- hx), then the reach test on
+            // the quadratic form at the quadrant centre
+            const bool box = A4.x + C4.y >= x_lo - 0.01f && A4.x - C4.y <= x_hi + 0.01f &&
+                             A4.y + C4.z >= y_lo - 0.01f && A4.y - C4.z <= y_hi + 0.01f;
+            const float cx = A4.x - qcx, cy = A4.y - qcy;
+            const float pc = __builtin_fmaf(cx, __builtin_fmaf(A4.z, cx, B4.x * cy), (A4.w * cy) * cy);
+            keep = box && -2.0f * pc <= C4.w;
         }
         const uint64_t km = __builtin_amdgcn_ballot_w64(keep);
         const int total = queued + (int)__popcll(km);
@@ -1126,7 +1169,7 @@ __global__ __launch_bounds__(kTilePixels) void k_blend(const uint4 *__restrict__
             const int slot = queued + (int)__popcll(km & lt);
             R[3 * slot] = A4;
             R[3 * slot + 1] = make_float4(B4.x, __log2f(B4.y), B4.z, B4.w);
-            R[3 * slot + 2] = make_float4(C1, __int_as_float(i - start + 1), 0.0f, 0.0f);
+            R[3 * slot + 2] = make_float4(C4.x, __int_as_float(i - start + 1), 0.0f, 0.0f);
         }
         if (lane < kept4 - total) {
             R[3 * (total + lane)] = zero4;
@@ -1149,27 +1192,29 @@ __global__ __launch_bounds__(kTilePixels) void k_blend(const uint4 *__restrict__
                 // -(A dx^2 + C dy^2)/2 - B dx dy = dx (-A/2 dx - B dy) + (-C/2 dy) dy
                 const float power = __builtin_fmaf(dx, __builtin_fmaf(R0.z, dx, R1.x * dy), (R0.w * dy) * dy);
                 // skipped entries (power > 0, alpha < 1/255) get alpha 0, and so
-                // does every entry after the pixel stopped (live = 0): then
-                // T (1 - alpha) = T >= 1e-4, nothing stops, adds or moves
-                const float pw = power > 0.0f ? -INFINITY : power;
-                float alpha = fminf(0.99f, __builtin_amdgcn_exp2f(__builtin_fmaf(pw, 1.44269504f, R1.y)));
-                alpha = alpha < a_min ? 0.0f : alpha;
-                const float ae = alpha * live;
-                const float test = __builtin_fmaf(-ae, T, T);   // T (1 - alpha), one rounding
+                // does every entry after the pixel stopped: then T (1 - alpha)
+                // = T >= 1e-4, nothing stops, adds or moves
+                const float e = __builtin_amdgcn_exp2f(__builtin_fmaf(power, 1.44269504f, R1.y));
+                // min(0.99, e) as a median (e >= 0): one instruction
+                const float alpha = (power > 0.0f || e < a_min || !live) ? 0.0f : __builtin_amdgcn_fmed3f(e, 0.0f, 0.99f);
+                const float test = __builtin_fmaf(-alpha, T, T);   // T (1 - alpha), one rounding
                 const bool stop = test < 0.0001f;
-                const int pos1 = __float_as_int(R2.y);
-                evals = stop ? pos1 : evals;
-                live = stop ? 0.0f : live;
                 // the weight alpha T is the drop in transmittance
                 const float Tn = stop ? T : test;
                 const float w = T - Tn;
                 cr = __builtin_fmaf(R1.z, w, cr);
                 cg = __builtin_fmaf(R1.w, w, cg);
                 cbl = __builtin_fmaf(R2.x, w, cbl);
-                last = w > 0.0f ? pos1 : last;
+                if constexpr (TRACK) {
+                    const int pos1 = __float_as_int(R2.y);
+                    comp += (live && pos1 != 0) ? 1u : 0u;
+                    evals = (stop && live) ? pos1 : evals;
+                    last = w > 0.0f ? pos1 : last;
+                }
+                live = live && !stop;
                 T = Tn;
             }
-            if (__builtin_amdgcn_ballot_w64(live > 0.0f) == 0) break;
+            if (__builtin_amdgcn_ballot_w64(live) == 0) break;
         }
         // carry the remainder to the front (kept4 >= kBlendUnroll > queued, so
         // the source and destination slots never overlap)
@@ -1185,30 +1230,40 @@ __global__ __launch_bounds__(kTilePixels) void k_blend(const uint4 *__restrict__
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    {
-        __shared__ unsigned long long s_ev[NW];
-        unsigned long long e = (unsigned long long)evals;
+    if constexpr (TRACK) {
+        __shared__ unsigned long long s_ev[NW], s_cp[NW];
+        unsigned long long e = (unsigned long long)evals, c = comp;
 #pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) e += __shfl_xor(e, o, 64);
-        if (lane == 0) s_ev[wave] = e;
+        for (int o = 32; o >= 1; o >>= 1) {
+            e += __shfl_xor(e, o, 64);
+            c += __shfl_xor(c, o, 64);
+        }
+        if (lane == 0) {
+            s_ev[wave] = e;
+            s_cp[wave] = c;
+        }
         __syncthreads();
         if (tid == 0) {
-            unsigned long long sum = 0;
-            for (int w = 0; w < NW; ++w) sum += s_ev[w];
-            tile_evals[tile] = sum;   // summed on the host by read_status (no contended atomic)
+            unsigned long long se = 0, sc = 0;
+            for (int w = 0; w < NW; ++w) {
+                se += s_ev[w];
+                sc += s_cp[w];
+            }
+            tile_evals[tile] = se;   // summed on the host by read_status (no contended atomic)
+            tile_comp[tile] = sc;
         }
     }
     if (inside) {
         float *__restrict__ image = camd->image;
-        float *__restrict__ final_T = camd->final_T;
-        int32_t *__restrict__ n_contrib = camd->n_contrib;
         const float bg0 = camd->bg[0], bg1 = camd->bg[1], bg2 = camd->bg[2];
         const size_t plane = (size_t)width * height;
         image[pix] = cr + T * bg0;
         image[plane + pix] = cg + T * bg1;
         image[2 * plane + pix] = cbl + T * bg2;
-        if (final_T) final_T[pix] = T;
-        if (n_contrib) n_contrib[pix] = last;
+        if constexpr (TRACK) {
+            if (float *__restrict__ final_T = camd->final_T) final_T[pix] = T;
+            if (int32_t *__restrict__ n_contrib = camd->n_contrib) n_contrib[pix] = last;
+        }
     }
 }
 
@@ -1234,14 +1289,14 @@ __global__ void k_export_gids(const DevStatus *__restrict__ st, const uint32_t *
 }
 
 __global__ void k_export_splat2d(int n, const float4 *__restrict__ recA, const float4 *__restrict__ recB,
-                                 const float *__restrict__ recC, float *__restrict__ out) {
+                                 const float4 *__restrict__ recC, float *__restrict__ out) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n) return;
     const float4 A = recA[g], B = recB[g];
     float *o = out + (size_t)g * 12;
     o[0] = A.x; o[1] = A.y; o[2] = A.z; o[3] = A.w;
     o[4] = B.x; o[5] = B.y; o[6] = B.z; o[7] = B.w;
-    o[8] = recC[g]; o[9] = 0.f; o[10] = 0.f; o[11] = 0.f;
+    o[8] = recC[g].x; o[9] = 0.f; o[10] = 0.f; o[11] = 0.f;
 }
 
 __global__ void k_export_rect(int n, const uint2 *__restrict__ rect, int32_t *__restrict__ out) {
@@ -1326,7 +1381,7 @@ g4d_status render(const g4d_splats *G, const g4d_camera *C, const g4d_workspace 
     uint2 *ranges = at<uint2>(ws, L.ranges);
     float4 *recA = at<float4>(ws, L.recA);
     float4 *recB = at<float4>(ws, L.recB);
-    float *recC = at<float>(ws, L.recC);
+    float4 *recC = at<float4>(ws, L.recC);
     uint2 *rect = at<uint2>(ws, L.rect);
     uint32_t *touched = at<uint32_t>(ws, L.touched);
     uint32_t *dgid = at<uint32_t>(ws, L.dgid);
@@ -1354,18 +1409,13 @@ g4d_status render(const g4d_splats *G, const g4d_camera *C, const g4d_workspace 
         hipLaunchKernelGGL(k_preprocess, dim3(nb_n), dim3(1024), 0, s, n, G->sh_degree, G->means, G->scales,
                            G->quats, G->opacity, G->sh, camd, recA, recB, recC, rect, touched, dgid, depth_hist, st);
         mark(2);
-        // 2. depth sort: four 8-bit passes over n keys; values start as the identity
+        // 2. depth sort: four 8-bit passes over n keys (constant-digit passes
+        //    skipped on the device); values start as the identity
         const int sblocks = (n + kSortTileN - 1) / kSortTileN;
-        const uint32_t *kin[4] = {dgid, dk[1], dk[0], dk[1]};
-        const uint32_t *vin[4] = {nullptr, dv[1], dv[0], dv[1]};
-        uint32_t *kout[4] = {dk[1], dk[0], dk[1], dk[0]};
-        uint32_t *vout[4] = {dv[1], dv[0], dv[1], dv[0]};
         for (int p = 0; p < 4; ++p) {
-            hipLaunchKernelGGL(k_sort_pass<kSortItemsN>, dim3(sblocks), dim3(kSortThreads), 0, s, kin[p], vin[p],
-                               kout[p], vout[p],
-                               nullptr, (uint32_t)n, 8 * p, 8, depth_hist + 256 * p,
-                               lb_depth + (size_t)p * L.nblk_n * 256, &st->tile_counter[p], &st->sort_error,
-                               nullptr);
+            hipLaunchKernelGGL(k_sort_pass<kSortItemsN>, dim3(sblocks), dim3(kSortThreads), 0, s, n, p, dgid, dk[0],
+                               dk[1], dv[0], dv[1], depth_hist, lb_depth + (size_t)p * L.nblk_n * 256,
+                               &st->tile_counter[p], &st->sort_error);
         }
         mark(3);
         const uint32_t *order = dv[0];
@@ -1415,10 +1465,12 @@ g4d_status render(const g4d_splats *G, const g4d_camera *C, const g4d_workspace 
     hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, s, ranges, tiles, order);
     mark(7);
     // 7. blend (with n == 0 every range is empty and the image is the background)
-    hipLaunchKernelGGL(k_blend, dim3(tiles), dim3(kTilePixels), 0, s, order, packed ? tk[0] : tv[0],
+    // the bookkeeping variant when the caller wants n_contrib or final_T
+    auto blend = (final_T || n_contrib) ? k_blend<true> : k_blend<false>;
+    hipLaunchKernelGGL(blend, dim3(tiles), dim3(kTilePixels), 0, s, order, packed ? tk[0] : tv[0],
                        packed ? (1u << gbits) - 1u : 0xffffffffu, recA, recB, recC, C->width,
                        C->height, cam.tiles_x, tiles, camd, st, at<unsigned long long>(ws, L.evals),
-                       plan.passes, std::max(n, 1));
+                       at<unsigned long long>(ws, L.comp), plan.passes, std::max(n, 1));
     mark(8);
     G4D_HIP_CHECK(hipGetLastError());
     return G4D_OK;
@@ -1435,16 +1487,25 @@ g4d_status read_status(const g4d_workspace *ws, g4d_device_status *out, hipStrea
     out->sort_error = (int32_t)h.sort_error;
     out->visible = (int32_t)h.visible;
     out->tiles = (int32_t)h.tiles;
-    // blend work: one count per tile of the last frame
-    int64_t evals = 0;
-    if (h.tiles > 0 && (int64_t)h.tiles <= (int64_t)L.tiles_max) {
-        std::vector<unsigned long long> te(h.tiles);
-        G4D_HIP_CHECK(hipMemcpyAsync(te.data(), at<unsigned long long>(ws, L.evals), te.size() * 8,
+    // blend work, one count per tile of the last frame (a render that wrote
+    // n_contrib or final_T counts it; -1 otherwise)
+    out->blend_evals = -1;
+    out->blend_composited = -1;
+    if (h.tracked && h.tiles > 0 && (int64_t)h.tiles <= (int64_t)L.tiles_max) {
+        std::vector<unsigned long long> te(2 * (size_t)h.tiles);
+        G4D_HIP_CHECK(hipMemcpyAsync(te.data(), at<unsigned long long>(ws, L.evals), (size_t)h.tiles * 8,
+                                     hipMemcpyDeviceToHost, s));
+        G4D_HIP_CHECK(hipMemcpyAsync(te.data() + h.tiles, at<unsigned long long>(ws, L.comp), (size_t)h.tiles * 8,
                                      hipMemcpyDeviceToHost, s));
         G4D_HIP_CHECK(hipStreamSynchronize(s));
-        for (unsigned long long v : te) evals += (int64_t)v;
+        int64_t evals = 0, comp = 0;
+        for (uint32_t t = 0; t < h.tiles; ++t) {
+            evals += (int64_t)te[t];
+            comp += (int64_t)te[h.tiles + t];
+        }
+        out->blend_evals = evals;
+        out->blend_composited = comp;
     }
-    out->blend_evals = evals;
     return G4D_OK;
 }
 
@@ -1498,7 +1559,7 @@ g4d_status render_export(const g4d_workspace *ws, int32_t kind, int32_t n, int64
             if (bytes < (size_t)n * 48) return G4D_EINVAL;
             if (n == 0) return G4D_OK;
             hipLaunchKernelGGL(k_export_splat2d, dim3(nb), dim3(256), 0, s, n, at<float4>(ws, L.recA),
-                               at<float4>(ws, L.recB), at<float>(ws, L.recC), static_cast<float *>(dst));
+                               at<float4>(ws, L.recB), at<float4>(ws, L.recC), static_cast<float *>(dst));
             break;
         }
         default:

@@ -98,7 +98,7 @@ __device__ __forceinline__ float row_sum(float v) {
 
 __global__ __launch_bounds__(256) void k_blend_bwd(const uint4 *__restrict__ order, const uint32_t *__restrict__ gids,
                                                    uint32_t gmask, const float4 *__restrict__ recA,
-                                                   const float4 *__restrict__ recB, const float *__restrict__ recC,
+                                                   const float4 *__restrict__ recB, const float4 *__restrict__ recC,
                                                    int width, int height, int tiles_x, int n_tiles, BwdCam cam,
                                                    const float *__restrict__ final_T,
                                                    const int32_t *__restrict__ n_contrib,
@@ -158,7 +158,7 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const uint4 *__restrict__ ord
             if (gid >= (uint32_t)n) gid = 0;
             A4 = recA[gid];
             B4 = recB[gid];
-            C1 = recC[gid];
+            C1 = recC[gid].x;
             const float A = -2.0f * A4.z, C = -2.0f * A4.w, Bc = -B4.x;
             const float iA = __builtin_amdgcn_rcpf(A), iC = __builtin_amdgcn_rcpf(C);
             const float thr = 2.0f * (__logf(B4.y) + 5.541263545158426f);
@@ -501,7 +501,7 @@ g4d_status render_backward(const g4d_splats *G, const g4d_camera *C, const g4d_w
     hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)std::min<size_t>(((size_t)kG2 * n + 255) / 256, 4096)), dim3(256),
                        0, s, g2d, (size_t)kG2 * n);
     hipLaunchKernelGGL(k_blend_bwd, dim3(tiles), dim3(256), 0, s, ws_at<uint4>(ws, L.order), gids, gmask,
-                       ws_at<float4>(ws, L.recA), ws_at<float4>(ws, L.recB), ws_at<float>(ws, L.recC), C->width,
+                       ws_at<float4>(ws, L.recA), ws_at<float4>(ws, L.recB), ws_at<float4>(ws, L.recC), C->width,
                        C->height, tiles_x, tiles, cam, final_T, n_contrib, grad_image, g2d, n);
     hipLaunchKernelGGL(k_preprocess_bwd, dim3((n + 255) / 256), dim3(256), 0, s, n, G->sh_degree, G->means,
                        G->scales, G->quats, G->sh, cam, g2d, out->means, out->scales, out->quats, out->opacity,

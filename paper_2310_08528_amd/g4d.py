@@ -79,7 +79,7 @@ class Workspace(ctypes.Structure):
 
 class DeviceStatus(ctypes.Structure):
     _fields_ = [("instances", c_i64), ("overflow", c_i32), ("sort_error", c_i32), ("visible", c_i32),
-                ("tiles", c_i32), ("blend_evals", c_i64)]
+                ("tiles", c_i32), ("blend_evals", c_i64), ("blend_composited", c_i64)]
 
 
 class DeformJob(ctypes.Structure):
