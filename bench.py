@@ -34,19 +34,23 @@ sys.path.insert(0, ROOT)
 
 METRIC = "deform+splat frames/s @800², 100k Gaussians; served p50/p99 ms vs plain"
 
-# MI355X peaks: published HBM and FP32 vector; the VALU issue peak for single
-# (non-packed, non-fused) binary32 operations derived from the unit counts:
-# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
+# MI355X peaks: published HBM and FP32 vector (157.3 TFLOP/s counts packed
+# fused multiply-adds); the VALU issue rate for wave64 instructions from the
+# unit counts: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD every 4
+# cycles at 2.4 GHz.
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
-PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+PEAK_WAVE_INSTR_PER_S = 256 * 4 * 2.4e9 / 4
 
-# Algorithmic work per unit: an evaluated (pixel, Gaussian) pair of the blend
-# costs 2 (offset) + 8 (quadratic form) + 2 (o exp) + 1 (min) + 2 (T (1 - alpha))
-# binary32 operations
-BLEND_FLOP_PER_EVAL = 15
-BWD_OPS_PER_EVAL = 55             # backward walk, per re-evaluated pair (an upper estimate of the work)
-STAGES = ["clear", "preprocess", "depth_sort", "offsets", "emit", "tile_sort", "ranges", "blend"]
+# Algorithmic work of the blend per evaluated (pixel, Gaussian) pair, as the
+# measurement contract counts it: about 24 binary32 operations (offset 2,
+# quadratic form 7, exponent scale and exp 3, clamp 1, the two skip tests 2,
+# T (1 - alpha) 2, stop test 1, weight 1, colour accumulation 6 - 1 for the
+# transmittance update folded into the weight).  An evaluated pair is every
+# list entry a pixel visits up to and including its stop (counted on the
+# device, equal to the oracle's count).
+BLEND_OPS_PER_EVAL = 24
+STAGES = ["clear", "preprocess", "depth_sort", "offsets", "emit", "tile_sort", "ranges_and_order", "blend"]
 
 
 def log(*a):
@@ -405,14 +409,10 @@ def time_training_step(steps, warmup):
             "steps": steps, "steps_per_s": round(steps / wall, 2), "ms_per_step": round(1e3 * wall / steps, 4),
             "stages_ms": {"forward": st(0), "loss": st(1), "render_backward": st(2), "deform_backward": st(3),
                           "tv_and_adam": st(4)},
-            # the backward walk re-evaluates the forward's (pixel, Gaussian) pairs; ~55 binary32
-            # ops per contributing pair (alpha as in the forward, T / (1 - alpha), the colour,
-            # opacity, position and conic terms); the stage also holds two small kernels
-            "render_backward_roofline": {"bound": "alu", "evaluated_pairs": evals, "ops_per_pair": BWD_OPS_PER_EVAL,
-                                         "achieved": round(evals * BWD_OPS_PER_EVAL / (rb_ms * 1e-3) / 1e12, 3),
-                                         "peak": round(PEAK_VALU_TOPS, 2), "unit": "T op/s",
-                                         "frac": round(evals * BWD_OPS_PER_EVAL / (rb_ms * 1e-3) / 1e12
-                                                       / PEAK_VALU_TOPS, 4)}}
+            # the backward walk re-evaluates the forward's (pixel, Gaussian) pairs; its
+            # VALU issue use is in the counter summary of the training iteration
+            "render_backward": {"evaluated_pairs": evals, "ms": round(rb_ms, 4),
+                                "ns_per_pair": round(rb_ms * 1e6 / max(evals, 1), 4)}}
 
 
 def extra_measurements(steps, warmup):
@@ -443,29 +443,36 @@ def extra_measurements(steps, warmup):
     return out
 
 
-def blend_traffic():
-    """HBM bytes per blend launch from the committed counter summary, or None
-    when the blend kernel's source has changed since the counters were taken."""
-    root = os.path.dirname(os.path.abspath(__file__))
+def _profile_json(name):
+    md = open(os.path.join(ROOT, "profiles", name)).read()
+    return json.loads(md.split("```json", 1)[1].split("```", 1)[0])
+
+
+def _blend_source_hash():
+    src = open(os.path.join(ROOT, "paper_2310_08528_amd", "csrc", "raster.hip")).read()
+    a = src.index("// ---------------------------------------------------------------- k_blend")
+    b = src.index("// ---------------------------------------------------------------- k_export")
+    return hashlib.sha256(src[a:b].encode()).hexdigest()
+
+
+def blend_counters():
+    """Counter figures of one blend launch (HBM bytes, VALU and transcendental
+    instructions, active cycles) from the committed counter summary, or None
+    when the blend kernel's source has changed since they were taken."""
     try:
-        md = open(os.path.join(root, "profiles", "k_blend_traffic_100k_800x800.md")).read()
-        data = json.loads(md.split("```json", 1)[1].split("```", 1)[0])
-        src = open(os.path.join(root, "paper_2310_08528_amd", "csrc", "raster.hip")).read()
-        a = src.index("// ---------------------------------------------------------------- k_blend")
-        b = src.index("// ---------------------------------------------------------------- k_export")
-    except (OSError, ValueError, IndexError):
+        data = _profile_json("k_blend_counters_100k_800x800.md")
+        if _blend_source_hash() != data.get("kernel_source_sha256"):
+            return None
+        return data
+    except (OSError, ValueError, IndexError, KeyError):
         return None
-    if hashlib.sha256(src[a:b].encode()).hexdigest() != data.get("kernel_source_sha256"):
-        return None
-    return int(data["traffic_bytes_per_launch"])
 
 
 def rasterizer_traffic():
     """HBM bytes of every rasterizer kernel of one frame, from the committed
     counter summary, or None when the rasterizer source has changed."""
     try:
-        md = open(os.path.join(ROOT, "profiles", "k_blend_traffic_100k_800x800.md")).read()
-        data = json.loads(md.split("```json", 1)[1].split("```", 1)[0])
+        data = _profile_json("k_blend_counters_100k_800x800.md")
         src = open(os.path.join(ROOT, "paper_2310_08528_amd", "csrc", "raster.hip")).read()
     except (OSError, ValueError, IndexError):
         return None
@@ -642,7 +649,6 @@ def main():
     n_prof = min(K, 100)
     stage_ev = [[ev.create() for _ in range(9)] for _ in range(n_prof)]
     dfm_ev = [(ev.create(), ev.create()) for _ in range(n_prof)]
-    evals_tot = 0
     for k in range(n_prof):
         ci, t = frames[(args.warmup + k) % len(frames)]
         ev.record(dfm_ev[k][0], sp)
@@ -651,23 +657,47 @@ def main():
         g4d.set_stage_events(stage_ev[k])
         g4d.render(S, cams[ci], ws, img)
         g4d.set_stage_events(None)
-        evals_tot += int(g4d.read_status(ws).blend_evals)
     torch.cuda.synchronize()
     stages = {"deform": float(np.mean([ev.elapsed(a, b) for a, b in dfm_ev]))}
     for i, name in enumerate(STAGES):
         stages[name] = float(np.mean([ev.elapsed(e[i], e[i + 1]) for e in stage_ev]))
-    evals_per_frame = evals_tot / n_prof
+    # ---- the blend's work over the timed frames: the same frames rendered
+    # again with n_contrib and final_T (the variant that counts), not timed
+    T_ = torch.empty((H, W), dtype=torch.float32, device=dev)
+    nc_ = torch.empty((H, W), dtype=torch.int32, device=dev)
+    evals_tot = comp_tot = 0
+    for k in range(K):
+        ci, t = frames[(args.warmup + k) % len(frames)]
+        g4d.deform(G, P, M, t, S)
+        g4d.render(S, cams[ci], ws, img, T_, nc_)
+        st = g4d.read_status(ws)
+        evals_tot += int(st.blend_evals)
+        comp_tot += int(st.blend_composited)
+    evals_per_frame = evals_tot / K
+    comp_per_frame = comp_tot / K
 
-    # ---- roofline of the dominant kernel (the blend: VALU-bound)
-    traffic = blend_traffic()
-    blend_flop = evals_per_frame * BLEND_FLOP_PER_EVAL
-    achieved = blend_flop / (blend_ms * 1e-3) / 1e12
-    roofline = {"bound": "alu", "kernel": "k_blend", "achieved": round(achieved, 3),
-                "peak": round(PEAK_VALU_TOPS, 2), "unit": "TFLOP/s", "frac": round(achieved / PEAK_VALU_TOPS, 4),
-                "traffic": traffic, "traffic_unit": "bytes/launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
-                "evals_per_frame": int(evals_per_frame),
-                "flop_per_eval": BLEND_FLOP_PER_EVAL, "avg_ms": round(blend_ms, 4),
-                "frac_of_published_fp32": round(achieved / PEAK_FP32_TFLOPS, 4)}
+    # ---- roofline of the dominant kernel (the blend: bound by VALU issue).
+    # achieved: the method's operations (24 per evaluated pair) per second of
+    # the blend's event-timed launch, against the published FP32 peak; the
+    # counted figures (VALU instructions per launch from the counter summary)
+    # give the issue utilisation beside it
+    cnt = blend_counters()
+    achieved = evals_per_frame * BLEND_OPS_PER_EVAL / (blend_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "kernel": "k_blend<false>", "achieved": round(achieved, 3),
+                "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                "traffic": int(cnt["traffic_bytes_per_launch"]) if cnt else None,
+                "traffic_unit": "bytes/launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+                "evaluated_pairs_per_frame": int(evals_per_frame),
+                "composited_pairs_per_frame": int(comp_per_frame),
+                "ops_per_evaluated_pair": BLEND_OPS_PER_EVAL, "avg_ms": round(blend_ms, 4)}
+    if cnt:
+        # wave64 VALU instructions of one launch (SQ_INSTS_VALU; a transcendental
+        # occupies its SIMD four issue slots) over the issue slots of the launch
+        slots = (cnt["valu_instructions_per_launch"] + 3 * cnt["trans_instructions_per_launch"])
+        roofline["valu_instructions_per_launch"] = cnt["valu_instructions_per_launch"]
+        roofline["valu_issue_utilization"] = round(slots / (PEAK_WAVE_INSTR_PER_S * blend_ms * 1e-3), 4)
+        roofline["valu_instructions_per_composited_pair"] = round(
+            cnt["valu_instructions_per_launch"] * 64 / max(comp_per_frame, 1), 2)
 
     # the rasterizer as a whole (counter bytes over its live time per frame)
     rbytes = rasterizer_traffic()

@@ -63,6 +63,7 @@ struct WsLayout {
     int32_t nblk_k;      // sort blocks over capacity
     int32_t nscan;       // scan blocks over n
     size_t status, depth_hist, lb_depth, lb_scan, ranges;
+    size_t tgrid;        // tile-count difference grid [tiles_y + 1][tiles_x + 1] (int32), cleared per render
     size_t zero_bytes;
     size_t cam;
     size_t recA, recB, recC, rect, touched, dgid, dk0, dk1, dv0, dv1, offsets, tk0, tk1, tv0, tv1;
@@ -92,6 +93,7 @@ inline bool make_layout(int32_t n, int32_t w, int32_t h, int64_t cap, WsLayout *
     L->lb_depth = take((size_t)4 * L->nblk_n * 256 * 4);
     L->lb_scan = take((size_t)L->nscan * 8);
     L->ranges = take((size_t)L->tiles_max * 8);
+    L->tgrid = take((size_t)(tx + 1) * (ty + 1) * 4);
     L->zero_bytes = o;
     L->cam = take(256);
     L->recA = take((size_t)nn * 16);

@@ -69,6 +69,12 @@ struct CamK {
     int32_t *n_contrib;
 };
 
+// Tile-count difference grids of up to kGridLdsCells cells ((tiles_x + 1) x
+// (tiles_y + 1), 64 KB) are accumulated in LDS per preprocess block.
+constexpr int kGridLdsCells = 16384;
+std::atomic<uint64_t> g_preprocess_lds{0};   // per device: the preprocess's dynamic-LDS limit raised
+std::atomic<uint64_t> g_order_lds{0};        // per device: k_tile_order's dynamic-LDS limit raised
+
 // ---------------------------------------------------------------- k_zero
 
 __global__ void k_zero(uint4 *__restrict__ p, size_t n16, CamK cam, CamK *__restrict__ camd) {
@@ -173,10 +179,13 @@ __global__ __launch_bounds__(1024) void k_preprocess(int n, int sh_degree, const
                                                     float4 *__restrict__ recB,
                                                     float4 *__restrict__ recC, uint2 *__restrict__ rect,
                                                     uint32_t *__restrict__ touched, uint32_t *__restrict__ dkeys,
-                                                    uint32_t *__restrict__ depth_hist, DevStatus *__restrict__ st) {
+                                                    uint32_t *__restrict__ depth_hist, DevStatus *__restrict__ st,
+                                                    int32_t *__restrict__ tgrid, int grid_lds) {
     __shared__ uint32_t h[4][256];
     __shared__ uint32_t s_vis;
+    extern __shared__ int32_t s_grid[];   // the block's difference grid, when it fits in LDS
     for (int i = threadIdx.x; i < 4 * 256; i += blockDim.x) (&h[0][0])[i] = 0;
+    for (int i = threadIdx.x; i < grid_lds; i += blockDim.x) s_grid[i] = 0;
     if (threadIdx.x == 0) s_vis = 0;
     __syncthreads();
     const CamK cam = *camd;
@@ -287,6 +296,17 @@ __global__ __launch_bounds__(1024) void k_preprocess(int n, int sh_degree, const
         rect[g] = rc;
         touched[g] = cnt;
         dkeys[g] = key;   // per-Gaussian depth key (kept for export and as the first sort input)
+        if (cnt) {
+            // the tile rectangle into the difference grid: its 2D prefix sum
+            // is the number of instances of each tile
+            const int x0 = rc.x & 0xffff, y0 = rc.x >> 16, x1 = rc.y & 0xffff, y1 = rc.y >> 16;
+            const int gw = cam.tiles_x + 1;
+            int32_t *gr = grid_lds ? s_grid : tgrid;
+            atomicAdd(&gr[y0 * gw + x0], 1);
+            atomicAdd(&gr[y0 * gw + x1], -1);
+            atomicAdd(&gr[y1 * gw + x0], -1);
+            atomicAdd(&gr[y1 * gw + x1], 1);
+        }
         atomicAdd(&h[0][key & 255u], 1u);
         atomicAdd(&h[1][(key >> 8) & 255u], 1u);
         atomicAdd(&h[2][(key >> 16) & 255u], 1u);
@@ -298,6 +318,10 @@ __global__ __launch_bounds__(1024) void k_preprocess(int n, int sh_degree, const
     for (int i = threadIdx.x; i < 4 * 256; i += blockDim.x) {
         const uint32_t c = (&h[0][0])[i];
         if (c) atomicAdd(&depth_hist[i], c);
+    }
+    for (int i = threadIdx.x; i < grid_lds; i += blockDim.x) {
+        const int32_t c = s_grid[i];
+        if (c) atomicAdd(&tgrid[i], c);
     }
     if (threadIdx.x == 0 && s_vis) atomicAdd(&st->visible, s_vis);
 }
@@ -977,53 +1001,108 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_down(
     }
 }
 
-// ---------------------------------------------------------------- k_ranges
-
-__global__ __launch_bounds__(256) void k_ranges(const DevStatus *__restrict__ st, const uint32_t *__restrict__ tkeys,
-                                                uint2 *__restrict__ ranges, uint32_t n_tiles, int kshift) {
-    const uint32_t K = st->k_used;
-    const uint32_t nq = (K + 3) / 4;
-    constexpr uint32_t kNone = 0xffffffffu;
-    for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += gridDim.x * blockDim.x) {
-        const uint32_t i0 = 4 * q;
-        uint32_t k[4];
-        if (i0 + 4 <= K) {
-            const uint4 v = *reinterpret_cast<const uint4 *>(tkeys + i0);
-            k[0] = v.x >> kshift; k[1] = v.y >> kshift; k[2] = v.z >> kshift; k[3] = v.w >> kshift;
-        } else {
-#pragma unroll
-            for (int j = 0; j < 4; ++j) k[j] = i0 + j < K ? tkeys[i0 + j] >> kshift : kNone;
-        }
-        const uint32_t prev = i0 > 0 ? tkeys[i0 - 1] >> kshift : kNone;
-        const uint32_t next = i0 + 4 < K ? tkeys[i0 + 4] >> kshift : kNone;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const uint32_t t = k[j];
-            if (i0 + j >= K || t >= n_tiles) continue;   // t >= n_tiles only if the sort failed (flagged there)
-            const uint32_t before = j > 0 ? k[j - 1] : prev;
-            const uint32_t after = j < 3 ? k[j + 1] : next;
-            if (before != t) ranges[t].x = i0 + j;
-            if (after != t) ranges[t].y = i0 + j + 1;
-        }
-    }
-}
-
 // ---------------------------------------------------------------- k_tile_order
 //
-// Blend order of the tiles: by list length, longest first, in power-of-two
-// classes (order inside a class is arbitrary; each tile's result does not
-// depend on it).  Blocks are dispatched in index order and spread round-robin
-// over the XCDs, so the longest tiles start first and land on different XCDs.
-
+// Tile ranges and blend order, one block.  The instances of a tile are the
+// Gaussians whose rectangle covers it, so its count is the 2D prefix sum of
+// the difference grid the preprocess filled (+1 / -1 at the rectangle's four
+// corners); the sorted list holds the tiles in id order, so a tile's range
+// starts at the exclusive scan of the counts in tile order.  An empty tile
+// gets [0, 0); an overflowed frame (its sort skipped) gets empty ranges
+// everywhere, and a count sum that differs from K is flagged.  The blend
+// order is by list length, longest first, in power-of-two classes (order
+// inside a class is arbitrary; each tile's result does not depend on it):
+// blocks are dispatched in index order and spread round-robin over the XCDs,
+// so the longest tiles start first and land on different XCDs.
 // order[k] = (tile, start, end, 0): the blend reads its tile's range with its id.
-__global__ __launch_bounds__(1024) void k_tile_order(const uint2 *__restrict__ ranges, int n_tiles,
-                                                     uint4 *__restrict__ order) {
+
+__global__ __launch_bounds__(1024) void k_tile_order(DevStatus *__restrict__ st, int32_t *__restrict__ tgrid,
+                                                     int tiles_x, int tiles_y, uint2 *__restrict__ ranges,
+                                                     uint4 *__restrict__ order, int grid_lds) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    constexpr int NW = 1024 / 64;
+    const int gw = tiles_x + 1;
+    const int n_tiles = tiles_x * tiles_y;
+    // the grid in LDS when it fits (else worked on in place in the workspace)
+    extern __shared__ int32_t s_g[];
+    int32_t *gr = tgrid;
+    if (grid_lds) {
+        for (int i = tid; i < grid_lds; i += 1024) s_g[i] = tgrid[i];
+        gr = s_g;
+    }
+    __syncthreads();
+    // inclusive prefix sums along the rows, then down the columns: one wave
+    // per row (column), 64 cells per step with a shuffle scan
+    for (int y = wave; y < tiles_y; y += NW) {
+        int32_t carry = 0;
+        for (int x0 = 0; x0 < tiles_x; x0 += 64) {
+            const int x = x0 + lane;
+            int32_t v = x < tiles_x ? gr[y * gw + x] : 0;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int32_t u = __shfl_up(v, o, 64);
+                if (lane >= o) v += u;
+            }
+            if (x < tiles_x) gr[y * gw + x] = carry + v;
+            carry += __shfl(v, 63, 64);
+        }
+    }
+    __syncthreads();
+    for (int x = wave; x < tiles_x; x += NW) {
+        int32_t carry = 0;
+        for (int y0 = 0; y0 < tiles_y; y0 += 64) {
+            const int y = y0 + lane;
+            int32_t v = y < tiles_y ? gr[y * gw + x] : 0;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int32_t u = __shfl_up(v, o, 64);
+                if (lane >= o) v += u;
+            }
+            if (y < tiles_y) gr[y * gw + x] = carry + v;
+            carry += __shfl(v, 63, 64);
+        }
+    }
+    __syncthreads();
+    // exclusive scan of the counts in tile order: a contiguous run of at most
+    // kOrderRun tiles per thread (kept in registers), then a block scan of the
+    // run sums
+    const bool ovf = st->overflow != 0;
+    const int q = (n_tiles + 1023) / 1024;
+    const int a0 = min(n_tiles, tid * q), a1 = min(n_tiles, a0 + q);
+    uint32_t part = 0;
+    {
+        int y = a0 / tiles_x, x = a0 - y * tiles_x;
+        for (int t = a0; t < a1; ++t) {
+            part += (uint32_t)gr[y * gw + x];
+            if (++x == tiles_x) { x = 0; ++y; }
+        }
+    }
+    uint32_t xs = part;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t u = __shfl_up(xs, o, 64);
+        if (lane >= o) xs += u;
+    }
+    __shared__ uint32_t s_w[NW];
     __shared__ uint32_t hist[33];
-    const int tid = threadIdx.x;
+    if (lane == 63) s_w[wave] = xs;
     if (tid < 33) hist[tid] = 0;
     __syncthreads();
-    auto cls = [](uint2 r) -> int { const uint32_t len = r.y > r.x ? r.y - r.x : 0u; return 32 - __clz(len); };
-    for (int t = tid; t < n_tiles; t += 1024) atomicAdd(&hist[cls(ranges[t])], 1u);
+    uint32_t base = xs - part;
+    for (int w = 0; w < wave; ++w) base += s_w[w];
+    auto cls = [](uint32_t len) -> int { return 32 - __clz(len); };
+    {
+        int y = a0 / tiles_x, x = a0 - y * tiles_x;
+        for (int t = a0; t < a1; ++t) {
+            const uint32_t c = (uint32_t)gr[y * gw + x];
+            const uint32_t len = ovf ? 0u : c;
+            ranges[t] = len ? make_uint2(base, base + c) : make_uint2(0u, 0u);
+            atomicAdd(&hist[cls(len)], 1u);
+            base += c;
+            if (++x == tiles_x) { x = 0; ++y; }
+        }
+    }
+    if (tid == 1023 && (unsigned long long)base != st->k_total) atomicOr(&st->sort_error, 16u);
     __syncthreads();
     if (tid == 0) {
         uint32_t pos = 0;
@@ -1034,9 +1113,18 @@ __global__ __launch_bounds__(1024) void k_tile_order(const uint2 *__restrict__ r
         }
     }
     __syncthreads();
-    for (int t = tid; t < n_tiles; t += 1024) {
-        const uint2 r = ranges[t];
-        order[atomicAdd(&hist[cls(r)], 1u)] = make_uint4((uint32_t)t, r.x, r.y, 0u);
+    {
+        base = xs - part;
+        for (int w = 0; w < wave; ++w) base += s_w[w];
+        int y = a0 / tiles_x, x = a0 - y * tiles_x;
+        for (int t = a0; t < a1; ++t) {
+            const uint32_t c = (uint32_t)gr[y * gw + x];
+            const uint32_t len = ovf ? 0u : c;
+            const uint2 r = len ? make_uint2(base, base + c) : make_uint2(0u, 0u);
+            order[atomicAdd(&hist[cls(len)], 1u)] = make_uint4((uint32_t)t, r.x, r.y, 0u);
+            base += c;
+            if (++x == tiles_x) { x = 0; ++y; }
+        }
     }
 }
 
@@ -1379,6 +1467,7 @@ g4d_status render(const g4d_splats *G, const g4d_camera *C, const g4d_workspace 
     uint32_t *lb_depth = at<uint32_t>(ws, L.lb_depth);
     unsigned long long *lb_scan = at<unsigned long long>(ws, L.lb_scan);
     uint2 *ranges = at<uint2>(ws, L.ranges);
+    int32_t *tgrid = at<int32_t>(ws, L.tgrid);
     float4 *recA = at<float4>(ws, L.recA);
     float4 *recB = at<float4>(ws, L.recB);
     float4 *recC = at<float4>(ws, L.recC);
@@ -1406,8 +1495,16 @@ g4d_status render(const g4d_splats *G, const g4d_camera *C, const g4d_workspace 
     if (n > 0) {
         const int nb_n = (n + 1023) / 1024;
         // 1. preprocess
-        hipLaunchKernelGGL(k_preprocess, dim3(nb_n), dim3(1024), 0, s, n, G->sh_degree, G->means, G->scales,
-                           G->quats, G->opacity, G->sh, camd, recA, recB, recC, rect, touched, dgid, depth_hist, st);
+        // the tile-count difference grid in LDS per block when it fits, else
+        // added straight into the workspace's grid
+        const int gcells = (cam.tiles_x + 1) * (cam.tiles_y + 1);
+        const int glds = gcells <= kGridLdsCells ? gcells : 0;
+        if (g4d_status e = ensure_max_lds(reinterpret_cast<const void *>(k_preprocess), g_preprocess_lds,
+                                          kGridLdsCells * 4))
+            return e;
+        hipLaunchKernelGGL(k_preprocess, dim3(nb_n), dim3(1024), glds * 4, s, n, G->sh_degree, G->means, G->scales,
+                           G->quats, G->opacity, G->sh, camd, recA, recB, recC, rect, touched, dgid, depth_hist, st,
+                           tgrid, glds);
         mark(2);
         // 2. depth sort: four 8-bit passes over n keys (constant-digit passes
         //    skipped on the device); values start as the identity
@@ -1454,15 +1551,19 @@ g4d_status render(const g4d_splats *G, const g4d_camera *C, const g4d_workspace 
             cur ^= 1;
         }
         mark(6);
-        // 6. ranges
-        {
-            const int rblocks = (int)std::min<int64_t>((L.cap + 255) / 256, 4096);
-            hipLaunchKernelGGL(k_ranges, dim3(rblocks), dim3(256), 0, s, st, tk[0], ranges, (uint32_t)tiles, kshift);
-        }
     } else {
         for (int i = 2; i <= 6; ++i) mark(i);
     }
-    hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, s, ranges, tiles, order);
+    // 6. ranges from the tile counts, and the blend order of the tiles
+    {
+        const int gcells = (cam.tiles_x + 1) * (cam.tiles_y + 1);
+        const int glds = gcells <= kGridLdsCells ? gcells : 0;
+        if (g4d_status e = ensure_max_lds(reinterpret_cast<const void *>(k_tile_order), g_order_lds,
+                                          kGridLdsCells * 4))
+            return e;
+        hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), glds * 4, s, st, tgrid, cam.tiles_x, cam.tiles_y,
+                           ranges, order, glds);
+    }
     mark(7);
     // 7. blend (with n == 0 every range is empty and the image is the background)
     // the bookkeeping variant when the caller wants n_contrib or final_T
