@@ -251,6 +251,21 @@ typedef struct {
 g4d_status g4d_deform_compose(const g4d_compose_item *items, int32_t n_items, g4d_splats *out,
                               void *stream);
 
+/* A spatial storage order for a Gaussian set: the Gaussians sorted by the
+ * 30-bit Morton code of their canonical means, quantised to 1024 cells per
+ * axis over the box [bmin, bmax] (means outside are clamped to it; the
+ * HexPlane's box is the natural choice), ties in index order.  A set stored
+ * in this order (every per-Gaussian array permuted once, e.g. when a scene is
+ * loaded) puts Gaussians that query neighbouring plane cells, and that
+ * project to neighbouring tiles, in the same deform blocks and near each
+ * other in memory.  The set is the same; only its numbering, and so the
+ * index tie-break of equal depths, changes.  Uses `ws` (a render workspace
+ * with n_max >= G->n) as scratch; writes order[n] (device): order[i] is the
+ * index of the i-th Gaussian of the new order.  Asynchronous.  G4D_EINVAL
+ * for a null argument, n outside the workspace or an empty box. */
+g4d_status g4d_spatial_order(const g4d_gaussians *G, const float bmin[3], const float bmax[3],
+                             const g4d_workspace *ws, uint32_t *order, void *stream);
+
 /* The encoder output f_h (Eq. 7) alone, [n][in_dim] float32: exposes the
  * intermediate of g4d_deform for verification.  Same kernel code path. */
 g4d_status g4d_deform_features(const g4d_gaussians *G, const g4d_planes *P, float t,

@@ -29,6 +29,11 @@ extern "C" g4d_status g4d_render(const g4d_splats *G, const g4d_camera *C, const
     return g4d::render(G, C, ws, image, final_T, n_contrib, reinterpret_cast<hipStream_t>(stream));
 }
 
+extern "C" g4d_status g4d_spatial_order(const g4d_gaussians *G, const float bmin[3], const float bmax[3],
+                                        const g4d_workspace *ws, uint32_t *order, void *stream) {
+    return g4d::spatial_order(G, bmin, bmax, ws, order, reinterpret_cast<hipStream_t>(stream));
+}
+
 extern "C" g4d_status g4d_read_status(const g4d_workspace *ws, g4d_device_status *out, void *stream) {
     return g4d::read_status(ws, out, reinterpret_cast<hipStream_t>(stream));
 }

@@ -149,6 +149,8 @@ void set_hip_error(hipError_t e);
 g4d_status render(const g4d_splats *G, const g4d_camera *C, const g4d_workspace *ws, float *image,
                   float *final_T, int32_t *n_contrib, hipStream_t s);
 g4d_status read_status(const g4d_workspace *ws, g4d_device_status *out, hipStream_t s);
+g4d_status spatial_order(const g4d_gaussians *G, const float bmin[3], const float bmax[3],
+                         const g4d_workspace *ws, uint32_t *order, hipStream_t s);
 g4d_status deform_batched(const g4d_deform_job *jobs, int n_jobs, hipStream_t s);
 g4d_status deform_backward(const g4d_gaussians *G, const g4d_planes *P, const g4d_mlp *M, float t,
                            const g4d_splats_grad *gout, const g4d_deform_grad *d, hipStream_t s);

@@ -568,6 +568,48 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_pass(
     }
 }
 
+// ---------------------------------------------------------------- k_morton
+//
+// Morton codes of the canonical means for a spatial processing order of the
+// deformation: 10 bits per axis over the box, interleaved (x highest), with
+// the four byte histograms of the codes for the radix passes.
+
+__device__ __forceinline__ uint32_t spread10(uint32_t v) {
+    v &= 0x3ffu;
+    v = (v | (v << 16)) & 0x030000ffu;
+    v = (v | (v << 8)) & 0x0300f00fu;
+    v = (v | (v << 4)) & 0x030c30c3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+__global__ __launch_bounds__(1024) void k_morton(int n, const float *__restrict__ means, float bx, float by,
+                                                 float bz, float sx, float sy, float sz,
+                                                 uint32_t *__restrict__ codes, uint32_t *__restrict__ hist4) {
+    __shared__ uint32_t h[4][256];
+    for (int i = threadIdx.x; i < 4 * 256; i += blockDim.x) (&h[0][0])[i] = 0;
+    __syncthreads();
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < n) {
+        auto cell = [](float x, float b, float sc) -> uint32_t {
+            return (uint32_t)fminf(fmaxf((x - b) * sc, 0.0f), 1023.0f);   // a NaN maps to 0
+        };
+        const uint32_t qx = cell(means[g], bx, sx), qy = cell(means[(size_t)n + g], by, sy);
+        const uint32_t qz = cell(means[2 * (size_t)n + g], bz, sz);
+        const uint32_t code = (spread10(qx) << 2) | (spread10(qy) << 1) | spread10(qz);
+        codes[g] = code;
+        atomicAdd(&h[0][code & 255u], 1u);
+        atomicAdd(&h[1][(code >> 8) & 255u], 1u);
+        atomicAdd(&h[2][(code >> 16) & 255u], 1u);
+        atomicAdd(&h[3][code >> 24], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 4 * 256; i += blockDim.x) {
+        const uint32_t c = (&h[0][0])[i];
+        if (c) atomicAdd(&hist4[i], c);
+    }
+}
+
 // ---------------------------------------------------------------- k_scan_offsets
 //
 // offsets[i] = sum_{j < i} touched[order[j]] (64-bit), single pass with a
@@ -1607,6 +1649,43 @@ g4d_status read_status(const g4d_workspace *ws, g4d_device_status *out, hipStrea
         out->blend_evals = evals;
         out->blend_composited = comp;
     }
+    return G4D_OK;
+}
+
+// Spatial processing order of a Gaussian set: Morton codes of the means, then
+// the four radix passes of the render's depth sort (stable, so ties keep
+// index order) in the workspace's buffers; the order lands in dv0.
+g4d_status spatial_order(const g4d_gaussians *G, const float bmin[3], const float bmax[3],
+                         const g4d_workspace *ws, uint32_t *order, hipStream_t s) {
+    WsLayout L;
+    if (!G || !bmin || !bmax || !order || !ws_layout(ws, &L)) return G4D_EINVAL;
+    const int n = G->n;
+    if (n < 0 || n > L.n_max || (n > 0 && !G->means)) return G4D_EINVAL;
+    for (int k = 0; k < 3; ++k)
+        if (!(bmax[k] > bmin[k])) return G4D_EINVAL;
+    if (n == 0) return G4D_OK;
+    DevStatus *st = at<DevStatus>(ws, L.status);
+    uint32_t *hist = at<uint32_t>(ws, L.depth_hist);
+    uint32_t *codes = at<uint32_t>(ws, L.dgid);
+    uint32_t *dk0 = at<uint32_t>(ws, L.dk0), *dk1 = at<uint32_t>(ws, L.dk1);
+    uint32_t *dv0 = at<uint32_t>(ws, L.dv0), *dv1 = at<uint32_t>(ws, L.dv1);
+    {
+        const size_t n16 = L.zero_bytes / 16;
+        const int blocks = (int)std::min<size_t>((n16 + 255) / 256, 2048);
+        hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, s, reinterpret_cast<uint4 *>(ws->ptr), n16, CamK{},
+                           at<CamK>(ws, L.cam));
+    }
+    float sc[3];
+    for (int k = 0; k < 3; ++k) sc[k] = (float)(1024.0 / ((double)bmax[k] - (double)bmin[k]));
+    hipLaunchKernelGGL(k_morton, dim3((n + 1023) / 1024), dim3(1024), 0, s, n, G->means, bmin[0], bmin[1], bmin[2],
+                       sc[0], sc[1], sc[2], codes, hist);
+    const int sblocks = (n + kSortTileN - 1) / kSortTileN;
+    uint32_t *lb = at<uint32_t>(ws, L.lb_depth);
+    for (int p = 0; p < 4; ++p)
+        hipLaunchKernelGGL(k_sort_pass<kSortItemsN>, dim3(sblocks), dim3(kSortThreads), 0, s, n, p, codes, dk0, dk1,
+                           dv0, dv1, hist, lb + (size_t)p * L.nblk_n * 256, &st->tile_counter[p], &st->sort_error);
+    hipLaunchKernelGGL(k_copy_u32, dim3((n + 255) / 256), dim3(256), 0, s, dv0, order, st, (uint32_t)n, 0);
+    G4D_HIP_CHECK(hipGetLastError());
     return G4D_OK;
 }
 

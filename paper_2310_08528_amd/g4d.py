@@ -131,6 +131,8 @@ SIGNATURES = {
     "g4d_deform_batched": (c_i32, [ctypes.POINTER(DeformJob), c_i32, c_p]),
     "g4d_deform_compose": (c_i32, [ctypes.POINTER(ComposeItem), c_i32, ctypes.POINTER(Splats), c_p]),
     "g4d_deform_features": (c_i32, [ctypes.POINTER(Gaussians), ctypes.POINTER(Planes), c_f32, c_p, c_p]),
+    "g4d_spatial_order": (c_i32, [ctypes.POINTER(Gaussians), ctypes.POINTER(c_f32), ctypes.POINTER(c_f32),
+                                  ctypes.POINTER(Workspace), c_p, c_p]),
     "g4d_render_workspace_bytes": (c_sz, [c_i32, c_i32, c_i32, c_i64]),
     "g4d_render": (c_i32, [ctypes.POINTER(Splats), ctypes.POINTER(Camera), ctypes.POINTER(Workspace), c_p, c_p,
                            c_p, c_p]),
@@ -385,6 +387,27 @@ def deform_compose(items, out: DeviceSplats, stream=None):
                              pl if pl is not None else placement())
     os_ = out.struct()
     check(load().g4d_deform_compose(arr, len(items), ctypes.byref(os_), _stream(stream)), "g4d_deform_compose")
+
+
+def spatial_order(G: DeviceGaussians, bmin, bmax, ws: "RenderWorkspace", stream=None):
+    """The Morton order of G's canonical means over the box [bmin, bmax] (an
+    int32 device tensor [n]: the index of the i-th Gaussian of the order)."""
+    import torch
+    order = torch.empty(max(G.n, 1), dtype=torch.int32, device=G.means.device)
+    gs = G.struct()
+    lo = (c_f32 * 3)(*[float(v) for v in bmin])
+    hi = (c_f32 * 3)(*[float(v) for v in bmax])
+    check(load().g4d_spatial_order(ctypes.byref(gs), lo, hi, ctypes.byref(ws.ws), _ptr(order), _stream(stream)),
+          "g4d_spatial_order")
+    return order[:G.n]
+
+
+def store_in_order(G: DeviceGaussians, order):
+    """Permute every per-Gaussian array of G in place into `order` (a
+    one-time data-layout step; the tensors keep their storage)."""
+    idx = order.long()
+    for t in (G.means, G.log_scales, G.quats, G.opacity_logits, G.sh):
+        t.copy_(t[..., idx])
 
 
 def deform_features(G: DeviceGaussians, P: DevicePlanes, t: float, features, stream=None):

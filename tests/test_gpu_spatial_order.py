@@ -1,0 +1,95 @@
+"""Spatial storage order of a Gaussian set (g4d_spatial_order): the order is
+the Morton order of the canonical means (checked against the codes computed
+here in binary32 and numpy's stable lexsort); a set stored in that order
+deforms to exactly the permutation of the original set's result (every
+Gaussian's result is computed by the same arithmetic whichever block row it
+lands in), and renders to the oracle's image of the permuted set."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2310_08528_amd import g4d, synth
+from tests.gpu_util import log
+from tests.test_gpu_parity import _check_render
+
+pytestmark = pytest.mark.gpu
+
+
+def _spread10(v):
+    v = v.astype(np.uint64) & 0x3FF
+    v = (v | (v << 16)) & 0x030000FF
+    v = (v | (v << 8)) & 0x0300F00F
+    v = (v | (v << 4)) & 0x030C30C3
+    v = (v | (v << 2)) & 0x09249249
+    return v
+
+
+def _morton_order(means, bmin, bmax):
+    q = []
+    for k in range(3):
+        sc = np.float32(1024.0 / (float(bmax[k]) - float(bmin[k])))
+        x = (means[k].astype(np.float32) - np.float32(bmin[k])) * sc
+        q.append(np.minimum(np.maximum(x, np.float32(0.0)), np.float32(1023.0)).astype(np.uint32))
+    code = (_spread10(q[0]) << 2) | (_spread10(q[1]) << 1) | _spread10(q[2])
+    idx = np.arange(means.shape[1])
+    return np.lexsort((idx, code)).astype(np.int64)
+
+
+def _order(G, planes, dev):
+    import torch
+    ws = g4d.RenderWorkspace(max(G.n, 1), 16, 16, 1024, dev)
+    o = g4d.spatial_order(G, planes.bmin, planes.bmax, ws)
+    torch.cuda.synchronize()
+    return o
+
+
+def test_spatial_order_is_the_morton_order(dev):
+    sc = synth.config2(n_cams=1, n_times=1)
+    G = g4d.DeviceGaussians(sc.gaussians, dev)
+    got = _order(G, sc.planes, dev).cpu().numpy().astype(np.int64)
+    assert np.array_equal(np.sort(got), np.arange(G.n))
+    np.testing.assert_array_equal(got, _morton_order(sc.gaussians.means, sc.planes.bmin, sc.planes.bmax))
+
+
+def _deform(G, P, M, t, dev):
+    import torch
+    S = g4d.DeviceSplats(G.n, G.sh_degree, None if M.has_colour else G.sh, dev)
+    g4d.deform(G, P, M, t, S)
+    torch.cuda.synchronize()
+    return {k: getattr(S, k).cpu().numpy() for k in ("means", "scales", "quats", "opacity", "sh")}
+
+
+@pytest.mark.parametrize("name", ["100k", "heads", "large_bf16"])
+def test_set_stored_in_order_deforms_to_the_permuted_result(dev, name):
+    if name == "100k":
+        sc, prec = synth.config2(n_cams=1, n_times=1), g4d.MLP_F32
+    elif name == "heads":
+        sc, prec = synth.config2(n=20_000, n_cams=1, n_times=1, colour_opacity=True), g4d.MLP_F32
+    else:
+        sc, prec = synth.config4(n=60_000), g4d.MLP_BF16
+    log(f"[spatial order] {name}: n={sc.gaussians.n}")
+    G = g4d.DeviceGaussians(sc.gaussians, dev)
+    P = g4d.DevicePlanes(sc.planes, dev)
+    M = g4d.DeviceMLP(sc.mlp, dev, prec)
+    a = _deform(G, P, M, 0.37, dev)
+    order = _order(G, sc.planes, dev)
+    g4d.store_in_order(G, order)
+    b = _deform(G, P, M, 0.37, dev)
+    o = order.cpu().numpy().astype(np.int64)
+    for k in a:
+        want = a[k].reshape(-1, G.n)[:, o]
+        assert np.array_equal(want.view(np.uint32), b[k].reshape(-1, G.n).view(np.uint32)), (name, k)
+
+
+def test_set_stored_in_order_renders_as_the_oracle(dev):
+    """The benchmark's layout: the 100k set stored in Morton order, deformed
+    by the oracle, rendered at 800x800 against the oracle on the same
+    (permuted) set: keys bit-exact, image within tolerance."""
+    sc = synth.config2()
+    o = _morton_order(sc.gaussians.means, sc.planes.bmin, sc.planes.bmax)
+    g = sc.gaussians
+    for k in ("means", "log_scales", "quats", "opacity_logits", "sh"):
+        setattr(g, k, np.ascontiguousarray(getattr(g, k)[..., o]))
+    cam, t = sc.cameras[5], sc.timestamps[11]
+    d = oracle.deform(g, sc.planes, sc.mlp, t)
+    _check_render(oracle.to_splats32(d, g.sh, 3), cam, "C2 frame, Morton layout", capacity=8 << 20)
