@@ -134,7 +134,7 @@ def cpu_baseline(sc, frames, n_frames: int, single_frames: int = 1):
 
 
 def serving_bench(seconds: float, rate: float, budget_gb: float, slots: int, warm_s: float = 2.0,
-                  sat_requests: int = 2000):
+                  sat_requests: int = 2000, tight_budget_gb: float = 2.0, tight_s: float = 10.0):
     """Poisson requests over three resident scenes (50k and 150k Gaussians
     from the cube generator, 300k from the box-and-cluster generator), each
     picking a scene, one of 20 ring cameras, t ~ U[0, 1] and a frame size
@@ -154,8 +154,8 @@ def serving_bench(seconds: float, rate: float, budget_gb: float, slots: int, war
     dev_scenes = [(g4d.DeviceGaussians(g, dev), g4d.DevicePlanes(p, dev), g4d.DeviceMLP(m, dev))
                   for (g, p, m, _) in scenes]
 
-    def run(slots_, graphs, batch):
-        srv = g4d.Server(int(budget_gb * (1 << 30)), max_slots=slots_, use_graphs=graphs, batch_deform=batch,
+    def run(slots_, graphs, batch, budget=budget_gb, dur=seconds):
+        srv = g4d.Server(int(budget * (1 << 30)), max_slots=slots_, use_graphs=graphs, batch_deform=batch,
                          max_width=1352, max_height=1014)
         ids = [srv.add_scene(*d) for d in dev_scenes]
         log(f"serving ({slots_} slots, graphs={graphs}, batch={batch}): warming {len(ids) * len(res)} classes")
@@ -169,6 +169,8 @@ def serving_bench(seconds: float, rate: float, budget_gb: float, slots: int, war
         k = 0
         next_log = 5.0
         for (ta, si, ci, t, r) in trace:
+            if ta >= warm_s + dur:
+                break
             delay = t0 + ta - time.perf_counter()
             if delay > 0:
                 time.sleep(delay)
@@ -184,7 +186,7 @@ def serving_bench(seconds: float, rate: float, budget_gb: float, slots: int, war
         # closed loop: the measured part of the trace submitted back to back
         # (arrival times ignored), completions per second at saturation
         srv.reset_stats()
-        sat = [(si, ci, t, r) for (ta, si, ci, t, r) in trace if ta >= warm_s][:sat_requests]
+        sat = [(si, ci, t, r) for (ta, si, ci, t, r) in trace if warm_s <= ta < warm_s + dur][:sat_requests]
         t0 = time.perf_counter()
         for j, (si, ci, t, r) in enumerate(sat):
             srv.submit(si, cams[si][res.index(tuple(r))][ci], t, outs[tuple(r)][j % 48])
@@ -198,13 +200,24 @@ def serving_bench(seconds: float, rate: float, budget_gb: float, slots: int, war
     log(f"served: {served}")
     plain = run(1, False, False)
     log(f"plain: {plain}")
+    # the same trace's first `tight_s` seconds with a tight request-memory
+    # budget, so that admissions wait for memory
+    tight = None
+    if tight_budget_gb:
+        tight = run(slots, True, True, budget=tight_budget_gb, dur=tight_s)
+        log(f"served, {tight_budget_gb:g} GB budget: {tight}")
     keep = ("p50_ms", "p99_ms", "mean_ms", "max_ms", "frames_per_s", "completed", "rejected",
-            "batched_launches", "graph_replays", "overflow_retries", "saturation_frames_per_s")
-    return {"workload": f"Poisson {rate:.0f}/s for {seconds:.0f} s (+{warm_s:.0f} s warm-up), 3 resident scenes "
-                        "(50k, 150k, 300k), frames 400x400 / 800x800 / 1352x1014",
-            "served": {k: served[k] for k in keep}, "plain": {k: plain[k] for k in keep},
-            "slots": slots, "hbm_budget_gb": budget_gb,
-            "peak_request_bytes": int(served["peak_bytes"])}
+            "batched_launches", "graph_replays", "eager_renders", "overflow_retries", "saturation_frames_per_s")
+    out = {"workload": f"Poisson {rate:.0f}/s for {seconds:.0f} s (+{warm_s:.0f} s warm-up), 3 resident scenes "
+                       "(50k, 150k, 300k), frames 400x400 / 800x800 / 1352x1014",
+           "served": {k: served[k] for k in keep}, "plain": {k: plain[k] for k in keep},
+           "slots": slots, "hbm_budget_gb": budget_gb,
+           "peak_request_bytes": int(served["peak_bytes"])}
+    if tight is not None:
+        out["served_tight_budget"] = {"hbm_budget_gb": tight_budget_gb, "seconds": tight_s,
+                                      "peak_request_bytes": int(tight["peak_bytes"]),
+                                      **{k: tight[k] for k in keep}}
+    return out
 
 
 def time_scene(sc, precision, steps, warmup, n_frames=None):
@@ -504,7 +517,7 @@ def main():
                     help="also time the large configuration (FP32 and BF16 MLP) and a sweep over N")
     ap.add_argument("--training", action="store_true",
                     help="only time the training iteration (2000 Gaussians, 800x800) and print its record")
-    ap.add_argument("--serve-seconds", type=float, default=20.0)
+    ap.add_argument("--serve-seconds", type=float, default=30.0)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-slots", type=int, default=3)
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)

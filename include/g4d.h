@@ -460,8 +460,9 @@ const char *g4d_version(void);
  * (scene, camera, t) requests with continuous batching: requests are
  * admitted while render slots and the memory budget allow, the
  * deformations of newly admitted requests run as one batched launch per
- * shape class, and each admitted request renders on its own stream (a
- * captured graph per slot and frame size in steady state), so requests
+ * shape class (on the stream of the first request of the class), and each
+ * admitted request renders on its own stream (replaying a captured graph per
+ * buffer set and frame size when it overlaps other requests), so requests
  * that arrive while others run overlap on the device.  The server owns all
  * memory it allocates; images are written to caller device buffers. */
 typedef struct g4d_server g4d_server;
@@ -469,7 +470,8 @@ typedef struct g4d_server g4d_server;
 typedef struct {
     size_t hbm_budget;          /* bytes for per-request memory (workspaces, deformed sets) */
     int32_t max_slots;          /* concurrent requests on the device, 1..64 */
-    int32_t use_graphs;         /* capture steady-state renders as HIP graphs */
+    int32_t use_graphs;         /* replay captured HIP graphs for renders that overlap other
+                                   requests (a request alone on the device launches directly) */
     int32_t batch_deform;       /* 1: batched deformation per admission round */
     int32_t max_width, max_height;
     double instance_factor;     /* capacity = factor * n * tiles-per-Gaussian bound; see server.cpp */

@@ -192,10 +192,11 @@ struct g4d_server {
     std::vector<int> free_slots;
     uint64_t next_ticket = 1;
     bool stop = false;
+    std::atomic<uint64_t> submit_count{0};   // requests submitted (read by the idle worker's poll)
+    std::atomic<bool> stop_flag{false};
     std::thread worker;
     // device objects
     int device = 0;
-    hipStream_t deform_stream = nullptr;
     std::vector<hipStream_t> slot_stream;
     std::vector<hipEvent_t> slot_done;
     std::vector<hipEvent_t> round_events;
@@ -278,11 +279,18 @@ hipEvent_t next_round_event(g4d_server *S) {
     return e;
 }
 
-// Launch deform + render for the requests admitted in one round.
-void launch_round(g4d_server *S, std::vector<Req *> &batch) {
+// Launch deform + render for the requests admitted in one round.  A request
+// that has the device to itself (nothing else in flight or queued) renders
+// with direct launches, which start the device soonest; requests that
+// overlap others replay their captured graphs, which take the worker thread
+// one call per render instead of one per kernel.
+void launch_round(g4d_server *S, std::vector<Req *> &batch, bool busy) {
     const bool batched = S->cfg.batch_deform != 0;
     if (batched) {
-        // one batched launch per shape class, chunks of G4D_MAX_BATCH_JOBS
+        // one batched launch per shape class, chunks of G4D_MAX_BATCH_JOBS,
+        // on the slot stream of the chunk's first request (no stream hop for
+        // it: a lone request runs deform and render back to back on its
+        // stream); the chunk's other requests wait for it with an event
         std::map<int, std::vector<Req *>> by_shape;
         for (Req *r : batch) by_shape[r->shape].push_back(r);
         for (auto &kv : by_shape) {
@@ -295,16 +303,19 @@ void launch_round(g4d_server *S, std::vector<Req *> &batch) {
                     const Scene &sc = *S->scenes[std::get<0>(r->key)];
                     jobs[q] = g4d_deform_job{&sc.G, &sc.P, &sc.M, r->t, &r->bufs->splats};
                 }
-                const g4d_status st = deform_batched(jobs, (int)m, S->deform_stream);
+                hipStream_t ds = S->slot_stream[v[i]->slot];
+                const g4d_status st = deform_batched(jobs, (int)m, ds);
                 if (st != G4D_OK) {
                     for (size_t q = 0; q < m; ++q) v[i + q]->status = st;
                 }
                 ++S->stats.batched_launches;
+                if (m > 1) {
+                    hipEvent_t ev = next_round_event(S);
+                    (void)hipEventRecord(ev, ds);
+                    for (size_t q = 1; q < m; ++q) (void)hipStreamWaitEvent(S->slot_stream[v[i + q]->slot], ev, 0);
+                }
             }
         }
-        hipEvent_t ev = next_round_event(S);
-        (void)hipEventRecord(ev, S->deform_stream);
-        for (Req *r : batch) (void)hipStreamWaitEvent(S->slot_stream[r->slot], ev, 0);
     }
     for (Req *r : batch) {
         hipStream_t s = S->slot_stream[r->slot];
@@ -317,7 +328,7 @@ void launch_round(g4d_server *S, std::vector<Req *> &batch) {
         }
         if (r->status == G4D_OK) {
             g4d_status st = G4D_OK;
-            if (S->cfg.use_graphs) {
+            if (S->cfg.use_graphs && busy) {
                 if (!b->exec) {
                     hipGraph_t g = nullptr;
                     if (hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed) != hipSuccess) {
@@ -351,12 +362,14 @@ void launch_round(g4d_server *S, std::vector<Req *> &batch) {
     }
 }
 
+constexpr int kIdleSpinUs = 2000;   // idle worker: polling window before it sleeps
+
 void worker_loop(g4d_server *S) {
     (void)hipSetDevice(S->device);
     std::vector<Req *> batch;
     while (true) {
         batch.clear();
-        bool idle = false;
+        bool idle = false, busy = false;
         {
             std::unique_lock<std::mutex> lk(S->mu);
             // completions
@@ -430,14 +443,25 @@ void worker_loop(g4d_server *S) {
                 S->inflight.push_back(r);
                 batch.push_back(r);
             }
+            busy = batch.size() > 1 || S->inflight.size() > batch.size() || !S->pending.empty();
             if (S->stop && S->pending.empty() && S->inflight.empty() && batch.empty()) break;
             idle = batch.empty() && S->inflight.empty() && S->pending.empty();
             if (idle) {
-                S->cv_work.wait_for(lk, std::chrono::milliseconds(5));
+                // poll for a new request for a while before sleeping: a thread
+                // woken from a condition variable starts tens of microseconds
+                // late, which an arrival at an idle device would pay in full
+                const uint64_t seen = S->submit_count.load(std::memory_order_acquire);
+                const auto spin_end = std::chrono::steady_clock::now() + std::chrono::microseconds(kIdleSpinUs);
+                lk.unlock();
+                while (S->submit_count.load(std::memory_order_acquire) == seen && !S->stop_flag.load() &&
+                       std::chrono::steady_clock::now() < spin_end)
+                    std::this_thread::yield();
+                lk.lock();
+                if (S->pending.empty() && !S->stop) S->cv_work.wait_for(lk, std::chrono::milliseconds(5));
                 continue;
             }
         }
-        if (!batch.empty()) launch_round(S, batch);
+        if (!batch.empty()) launch_round(S, batch, busy);
         else std::this_thread::yield();
     }
 }
@@ -467,7 +491,7 @@ extern "C" g4d_status g4d_server_create(const g4d_server_config *cfg, g4d_server
         delete S;
         return G4D_EHIP;
     }
-    hipError_t e = hipStreamCreateWithFlags(&S->deform_stream, hipStreamNonBlocking);
+    hipError_t e = hipSuccess;
     S->slot_stream.resize(cfg->max_slots);
     S->slot_done.resize(cfg->max_slots);
     for (int i = 0; i < cfg->max_slots && e == hipSuccess; ++i) {
@@ -570,6 +594,7 @@ extern "C" g4d_status g4d_server_submit(g4d_server *S, int32_t scene_id, const g
     ++S->stats.submitted;
     *ticket = r->ticket;
     S->pending.push_back(r.get());
+    S->submit_count.fetch_add(1, std::memory_order_release);
     S->reqs[r->ticket] = std::move(r);
     S->cv_work.notify_one();
     return G4D_OK;
@@ -636,6 +661,7 @@ extern "C" g4d_status g4d_server_destroy(g4d_server *S) {
         std::unique_lock<std::mutex> lk(S->mu);
         S->cv_done.wait(lk, [&] { return S->pending.empty() && S->inflight.empty(); });
         S->stop = true;
+        S->stop_flag.store(true);
         S->cv_work.notify_all();
     }
     if (S->worker.joinable()) S->worker.join();
@@ -648,7 +674,6 @@ extern "C" g4d_status g4d_server_destroy(g4d_server *S) {
         if (S->slot_done[i]) (void)hipEventDestroy(S->slot_done[i]);
         if (S->slot_stream[i]) (void)hipStreamDestroy(S->slot_stream[i]);
     }
-    if (S->deform_stream) (void)hipStreamDestroy(S->deform_stream);
     if (S->status_host) (void)hipHostFree(S->status_host);
     delete S;
     return G4D_OK;

@@ -1,6 +1,7 @@
 """The serving loop on the GPU: every request's image is the same whether it
-runs alone, in a concurrent mix, as a graph replay or eagerly, and equals
-the direct deform + render path (and the oracle within tolerance)."""
+runs alone (direct launches: the device is its own), in a concurrent mix
+(graph replays), on a server without graphs, and equals the direct deform +
+render path (and the oracle within tolerance)."""
 import numpy as np
 import pytest
 
@@ -82,10 +83,15 @@ def test_alone_mixed_graph_eager_and_direct_agree(dev):
     log(f"[serve] {len(reqs)} requests over {len(scenes)} scenes")
     srv, dev_objs = _server(scenes, max_slots=8, use_graphs=True, batch_deform=True)
     alone = _run(srv, reqs, concurrent=False)
+    st_alone = srv.stats()
     mixed = _run(srv, reqs, concurrent=True)
     st = srv.stats()
     srv.close()
-    assert st["graph_replays"] >= 2 * len(reqs) and st["batched_launches"] >= 1
+    # alone: every render launched directly; in the mix the renders that
+    # overlap others replay graphs (every request lands in one of the two)
+    assert st_alone["eager_renders"] == len(reqs) and st_alone["graph_replays"] == 0
+    assert st["graph_replays"] >= 1 and st["batched_launches"] >= 1
+    assert st["graph_replays"] + st["eager_renders"] >= 2 * len(reqs)
     eager_srv, _ = _server(scenes, max_slots=4, use_graphs=False, batch_deform=False)
     eager = _run(eager_srv, reqs, concurrent=True)
     eager_srv.close()
