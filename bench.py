@@ -344,22 +344,42 @@ def time_composition(steps, warmup, n_each=50_000):
             "instances_max": kmax}
 
 
-def time_training_step(steps, warmup):
-    """One training iteration of the small configuration's scene (2000
-    Gaussians, SH0, planes 32 x t8 F16, MLP 16-64-10) at 800x800: deform +
-    render, the L1 loss and its gradient against a target frame, render
-    backward and deform backward (gradients of every canonical parameter,
-    plane cell and decoder weight), the grid TV term, and the Adam update of
-    every trainable tensor."""
+TRAIN_WORKLOADS = {
+    "small": "training iteration, 2000 Gaussians (SH0, planes 32 x t8 F16, MLP 16-64-10), 800x800, "
+             "L1 + grid TV; gradients of every canonical parameter, plane cell and decoder weight; "
+             "Adam update of all of them",
+    "100k": "training iteration, 100k Gaussians (shell, SH3, planes 64/128 x t25 F32, MLP 64-64-10), 800x800, "
+            "L1 + grid TV; gradients of every canonical parameter, plane cell and decoder weight; "
+            "Adam update of all of them",
+}
+
+
+def time_training_step(steps, warmup, which="small", layout="index"):
+    """One training iteration at 800x800: deform + render, the L1 loss and
+    its gradient against a target frame, render backward and deform backward
+    (gradients of every canonical parameter, plane cell and decoder weight),
+    the grid TV term, and the Adam update of every trainable tensor.  "small"
+    is the small configuration's scene (2000 Gaussians, SH0, planes 32 x t8
+    F16, MLP 16-64-10), "100k" the headline scene (stored in Morton order
+    with layout="morton")."""
     import torch
     from paper_2310_08528_amd import g4d, synth
     dev = "cuda:0"
     ev = HipEvents()
-    sc = synth.config1()
-    cam = g4d.camera_struct(synth.look_at_camera((0.0, 0.0, 4.0), (0.0, 0.0, 0.0), 800, 800, 50.0))
+    if which == "small":
+        sc = synth.config1()
+        cam = g4d.camera_struct(synth.look_at_camera((0.0, 0.0, 4.0), (0.0, 0.0, 0.0), 800, 800, 50.0))
+        cap_per = 256
+    else:
+        sc = synth.config2(n_cams=1, n_times=20)
+        cam = g4d.camera_struct(sc.cameras[0])
+        cap_per = 64
     G, P, M = g4d.DeviceGaussians(sc.gaussians, dev), g4d.DevicePlanes(sc.planes, dev), g4d.DeviceMLP(sc.mlp, dev)
     S = g4d.DeviceSplats(G.n, G.sh_degree, G.sh, dev)
-    ws = g4d.RenderWorkspace(G.n, 800, 800, 256 * G.n + 4096, dev)
+    ws = g4d.RenderWorkspace(G.n, 800, 800, cap_per * G.n + 4096, dev)
+    if layout == "morton":
+        g4d.store_in_order(G, g4d.spatial_order(G, sc.planes.bmin, sc.planes.bmax, ws))
+        torch.cuda.synchronize()
     img = torch.empty((3, 800, 800), device=dev)
     T = torch.empty((800, 800), device=dev)
     nc = torch.empty((800, 800), dtype=torch.int32, device=dev)
@@ -416,9 +436,7 @@ def time_training_step(steps, warmup):
     st = lambda i: round(float(np.median([ev.elapsed(m[i], m[i + 1]) for m in marks])), 4)
     evals = int(g4d.read_status(ws).blend_evals)
     rb_ms = float(np.median([ev.elapsed(m[2], m[3]) for m in marks]))
-    return {"workload": "training iteration, 2000 Gaussians (SH0, planes 32 x t8 F16, MLP 16-64-10), 800x800, "
-                        "L1 + grid TV; gradients of every canonical parameter, plane cell and decoder weight; "
-                        "Adam update of all of them",
+    return {"workload": TRAIN_WORKLOADS[which], "layout": layout,
             "steps": steps, "steps_per_s": round(steps / wall, 2), "ms_per_step": round(1e3 * wall / steps, 4),
             "stages_ms": {"forward": st(0), "loss": st(1), "render_backward": st(2), "deform_backward": st(3),
                           "tv_and_adam": st(4)},
@@ -533,7 +551,9 @@ def main():
     torch.cuda.set_device(0)
     ev = HipEvents()
     if args.training:
-        print(json.dumps({"training_step": time_training_step(args.steps, args.warmup)}), flush=True)
+        print(json.dumps({"training_step": time_training_step(args.steps, args.warmup),
+                          "training_step_100k": time_training_step(min(args.steps, 50), min(args.warmup, 5),
+                                                                   "100k", args.layout)}), flush=True)
         return
 
     sc = synth.config2(n=args.n)
@@ -748,6 +768,8 @@ def main():
     # the training direction on its own workload (a few seconds; not part of `value`)
     log("training iteration")
     out["training"] = time_training_step(200, 20)
+    log("training iteration, 100k Gaussians")
+    out["training_100k"] = time_training_step(50, 5, "100k", args.layout)
     if args.extra:
         out["extra"] = extra_measurements(min(K, 200), 20)
     if not args.no_cpu_baseline:

@@ -17,11 +17,15 @@
 //                         grid coordinates receive the bilinear slopes
 //                         (zero at and beyond the box border, as the border
 //                         clamp of the query has no slope there).
-// The three time planes (xt, yt, zt) take every Gaussian's update in the two
-// rows of the frame's t: when those rows fit (2 x res x F per plane and
-// scale, at most kTimeLds bytes in all), a block sums its updates to them in
-// LDS and adds the sums to the plane gradients once (the spatial planes
-// scatter straight to global memory).
+// Plane-cell updates are summed per block before they reach memory: for
+// every plane the block takes the window of cells its Gaussians touch (the
+// range of their corner cells along each grid axis; the time axis has the two
+// rows of the frame's t), and the windows that fit in the LDS left free by
+// the decoder phases accumulate the updates with LDS atomics; each window is
+// then added to the plane gradients with one global atomic per nonzero value.
+// A block whose Gaussians are spatially close (a set stored in spatial order)
+// has small windows; a plane whose window does not fit scatters straight to
+// global memory.
 // W1 is read from global memory (L1/L2-resident: every block reads it); the
 // head weights, their biases and the per-row gradient pointers are staged in
 // LDS once per block (the heads are selected by a runtime row index, which
@@ -56,11 +60,8 @@ struct BwdJob {
     float bmin[3], bmax[3];
     int n, n_sh_rows;                    // n_sh_rows: 3 (d+1)^2 of the Gaussians
     float t;
-    int tp_floats;                       // LDS floats of the time-plane rows (0: scatter to global)
-    int tp_off[kMaxScalesB][3];          // offset of plane (l, xt/yt/zt) in that region
 };
 
-constexpr int kTimeLds = 32 * 1024;
 constexpr size_t kLdsMax = 160 * 1024;   // LDS per CU (and per block) on gfx950
 
 __device__ constexpr int axis_a(int p) { return p == 2 ? 1 : (p == 5 ? 2 : (p == 4 ? 1 : 0)); }
@@ -96,13 +97,16 @@ __global__ __launch_bounds__(kThreads) void k_deform_bwd(BwdJob J, int rows) {
     constexpr int FH = K + 1, HH = HID + 1, DS = 65;
     extern __shared__ __attribute__((aligned(16))) float smem[];
     float *s_fh = smem;                  // [GB][K+1]: f_h, later df_h
-    float *s_h = s_fh + GB * FH;        // [GB][HID+1]: h (after ReLU)
+    float *s_dm = s_fh + GB * FH;       // [GB][3]: dL/d canonical mean
+    float *s_h = s_dm + GB * 3;         // [GB][HID+1]: h (after ReLU)
     float *s_dz = s_h + GB * HH;        // [GB][HID+1]: dL/d(pre-activation)
     float *s_dd = s_dz + GB * HH;       // [GB][65]: head outputs, then their gradients
-    float *s_dm = s_dd + GB * DS;       // [GB][3]: dL/d canonical mean
-    float *s_w2 = s_dm + GB * 3;        // [rows][HID+1]: head weights
+    float *s_w2 = s_dd + GB * DS;       // [rows][HID+1]: head weights
     float *s_b2 = s_w2 + rows * HH;      // [rows]
-    float *s_tp = s_b2 + rows;           // [tp_floats]: time-plane rows of this frame's t
+    // the plane-cell windows of the encoder backward reuse everything from
+    // s_h on (dead once df_h is computed)
+    float *s_win = s_h;
+    const int win_cap = 2 * GB * HH + GB * DS + rows * HH + rows;
     __shared__ float *s_dw[64];          // gradient row of head row r (null: padding)
     __shared__ float *s_db[64];
     const int tid = threadIdx.x;
@@ -125,7 +129,6 @@ __global__ __launch_bounds__(kThreads) void k_deform_bwd(BwdJob J, int rows) {
         int hq, k;
         s_w2[r * HH + j] = head_of(J, r, hq, k) ? J.hw[hq][(size_t)k * HID + j] : 0.0f;
     }
-    for (int idx = tid; idx < J.tp_floats; idx += kThreads) s_tp[idx] = 0.0f;
 
     // ---- A. encoder (as in the forward)
     constexpr int LPG = F / 4;
@@ -171,13 +174,26 @@ __global__ __launch_bounds__(kThreads) void k_deform_bwd(BwdJob J, int rows) {
         }
     }
     __syncthreads();
-    // ---- B. h = ReLU(W1 f_h + b1); Gaussian fastest, so a weight is one broadcast load
-    for (int idx = tid; idx < GB * HID; idx += kThreads) {
-        const int g = idx % GB, j = idx / GB;
-        float acc = J.b1[j];
-        const float *w = J.w1 + (size_t)j * K;
-        for (int i = 0; i < K; ++i) acc += w[i] * s_fh[g * FH + i];
-        s_h[g * HH + j] = fmaxf(acc, 0.0f);
+    // ---- B. h = ReLU(W1 f_h + b1).  With 64 Gaussians per block a wave owns
+    // whole rows of W1 (lane = Gaussian), so a row is wave-uniform and its
+    // weights come through scalar loads; with fewer, Gaussian fastest (a
+    // weight is one broadcast vector load)
+    const int wave_u = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+    if constexpr (GB == 64) {
+        for (int j = wave_u; j < HID; j += kThreads / 64) {
+            const float *w = J.w1 + (size_t)j * K;
+            float acc = J.b1[j];
+            for (int i = 0; i < K; ++i) acc += w[i] * s_fh[lane * FH + i];
+            s_h[lane * HH + j] = fmaxf(acc, 0.0f);
+        }
+    } else {
+        for (int idx = tid; idx < GB * HID; idx += kThreads) {
+            const int g = idx % GB, j = idx / GB;
+            float acc = J.b1[j];
+            const float *w = J.w1 + (size_t)j * K;
+            for (int i = 0; i < K; ++i) acc += w[i] * s_fh[g * FH + i];
+            s_h[g * HH + j] = fmaxf(acc, 0.0f);
+        }
     }
     __syncthreads();
     // ---- C. head outputs delta = W2 h + b2 (padding rows: zero weights)
@@ -281,13 +297,78 @@ __global__ __launch_bounds__(kThreads) void k_deform_bwd(BwdJob J, int rows) {
         }
     }
     __syncthreads();
-    // df_h = W1^T dz (overwrites f_h)
-    for (int idx = tid; idx < GB * K; idx += kThreads) {
-        const int g = idx % GB, i = idx / GB;
-        float acc = 0.0f;
-        for (int j = 0; j < HID; ++j) acc += J.w1[(size_t)j * K + i] * s_dz[g * HH + j];
-        s_fh[g * FH + i] = acc;
+    // df_h = W1^T dz (overwrites f_h); column i of W1 wave-uniform as above
+    if constexpr (GB == 64) {
+        for (int i = wave_u; i < K; i += kThreads / 64) {
+            float acc = 0.0f;
+            for (int j = 0; j < HID; ++j) acc += J.w1[(size_t)j * K + i] * s_dz[lane * HH + j];
+            s_fh[lane * FH + i] = acc;
+        }
+    } else {
+        for (int idx = tid; idx < GB * K; idx += kThreads) {
+            const int g = idx % GB, i = idx / GB;
+            float acc = 0.0f;
+            for (int j = 0; j < HID; ++j) acc += J.w1[(size_t)j * K + i] * s_dz[g * HH + j];
+            s_fh[g * FH + i] = acc;
+        }
     }
+    __syncthreads();
+    // ---- plane-cell windows of this block: the range of the Gaussians'
+    // lower corner cells along each spatial grid axis, per scale; a window
+    // spans that range plus one (the upper corners)
+    __shared__ int s_lo[kMaxScalesB * 3], s_hi[kMaxScalesB * 3];
+    __shared__ int s_woff[kMaxScalesB * 6], s_wa0[kMaxScalesB * 6], s_wb0[kMaxScalesB * 6];
+    __shared__ int s_wn[kMaxScalesB * 6], s_wm[kMaxScalesB * 6];
+    __shared__ int s_wtotal;
+    if (tid < 3 * L) {
+        s_lo[tid] = 0x7fffffff;
+        s_hi[tid] = -1;
+    }
+    __syncthreads();
+    if (tid < GB && g0 + tid < n) {
+        const int g = g0 + tid;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const float xk = J.means[(size_t)k * n + g] - J.bmin[k];
+#pragma unroll
+            for (int l = 0; l < L; ++l) {
+                int i0;
+                float w;
+                grid_coord(xk, J.gscale[l][k], J.res[l][k], i0, w);
+                atomicMin(&s_lo[l * 3 + k], i0);
+                atomicMax(&s_hi[l * 3 + k], i0);
+            }
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int used = 0;
+        for (int l = 0; l < L; ++l) {
+            int it;
+            float wt;
+            grid_coord(J.t, J.gscale[l][3], J.res[l][3], it, wt);
+            for (int p = 0; p < 6; ++p) {
+                const int a = axis_a(p), b = axis_b(p), q = l * 6 + p;
+                const int la = s_lo[l * 3 + a], ha = s_hi[l * 3 + a];
+                const int lb = b == 3 ? it : s_lo[l * 3 + b], hb = b == 3 ? it : s_hi[l * 3 + b];
+                const int wn = ha - la + 2, wm = hb - lb + 2;
+                const int need = wn * wm * F;
+                if (ha >= la && hb >= lb && used + need <= win_cap) {
+                    s_woff[q] = used;
+                    s_wa0[q] = la;
+                    s_wb0[q] = lb;
+                    s_wn[q] = wn;
+                    s_wm[q] = wm;
+                    used += need;
+                } else {
+                    s_woff[q] = -1;
+                }
+            }
+        }
+        s_wtotal = used;
+    }
+    __syncthreads();
+    for (int i = tid; i < s_wtotal; i += kThreads) s_win[i] = 0.0f;
     __syncthreads();
     // ---- encoder backward (Eq. 7)
 #pragma unroll
@@ -310,7 +391,7 @@ __global__ __launch_bounds__(kThreads) void k_deform_bwd(BwdJob J, int rows) {
                 float4 val[6];
                 float wa_[6], wb_[6];
                 size_t off[6];
-                int na_[6];
+                int na_[6], ia_[6], ib_[6];
 #pragma unroll
                 for (int p = 0; p < 6; ++p) {
                     const int a = axis_a(p), b = axis_b(p);
@@ -321,6 +402,8 @@ __global__ __launch_bounds__(kThreads) void k_deform_bwd(BwdJob J, int rows) {
                     grid_coord(x[b], J.gscale[l][b], nb, ib, wb);
                     off[p] = ((size_t)ib * na + ia) * F + 4 * c4;
                     na_[p] = na;
+                    ia_[p] = ia;
+                    ib_[p] = ib;
                     wa_[p] = wa;
                     wb_[p] = wb;
                     const float *base = J.planes[l * 6 + p] + off[p];
@@ -358,17 +441,30 @@ __global__ __launch_bounds__(kThreads) void k_deform_bwd(BwdJob J, int rows) {
                     const float w01 = (1.0f - wa) * wb, w11 = wa * wb;
                     const size_t rowF = (size_t)na_[p] * F;
                     const float dvv[4] = {dv.x, dv.y, dv.z, dv.w};
-                    // time planes: rows ib and ib + 1 of the LDS copy (same t for every Gaussian)
-                    const bool in_lds = p >= 3 && J.tp_floats > 0;
-                    float *gb = in_lds ? s_tp + J.tp_off[l][p - 3] + (off[p] % rowF)
-                                       : J.d_planes[l * 6 + p] + off[p];
+                    const int q = l * 6 + p;
+                    const int wo = s_woff[q];
+                    if (wo >= 0) {
+                        // this block's window of the plane, in LDS
+                        const int wrow = s_wn[q] * F;
+                        float *lb = s_win + wo + ((ib_[p] - s_wb0[q]) * s_wn[q] + (ia_[p] - s_wa0[q])) * F + 4 * c4;
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) {
-                        if (dvv[c] == 0.0f) continue;
-                        if (w00 != 0.0f) atomicAdd(gb + c, w00 * dvv[c]);
-                        if (w10 != 0.0f) atomicAdd(gb + F + c, w10 * dvv[c]);
-                        if (w01 != 0.0f) atomicAdd(gb + rowF + c, w01 * dvv[c]);
-                        if (w11 != 0.0f) atomicAdd(gb + rowF + F + c, w11 * dvv[c]);
+                        for (int c = 0; c < 4; ++c) {
+                            if (dvv[c] == 0.0f) continue;
+                            if (w00 != 0.0f) atomicAdd(lb + c, w00 * dvv[c]);
+                            if (w10 != 0.0f) atomicAdd(lb + F + c, w10 * dvv[c]);
+                            if (w01 != 0.0f) atomicAdd(lb + wrow + c, w01 * dvv[c]);
+                            if (w11 != 0.0f) atomicAdd(lb + wrow + F + c, w11 * dvv[c]);
+                        }
+                    } else {
+                        float *gb = J.d_planes[q] + off[p];
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) {
+                            if (dvv[c] == 0.0f) continue;
+                            if (w00 != 0.0f) atomicAdd(gb + c, w00 * dvv[c]);
+                            if (w10 != 0.0f) atomicAdd(gb + F + c, w10 * dvv[c]);
+                            if (w01 != 0.0f) atomicAdd(gb + rowF + c, w01 * dvv[c]);
+                            if (w11 != 0.0f) atomicAdd(gb + rowF + F + c, w11 * dvv[c]);
+                        }
                     }
                     // slopes of the bilinear query along its two grid axes
                     const int a = axis_a(p), b = axis_b(p);
@@ -406,24 +502,20 @@ __global__ __launch_bounds__(kThreads) void k_deform_bwd(BwdJob J, int rows) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) J.d_means[(size_t)k * n + g0 + tid] = s_dm[tid * 3 + k];
     }
-    if (J.tp_floats > 0) {
-        // the block's time-plane sums, one global atomic per touched value
-#pragma unroll
-        for (int l = 0; l < L; ++l) {
-            int ib;
-            float wb;
-            grid_coord(J.t, J.gscale[l][3], J.res[l][3], ib, wb);
-#pragma unroll
-            for (int p = 3; p < 6; ++p) {
-                const int na = J.res[l][axis_a(p)];
-                const int cnt = 2 * na * F;
-                const float *src = s_tp + J.tp_off[l][p - 3];
-                float *dst = J.d_planes[l * 6 + p] + (size_t)ib * na * F;   // rows ib, ib + 1
-                for (int i = tid; i < cnt; i += kThreads) {
-                    const float v = src[i];
-                    if (v != 0.0f) atomicAdd(dst + i, v);
-                }
-            }
+    // the block's windows into the plane gradients, one global atomic per
+    // nonzero value (consecutive threads: consecutive values of a row)
+    for (int q = 0; q < L * 6; ++q) {
+        const int wo = s_woff[q];
+        if (wo < 0) continue;
+        const int wn = s_wn[q], cnt = wn * s_wm[q] * F;
+        const int na = J.res[q / 6][axis_a(q % 6)];
+        float *dst = J.d_planes[q] + ((size_t)s_wb0[q] * na + s_wa0[q]) * F;
+        for (int i = tid; i < cnt; i += kThreads) {
+            const float v = s_win[wo + i];
+            if (v == 0.0f) continue;
+            const int cell = i / F, f = i - cell * F;
+            const int cb = cell / wn, ca = cell - cb * wn;
+            atomicAdd(dst + ((size_t)cb * na + ca) * F + f, v);
         }
     }
 }
@@ -454,9 +546,9 @@ const BwdEntry kBwdKernels[] = {
     G4D_BWD_ENTRY(32, 3, 64), G4D_BWD_ENTRY(32, 3, 128),
 };
 
-size_t bwd_smem(int gb, int K, int HID, int rows, int tp_floats) {
+size_t bwd_smem(int gb, int K, int HID, int rows) {
     return ((size_t)gb * (K + 1) + 2 * (size_t)gb * (HID + 1) + (size_t)gb * 65 + (size_t)gb * 3 +
-            (size_t)rows * (HID + 1) + rows + tp_floats) * 4;
+            (size_t)rows * (HID + 1) + rows) * 4;
 }
 
 }  // namespace
@@ -532,27 +624,17 @@ g4d_status deform_backward(const g4d_gaussians *G, const g4d_planes *P, const g4
     J.n = n;
     J.n_sh_rows = n_sh;
     J.t = t;
-    {
-        int tp = 0;
-        for (int l = 0; l < P->n_scales; ++l)
-            for (int a = 0; a < 3; ++a) {   // xt, yt, zt: spatial axis a, time rows
-                J.tp_off[l][a] = tp;
-                tp += 2 * P->res[l][a] * P->feat;
-            }
-        J.tp_floats = (size_t)tp * 4 <= (size_t)kTimeLds ? tp : 0;
-        if (bwd_smem(kGB, K, hid, rows, J.tp_floats) > kLdsMax) J.tp_floats = 0;   // either block size
-    }
     hipLaunchKernelGGL(k_fill_list, dim3(64, (unsigned)fl.n), dim3(256), 0, s, fl);
     if (n > 0) {
         const bool small = n <= kSmallN;
         const int gb = small ? kGBSmall : kGB;
         const BwdKernel fn = small ? ke->fn_small : ke->fn;
-        const size_t smem = bwd_smem(gb, K, hid, rows, J.tp_floats);
+        const size_t smem = bwd_smem(gb, K, hid, rows);
         static std::atomic<uint64_t> attr_done[2][sizeof(kBwdKernels) / sizeof(kBwdKernels[0])];
         const size_t idx = (size_t)(ke - kBwdKernels);
         // the largest head count (64 rows) sets the limit
         if (g4d_status st = ensure_max_lds(reinterpret_cast<const void *>(fn), attr_done[small][idx],
-                                           (int)std::min(bwd_smem(gb, K, hid, 64, kTimeLds / 4), kLdsMax)))
+                                           (int)std::min(bwd_smem(gb, K, hid, 64), kLdsMax)))
             return st;
         hipLaunchKernelGGL(fn, dim3((n + gb - 1) / gb), dim3(kThreads), smem, s, J, rows);
     }
