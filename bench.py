@@ -533,6 +533,9 @@ def main():
                     help="frames in flight for the reported throughput (1 = one frame at a time)")
     ap.add_argument("--extra", action="store_true",
                     help="also time the large configuration (FP32 and BF16 MLP) and a sweep over N")
+    ap.add_argument("--profile-frames", type=int, default=0,
+                    help="only run this many frames (deform + render, one at a time, after the copy "
+                         "calibration if asked) and exit: the workload the committed profiles are taken on")
     ap.add_argument("--training", action="store_true",
                     help="only time the training iteration (2000 Gaussians, 800x800) and print its record")
     ap.add_argument("--serve-seconds", type=float, default=30.0)
@@ -572,6 +575,25 @@ def main():
     # size the instance capacity over every frame of the sequence (grow on overflow)
     capacity = 64 * G.n + 4096
     ws = g4d.RenderWorkspace(G.n, W, H, capacity, dev)
+    if args.profile_frames:
+        if args.layout == "morton":
+            g4d.store_in_order(G, g4d.spatial_order(G, sc.planes.bmin, sc.planes.bmax, ws))
+        if args.copy_calibration:
+            src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+            dst = torch.empty_like(src)
+            for _ in range(5):
+                dst.copy_(src)
+            del src, dst
+        torch.cuda.synchronize()
+        for k in range(args.profile_frames):
+            ci, t = frames[k % len(frames)]
+            g4d.deform(G, P, M, t, S)
+            g4d.render(S, cams[ci], ws, img)
+        torch.cuda.synchronize()
+        st = g4d.read_status(ws)
+        assert st.overflow == 0 and st.sort_error == 0
+        print(json.dumps({"profile_frames": args.profile_frames, "layout": args.layout}), flush=True)
+        return
     kmax = 0
     for (ci, t) in frames:
         g4d.deform(G, P, M, t, S)

@@ -187,6 +187,25 @@ def _deform_compare(gpu, ref, name, tol):
     assert not bad, bad
 
 
+def _cell_edge_flags(means, planes, rel=4.0 * 2.0 ** -24):
+    """Means whose grid coordinate g = (x - bmin) (R - 1) / (bmax - bmin),
+    along any axis at any scale, lies within rel x (R - 1) cells of an integer
+    (the binary32 evaluation's reach: two roundings of g)."""
+    x = np.asarray(means, np.float64)
+    flag = np.zeros(x.shape[1], bool)
+    for res in planes.res:
+        for k in range(3):
+            r = res[k] - 1
+            gk = (x[k] - planes.bmin[k]) * r / (planes.bmax[k] - planes.bmin[k])
+            flag |= np.abs(gk - np.rint(gk)) <= rel * r + 1e-12
+    return flag
+
+
+def _morton_order(means, bmin, bmax):
+    from tests.test_gpu_spatial_order import _morton_order as mo
+    return mo(means, bmin, bmax)
+
+
 def _gpu_deform_backward(sc, t, gout):
     import torch
     G, P, M = (g4d.DeviceGaussians(sc.gaussians, DEV), g4d.DevicePlanes(sc.planes, DEV),
@@ -204,15 +223,24 @@ def _gpu_deform_backward(sc, t, gout):
 
 
 @pytest.mark.parametrize("case", ["tiny_h32", "small_config", "headline_shape", "heads_sh3", "blocks_of_64",
-                                  "headline_shape_64", "heads_sh3_64"])
+                                  "headline_shape_64", "heads_sh3_64", "headline_100k_morton"])
 def test_deform_backward_matches_oracle(dev, case):
     """Up to 4096 Gaussians the kernel takes 16 per block, above it 64 (the
     last three cases).  headline_shape_64 runs the 100k configuration's
     variant as the benchmark does: two encoder passes (32 features, two
     scales) and the time-plane updates scattered straight into the planes
     (their rows at t exceed the block's LDS); heads_sh3_64 the 59-row head
-    variant at 64 per block."""
-    if case == "blocks_of_64":
+    variant at 64 per block.  headline_100k_morton is the training leg's
+    scene at full size (100k Gaussians), stored in the Morton order of its
+    means as the benchmark stores it: blocks of spatially close Gaussians,
+    so their plane updates go through the LDS windows."""
+    if case == "headline_100k_morton":
+        sc = synth.config2(plane_dist="uniform", n_cams=1, n_times=1)
+        g = sc.gaussians
+        o = _morton_order(g.means, sc.planes.bmin, sc.planes.bmax)
+        for k in ("means", "log_scales", "quats", "opacity_logits", "sh"):
+            setattr(g, k, np.ascontiguousarray(getattr(g, k)[..., o]))
+    elif case == "blocks_of_64":
         sc = synth.config1(plane_dist="uniform", n=9000)
     elif case == "headline_shape_64":
         sc = synth.config2(plane_dist="uniform", n=6000)
@@ -240,6 +268,14 @@ def test_deform_backward_matches_oracle(dev, case):
     gout = {k: (v * ~flag).astype(np.float32).astype(np.float64) for k, v in gout.items()}
     gpu = _gpu_deform_backward(sc, t, gout)
     ref = og.deform_grads(g, sc.planes, sc.mlp, t, gout)
+    # a mean within binary32 rounding of a plane-cell boundary may fall in
+    # either cell on the two sides: the bilinear slopes (its position
+    # gradient) jump there, while every plane-cell gradient is continuous
+    edge = _cell_edge_flags(g.means, sc.planes)
+    log(f"[deform bwd] {case}: {int(edge.sum())} of {g.n} means within rounding of a cell boundary")
+    assert edge.mean() < 0.01
+    gpu["means"] = np.where(edge[None, :], 0.0, gpu["means"])
+    ref["means"] = np.where(edge[None, :], 0.0, ref["means"])
     _deform_compare(gpu, ref, case, 1e-4)
 
 
