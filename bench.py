@@ -5,10 +5,12 @@
 A step is one frame of the whole hot path: the HexPlane deformation of all
 Gaussians at timestamp t (g4d_deform) followed by the tile render through
 one camera (g4d_render), inputs resident in HBM, image left on the device.
-The reported rate runs the frames with --in-flight (default 3) frames in
+The reported rate runs the frames with --in-flight (default 4) frames in
 flight: frame k goes to slot k % m, each slot with its own stream, splat
 buffer, workspace and image (as serving slots do); the one-frame-at-a-time
-rate and the rates at 1-4 frames in flight are reported beside it.
+rate and the rates at 1, 2, 3, 4, 6 and 8 frames in flight are reported
+beside it.  The scene is stored once, before timing, in the Morton order of
+its means (--layout morton; --layout index keeps the generated order).
 Workload: 100k Gaussians on a noisy sphere shell (SH degree 3), planes at
 spatial 64/128 and temporal 25 with 32 features, MLP 64-64-10, 800x800,
 frames cycling through 20 ring cameras x 20 timestamps.
@@ -134,14 +136,17 @@ def cpu_baseline(sc, frames, n_frames: int, single_frames: int = 1):
 
 
 def serving_bench(seconds: float, rate: float, budget_gb: float, slots: int, warm_s: float = 2.0,
-                  sat_requests: int = 2000, tight_budget_gb: float = 2.0, tight_s: float = 10.0):
+                  sat_requests: int = 2000, tight_budget_gb: float = 2.0, tight_s: float = 10.0,
+                  layout: str = "morton"):
     """Poisson requests over three resident scenes (50k and 150k Gaussians
     from the cube generator, 300k from the box-and-cluster generator), each
     picking a scene, one of 20 ring cameras, t ~ U[0, 1] and a frame size
     from {400x400, 800x800, 1352x1014}.  Served with continuous batching,
     then the same trace through the plain path (one request at a time, no
     batching, no graphs).  Each path then takes the first `sat_requests`
-    requests of the trace back to back (closed loop) for its peak rate."""
+    requests of the trace back to back (closed loop) for its peak rate.
+    With layout="morton" each scene is stored in the Morton order of its
+    means before it is added (the same one-time step as the frame benchmark's)."""
     import torch
     from paper_2310_08528_amd import g4d, synth
     dev = "cuda:0"
@@ -153,6 +158,12 @@ def serving_bench(seconds: float, rate: float, budget_gb: float, slots: int, war
     trace = synth.poisson_arrivals(rate, warm_s + seconds, len(scenes), 20, res, seed=5)
     dev_scenes = [(g4d.DeviceGaussians(g, dev), g4d.DevicePlanes(p, dev), g4d.DeviceMLP(m, dev))
                   for (g, p, m, _) in scenes]
+    if layout == "morton":
+        for (G_, _, _), (_, p, _, _) in zip(dev_scenes, scenes):
+            ws_ = g4d.RenderWorkspace(G_.n, 16, 16, 4096, dev)
+            g4d.store_in_order(G_, g4d.spatial_order(G_, p.bmin, p.bmax, ws_))
+            del ws_
+        torch.cuda.synchronize()
 
     def run(slots_, graphs, batch, budget=budget_gb, dur=seconds):
         srv = g4d.Server(int(budget * (1 << 30)), max_slots=slots_, use_graphs=graphs, batch_deform=batch,
@@ -211,7 +222,7 @@ def serving_bench(seconds: float, rate: float, budget_gb: float, slots: int, war
     out = {"workload": f"Poisson {rate:.0f}/s for {seconds:.0f} s (+{warm_s:.0f} s warm-up), 3 resident scenes "
                        "(50k, 150k, 300k), frames 400x400 / 800x800 / 1352x1014",
            "served": {k: served[k] for k in keep}, "plain": {k: plain[k] for k in keep},
-           "slots": slots, "hbm_budget_gb": budget_gb,
+           "slots": slots, "hbm_budget_gb": budget_gb, "layout": layout,
            "peak_request_bytes": int(served["peak_bytes"])}
     if tight is not None:
         out["served_tight_budget"] = {"hbm_budget_gb": tight_budget_gb, "seconds": tight_s,
@@ -529,7 +540,7 @@ def main():
                          "permutation before anything is timed) or as generated")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (for scaling HBM byte counters)")
-    ap.add_argument("--in-flight", type=int, default=3,
+    ap.add_argument("--in-flight", type=int, default=4,
                     help="frames in flight for the reported throughput (1 = one frame at a time)")
     ap.add_argument("--extra", action="store_true",
                     help="also time the large configuration (FP32 and BF16 MLP) and a sweep over N")
@@ -668,7 +679,7 @@ def main():
     # ---- the same K frames with several in flight: frame k runs (deform,
     # then render) on slot k % m, each slot with its own stream, splat
     # buffer, workspace and image, as m serving slots would
-    m_max = max(4, args.in_flight)
+    m_max = max(8, args.in_flight)
     slot_S, slot_W, slot_I, slot_ws, keep = [bS], [bW], [ip], [ws], []
     for _ in range(m_max - 1):
         S_ = g4d.DeviceSplats(G.n, G.sh_degree, G.sh, dev)
@@ -686,6 +697,9 @@ def main():
     slot_sp = [sp] + [x.cuda_stream for x in slot_streams]
 
     def in_flight(m, n_frames, k0):
+        """Enqueue n_frames frames over m slots; returns the host time the
+        enqueueing took."""
+        t_host = time.perf_counter()
         for k in range(n_frames):
             b = k % m
             ci, t = frames[(k0 + k) % len(frames)]
@@ -693,19 +707,20 @@ def main():
             r2 = lib.g4d_render(slot_S[b], bC[ci], slot_W[b], slot_I[b], None, None, slot_sp[b])
             if r1 or r2:
                 raise g4d.G4DError(r1 or r2, "bench frames in flight")
+        return time.perf_counter() - t_host
 
     flight = {}
-    for m in sorted({1, 2, 3, 4, args.in_flight}):
+    for m in sorted({1, 2, 3, 4, 6, 8, args.in_flight}):
         in_flight(m, args.warmup, 0)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        in_flight(m, K, args.warmup)
+        host_s = in_flight(m, K, args.warmup)
         torch.cuda.synchronize()
         flight[m] = time.perf_counter() - t0
         for w_ in slot_ws[:m]:
             st = g4d.read_status(w_)
             assert st.overflow == 0 and st.sort_error == 0
-        log(f"{m} in flight: {K / flight[m]:.1f} frames/s")
+        log(f"{m} in flight: {K / flight[m]:.1f} frames/s (host enqueue {1e6 * host_s / K:.1f} us per frame)")
     wall_pipe = flight[args.in_flight]
     log("stage breakdown")
     # ---- per-stage breakdown (separate pass with events at every boundary)
@@ -786,7 +801,8 @@ def main():
                           "how": "one frame at a time on one stream (deform, then render)"}}
     log("stages done")
     if not args.no_serve:
-        out["serving"] = serving_bench(args.serve_seconds, args.serve_rate, args.serve_budget_gb, args.serve_slots)
+        out["serving"] = serving_bench(args.serve_seconds, args.serve_rate, args.serve_budget_gb, args.serve_slots,
+                                       layout=args.layout)
     # the training direction on its own workload (a few seconds; not part of `value`)
     log("training iteration")
     out["training"] = time_training_step(200, 20)

@@ -26,11 +26,15 @@
 // A block whose Gaussians are spatially close (a set stored in spatial order)
 // has small windows; a plane whose window does not fit scatters straight to
 // global memory.
-// W1 is read from global memory (L1/L2-resident: every block reads it); the
-// head weights, their biases and the per-row gradient pointers are staged in
-// LDS once per block (the heads are selected by a runtime row index, which
-// in the inner loops would be a dependent kernel-argument load per step);
-// f_h, h, the deltas and dz live in LDS.
+// The decoder products of a 64-Gaussian block (h, the head outputs, dz,
+// dW2, dW1 and df_h: 64 x 64 x 64 at the headline sizes) run on 16x16x4 FP32
+// MFMA tiles with operands in LDS, except W1, whose fragments each wave loads
+// from global memory (L2-resident: every block reads it) into registers ahead
+// of the phase that uses them.  Blocks of 16 Gaussians (small sets) use FMA
+// loops.  The head weights, their biases and the per-row gradient pointers
+// are staged in LDS once per block (the heads are selected by a runtime row
+// index, which in the inner loops would be a dependent kernel-argument load
+// per step); f_h, h, the deltas and dz live in LDS.
 #include "g4d_internal.h"
 
 #include <vector>
@@ -64,6 +68,45 @@ struct BwdJob {
 
 constexpr size_t kLdsMax = 160 * 1024;   // LDS per CU (and per block) on gfx950
 
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+// Row stride (floats) of an LDS matrix read by 16x16x4 MFMA fragments.  A
+// fragment read touches 16 consecutive rows at one column per k-group
+// (address row*ld + k) or, read transposed, 4 rows of 16 consecutive columns
+// (k*ld + col); a stride whose residue mod 64 is 12, 20, ..., 52 makes the
+// first conflict-free over the 64 banks and the second at most two-way.
+__host__ __device__ constexpr int mfma_ld(int x) {
+    int ld = x + 1;
+    while ((ld & 7) != 4 || (ld & 63) == 4 || (ld & 63) == 60) ++ld;
+    return ld;
+}
+
+// LDS layout of a block, shared by the kernel and the launch:
+//   s_fh [gb][fh] | s_dm [gb][3] | s_h [gb][hh] | s_dz [gb][hh] | s_dd [gb][ds] | s_w2 [rp][hh] | s_b2 [rp]
+// rp: head rows padded to whole 16-row tiles (zero rows).  64-Gaussian
+// blocks run the decoder on MFMA with padded strides; 16-Gaussian blocks use
+// FMA loops with odd strides.
+struct BwdLds {
+    int fh, hh, ds, rp;
+    int o_dm, o_h, o_dz, o_dd, o_w2, o_b2, total;
+};
+__host__ __device__ inline BwdLds bwd_lds(int gb, int K, int HID, int rows) {
+    BwdLds b{};
+    b.rp = (rows + 15) & ~15;
+    const bool mf = gb == 64;
+    b.fh = mf ? mfma_ld(K) : K + 1;
+    b.hh = mf ? mfma_ld(HID) : HID + 1;
+    b.ds = mf ? mfma_ld(b.rp) : 65;
+    b.o_dm = gb * b.fh;
+    b.o_h = b.o_dm + gb * 3;
+    b.o_dz = b.o_h + gb * b.hh;
+    b.o_dd = b.o_dz + gb * b.hh;
+    b.o_w2 = b.o_dd + gb * b.ds;
+    b.o_b2 = b.o_w2 + b.rp * b.hh;
+    b.total = b.o_b2 + b.rp;
+    return b;
+}
+
 __device__ constexpr int axis_a(int p) { return p == 2 ? 1 : (p == 5 ? 2 : (p == 4 ? 1 : 0)); }
 __device__ constexpr int axis_b(int p) { return p == 0 ? 1 : (p == 1 || p == 2 ? 2 : 3); }
 
@@ -94,27 +137,31 @@ __device__ __forceinline__ bool head_of(const BwdJob &J, int r, int &h, int &k) 
 template <int F, int L, int HID, int GB>
 __global__ __launch_bounds__(kThreads) void k_deform_bwd(BwdJob J, int rows) {
     constexpr int K = F * L;
-    constexpr int FH = K + 1, HH = HID + 1, DS = 65;
+    constexpr bool kMfma = GB == 64;
+    static_assert(!kMfma || (K % 16 == 0 && HID % 16 == 0), "MFMA tiles need 16-multiples");
+    constexpr int FH = kMfma ? mfma_ld(K) : K + 1, HH = kMfma ? mfma_ld(HID) : HID + 1;
+    const BwdLds lay = bwd_lds(GB, K, HID, rows);
+    const int DS = lay.ds, RP = lay.rp;
     extern __shared__ __attribute__((aligned(16))) float smem[];
-    float *s_fh = smem;                  // [GB][K+1]: f_h, later df_h
-    float *s_dm = s_fh + GB * FH;       // [GB][3]: dL/d canonical mean
-    float *s_h = s_dm + GB * 3;         // [GB][HID+1]: h (after ReLU)
-    float *s_dz = s_h + GB * HH;        // [GB][HID+1]: dL/d(pre-activation)
-    float *s_dd = s_dz + GB * HH;       // [GB][65]: head outputs, then their gradients
-    float *s_w2 = s_dd + GB * DS;       // [rows][HID+1]: head weights
-    float *s_b2 = s_w2 + rows * HH;      // [rows]
+    float *s_fh = smem;                  // [GB][FH]: f_h, later df_h
+    float *s_dm = smem + lay.o_dm;       // [GB][3]: dL/d canonical mean
+    float *s_h = smem + lay.o_h;         // [GB][HH]: h (after ReLU)
+    float *s_dz = smem + lay.o_dz;       // [GB][HH]: dL/d(pre-activation)
+    float *s_dd = smem + lay.o_dd;       // [GB][DS]: head outputs, then their gradients
+    float *s_w2 = smem + lay.o_w2;       // [RP][HH]: head weights (zero padding rows)
+    float *s_b2 = smem + lay.o_b2;       // [RP]
     // the plane-cell windows of the encoder backward reuse everything from
     // s_h on (dead once df_h is computed)
     float *s_win = s_h;
-    const int win_cap = 2 * GB * HH + GB * DS + rows * HH + rows;
+    const int win_cap = lay.total - lay.o_h;
     __shared__ float *s_dw[64];          // gradient row of head row r (null: padding)
     __shared__ float *s_db[64];
     const int tid = threadIdx.x;
     const int g0 = blockIdx.x * GB;
     const int n = J.n;
-    if (tid < rows) {
+    if (tid < RP) {
         int hq, k;
-        if (head_of(J, tid, hq, k)) {
+        if (tid < rows && head_of(J, tid, hq, k)) {
             s_dw[tid] = J.d_hw[hq] + (size_t)k * HID;
             s_db[tid] = J.d_hb[hq] + k;
             s_b2[tid] = J.hb[hq][k];
@@ -124,10 +171,26 @@ __global__ __launch_bounds__(kThreads) void k_deform_bwd(BwdJob J, int rows) {
             s_b2[tid] = 0.0f;
         }
     }
-    for (int idx = tid; idx < rows * HID; idx += kThreads) {
+    for (int idx = tid; idx < RP * HID; idx += kThreads) {
         const int r = idx / HID, j = idx - r * HID;
         int hq, k;
-        s_w2[r * HH + j] = head_of(J, r, hq, k) ? J.hw[hq][(size_t)k * HID + j] : 0.0f;
+        s_w2[r * HH + j] = r < rows && head_of(J, r, hq, k) ? J.hw[hq][(size_t)k * HID + j] : 0.0f;
+    }
+    const int wave_u = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+    const int lrow = lane & 15, lk = lane >> 4;     // MFMA fragment: row / column 0..15, k group 0..3
+    // W1 fragments of h = W1 f_h (wave w: output columns of tiles w, w + 4):
+    // lane (lrow, lk) holds W1[c*16 + lrow][4 kk + lk].  Loaded before the
+    // encoder so that their latency hides under its gathers.
+    constexpr int NC1 = kMfma ? (HID / 16 + 3) / 4 : 0;
+    float w1f[NC1 > 0 ? NC1 : 1][kMfma ? K / 4 : 1];
+    if constexpr (kMfma) {
+#pragma unroll
+        for (int ci = 0; ci < NC1; ++ci) {
+            const int c = wave_u + 4 * ci;
+#pragma unroll
+            for (int kk = 0; kk < K / 4; ++kk)
+                w1f[ci][kk] = c < HID / 16 ? J.w1[(size_t)(c * 16 + lrow) * K + kk * 4 + lk] : 0.0f;
+        }
     }
 
     // ---- A. encoder (as in the forward)
@@ -174,17 +237,34 @@ __global__ __launch_bounds__(kThreads) void k_deform_bwd(BwdJob J, int rows) {
         }
     }
     __syncthreads();
-    // ---- B. h = ReLU(W1 f_h + b1).  With 64 Gaussians per block a wave owns
-    // whole rows of W1 (lane = Gaussian), so a row is wave-uniform and its
-    // weights come through scalar loads; with fewer, Gaussian fastest (a
-    // weight is one broadcast vector load)
-    const int wave_u = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-    if constexpr (GB == 64) {
-        for (int j = wave_u; j < HID; j += kThreads / 64) {
-            const float *w = J.w1 + (size_t)j * K;
-            float acc = J.b1[j];
-            for (int i = 0; i < K; ++i) acc += w[i] * s_fh[lane * FH + i];
-            s_h[lane * HH + j] = fmaxf(acc, 0.0f);
+    // ---- B. h = ReLU(W1 f_h + b1).  64-Gaussian blocks: 16x16x4 MFMA tiles
+    // with the forward kernel's operands and k order (per tile the same chain
+    // over k = 4 kk + lk), so the recomputed h rounds as the forward's does.
+    // 16-Gaussian blocks: FMA loops, Gaussian fastest (a weight is one
+    // broadcast load).
+    if constexpr (kMfma) {
+#pragma unroll
+        for (int ci = 0; ci < NC1; ++ci) {
+            const int c = wave_u + 4 * ci;
+            if (c < HID / 16) {
+                float4_t acc[4];
+#pragma unroll
+                for (int rt = 0; rt < 4; ++rt) acc[rt] = float4_t{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int kk = 0; kk < K / 4; ++kk) {
+#pragma unroll
+                    for (int rt = 0; rt < 4; ++rt) {
+                        const float a = s_fh[(rt * 16 + lrow) * FH + kk * 4 + lk];
+                        acc[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, w1f[ci][kk], acc[rt], 0, 0, 0);
+                    }
+                }
+                const int col = c * 16 + lrow;
+                const float bias = J.b1[col];
+#pragma unroll
+                for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) s_h[(rt * 16 + 4 * lk + i) * HH + col] = fmaxf(acc[rt][i] + bias, 0.0f);
+            }
         }
     } else {
         for (int idx = tid; idx < GB * HID; idx += kThreads) {
@@ -195,14 +275,44 @@ __global__ __launch_bounds__(kThreads) void k_deform_bwd(BwdJob J, int rows) {
             s_h[g * HH + j] = fmaxf(acc, 0.0f);
         }
     }
+    // W1 fragments of df_h = W1^T dz (wave w: df_h columns of tiles w, w + 4):
+    // lane (lrow, lk) holds W1[4 kk + lk][c*16 + lrow]; in flight until the
+    // last decoder phase
+    constexpr int NC7 = kMfma ? (K / 16 + 3) / 4 : 0;
+    float w1g[NC7 > 0 ? NC7 : 1][kMfma ? HID / 4 : 1];
+    if constexpr (kMfma) {
+#pragma unroll
+        for (int ci = 0; ci < NC7; ++ci) {
+            const int c = wave_u + 4 * ci;
+#pragma unroll
+            for (int kk = 0; kk < HID / 4; ++kk)
+                w1g[ci][kk] = c < K / 16 ? J.w1[(size_t)(kk * 4 + lk) * K + c * 16 + lrow] : 0.0f;
+        }
+    }
     __syncthreads();
-    // ---- C. head outputs delta = W2 h + b2 (padding rows: zero weights)
-    for (int idx = tid; idx < GB * rows; idx += kThreads) {
-        const int g = idx % GB, r = idx / GB;
-        float acc = s_b2[r];
-        const float *w = s_w2 + r * HH;
-        for (int j = 0; j < HID; ++j) acc += w[j] * s_h[g * HH + j];
-        s_dd[g * DS + r] = acc;
+    // ---- C. head outputs delta = W2 h + b2 (padding rows: zero weights);
+    // MFMA tiles as in the forward (wave w: Gaussians 16w..16w+15)
+    if constexpr (kMfma) {
+        const int row0 = wave_u * 16;
+        for (int c = 0; c < RP / 16; ++c) {
+            float4_t acc = float4_t{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 8
+            for (int kk = 0; kk < HID / 4; ++kk) {
+                const float a = s_h[(row0 + lrow) * HH + kk * 4 + lk];
+                const float b = s_w2[(c * 16 + lrow) * HH + kk * 4 + lk];
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) s_dd[(row0 + 4 * lk + i) * DS + c * 16 + lrow] = acc[i] + s_b2[c * 16 + lrow];
+        }
+    } else {
+        for (int idx = tid; idx < GB * rows; idx += kThreads) {
+            const int g = idx % GB, r = idx / GB;
+            float acc = s_b2[r];
+            const float *w = s_w2 + r * HH;
+            for (int j = 0; j < HID; ++j) acc += w[j] * s_h[g * HH + j];
+            s_dd[g * DS + r] = acc;
+        }
     }
     __syncthreads();
     // ---- Eq. 8 + activations, backward (one Gaussian per thread of wave 0);
@@ -251,9 +361,9 @@ __global__ __launch_bounds__(kThreads) void k_deform_bwd(BwdJob J, int rows) {
             const float dl = J.g_opac[g] * sg * (1.0f - sg);
             J.d_opac[g] = dl;
             if (J.hrows[4]) dd[10 + nc] = dl;
-            for (int r = 10 + nc + J.hrows[4]; r < rows; ++r) dd[r] = 0.0f;
+            for (int r = 10 + nc + J.hrows[4]; r < RP; ++r) dd[r] = 0.0f;
         } else {
-            for (int r = 0; r < rows; ++r) dd[r] = 0.0f;
+            for (int r = 0; r < RP; ++r) dd[r] = 0.0f;
             for (int k = 0; k < 3; ++k) s_dm[gl * 3 + k] = 0.0f;
         }
     } else if (J.d_sh) {
@@ -263,46 +373,137 @@ __global__ __launch_bounds__(kThreads) void k_deform_bwd(BwdJob J, int rows) {
         }
     }
     __syncthreads();
-    // ---- heads backward: dz = (W2^T ddelta) * [h > 0]
-    for (int idx = tid; idx < GB * HID; idx += kThreads) {
-        const int g = idx % GB, j = idx / GB;
-        float acc = 0.0f;
-        for (int r = 0; r < rows; ++r) acc += s_w2[r * HH + j] * s_dd[g * DS + r];
-        s_dz[g * HH + j] = s_h[g * HH + j] > 0.0f ? acc : 0.0f;
-    }
-    // dW2 += ddelta h^T, db2 += ddelta (sums over the block's Gaussians)
-    for (int idx = tid; idx < rows * (HID + 1); idx += kThreads) {
-        const int r = idx / (HID + 1), j = idx % (HID + 1);
-        if (!s_dw[r]) continue;
-        float acc = 0.0f;
-        if (j < HID) {
-            for (int g = 0; g < GB; ++g) acc += s_dd[g * DS + r] * s_h[g * HH + j];
-            if (acc != 0.0f) atomicAdd(s_dw[r] + j, acc);
-        } else {
-            for (int g = 0; g < GB; ++g) acc += s_dd[g * DS + r];
-            if (acc != 0.0f) atomicAdd(s_db[r], acc);
+    // ---- heads backward: dz = (W2^T ddelta) * [h > 0];
+    // dW2 += ddelta^T h, db2 += ddelta (sums over the block's Gaussians)
+    if constexpr (kMfma) {
+        {
+            const int row0 = wave_u * 16;
+            const int kr = (rows + 3) >> 2;          // k steps over the head rows (zero padded)
+            float4_t acc[HID / 16];
+#pragma unroll
+            for (int c = 0; c < HID / 16; ++c) acc[c] = float4_t{0.0f, 0.0f, 0.0f, 0.0f};
+            for (int kk = 0; kk < kr; ++kk) {
+                const float a = s_dd[(row0 + lrow) * DS + kk * 4 + lk];
+#pragma unroll
+                for (int c = 0; c < HID / 16; ++c) {
+                    const float b = s_w2[(kk * 4 + lk) * HH + c * 16 + lrow];
+                    acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[c], 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < HID / 16; ++c)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int o = (row0 + 4 * lk + i) * HH + c * 16 + lrow;
+                    s_dz[o] = s_h[o] > 0.0f ? acc[c][i] : 0.0f;
+                }
         }
-    }
-    __syncthreads();
-    // ---- feature merger: dW1 += dz f_h^T, db1 += dz
-    for (int idx = tid; idx < HID * (K + 1); idx += kThreads) {
-        const int j = idx / (K + 1), i = idx % (K + 1);
-        float acc = 0.0f;
-        if (i < K) {
-            for (int g = 0; g < GB; ++g) acc += s_dz[g * HH + j] * s_fh[g * FH + i];
-            if (acc != 0.0f) atomicAdd(&J.d_w1[(size_t)j * K + i], acc);
-        } else {
-            for (int g = 0; g < GB; ++g) acc += s_dz[g * HH + j];
-            if (acc != 0.0f) atomicAdd(&J.d_b1[j], acc);
+        const int ntile = (RP / 16) * (HID / 16);
+        for (int t = wave_u; t < ntile; t += 4) {
+            const int rt = t / (HID / 16), ct = t - rt * (HID / 16);
+            float4_t acc = float4_t{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 8
+            for (int kk = 0; kk < GB / 4; ++kk) {
+                const float a = s_dd[(kk * 4 + lk) * DS + rt * 16 + lrow];
+                const float b = s_h[(kk * 4 + lk) * HH + ct * 16 + lrow];
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = rt * 16 + 4 * lk + i;
+                if (r < rows && acc[i] != 0.0f) atomicAdd(s_dw[r] + ct * 16 + lrow, acc[i]);
+            }
         }
-    }
-    __syncthreads();
-    // df_h = W1^T dz (overwrites f_h); column i of W1 wave-uniform as above
-    if constexpr (GB == 64) {
-        for (int i = wave_u; i < K; i += kThreads / 64) {
+        if (tid < rows) {
             float acc = 0.0f;
-            for (int j = 0; j < HID; ++j) acc += J.w1[(size_t)j * K + i] * s_dz[lane * HH + j];
-            s_fh[lane * FH + i] = acc;
+            for (int g = 0; g < GB; ++g) acc += s_dd[g * DS + tid];
+            if (acc != 0.0f) atomicAdd(s_db[tid], acc);
+        }
+    } else {
+        for (int idx = tid; idx < GB * HID; idx += kThreads) {
+            const int g = idx % GB, j = idx / GB;
+            float acc = 0.0f;
+            for (int r = 0; r < rows; ++r) acc += s_w2[r * HH + j] * s_dd[g * DS + r];
+            s_dz[g * HH + j] = s_h[g * HH + j] > 0.0f ? acc : 0.0f;
+        }
+        for (int idx = tid; idx < rows * (HID + 1); idx += kThreads) {
+            const int r = idx / (HID + 1), j = idx % (HID + 1);
+            if (!s_dw[r]) continue;
+            float acc = 0.0f;
+            if (j < HID) {
+                for (int g = 0; g < GB; ++g) acc += s_dd[g * DS + r] * s_h[g * HH + j];
+                if (acc != 0.0f) atomicAdd(s_dw[r] + j, acc);
+            } else {
+                for (int g = 0; g < GB; ++g) acc += s_dd[g * DS + r];
+                if (acc != 0.0f) atomicAdd(s_db[r], acc);
+            }
+        }
+    }
+    __syncthreads();
+    // ---- feature merger: dW1 += dz^T f_h, db1 += dz
+    if constexpr (kMfma) {
+        constexpr int NI = K / 16;
+        for (int jt = wave_u; jt < HID / 16; jt += 4) {
+            float4_t acc[NI];
+#pragma unroll
+            for (int it = 0; it < NI; ++it) acc[it] = float4_t{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 4
+            for (int kk = 0; kk < GB / 4; ++kk) {
+                const float a = s_dz[(kk * 4 + lk) * HH + jt * 16 + lrow];
+#pragma unroll
+                for (int it = 0; it < NI; ++it) {
+                    const float b = s_fh[(kk * 4 + lk) * FH + it * 16 + lrow];
+                    acc[it] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[it], 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int it = 0; it < NI; ++it)
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (acc[it][i] != 0.0f)
+                        atomicAdd(&J.d_w1[(size_t)(jt * 16 + 4 * lk + i) * K + it * 16 + lrow], acc[it][i]);
+        }
+        if (tid < HID) {
+            float acc = 0.0f;
+            for (int g = 0; g < GB; ++g) acc += s_dz[g * HH + tid];
+            if (acc != 0.0f) atomicAdd(&J.d_b1[tid], acc);
+        }
+    } else {
+        for (int idx = tid; idx < HID * (K + 1); idx += kThreads) {
+            const int j = idx / (K + 1), i = idx % (K + 1);
+            float acc = 0.0f;
+            if (i < K) {
+                for (int g = 0; g < GB; ++g) acc += s_dz[g * HH + j] * s_fh[g * FH + i];
+                if (acc != 0.0f) atomicAdd(&J.d_w1[(size_t)j * K + i], acc);
+            } else {
+                for (int g = 0; g < GB; ++g) acc += s_dz[g * HH + j];
+                if (acc != 0.0f) atomicAdd(&J.d_b1[j], acc);
+            }
+        }
+    }
+    __syncthreads();
+    // df_h = W1^T dz (overwrites f_h)
+    if constexpr (kMfma) {
+#pragma unroll
+        for (int ci = 0; ci < NC7; ++ci) {
+            const int c = wave_u + 4 * ci;
+            if (c < K / 16) {
+                float4_t acc[4];
+#pragma unroll
+                for (int rt = 0; rt < 4; ++rt) acc[rt] = float4_t{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int kk = 0; kk < HID / 4; ++kk) {
+#pragma unroll
+                    for (int rt = 0; rt < 4; ++rt) {
+                        const float a = s_dz[(rt * 16 + lrow) * HH + kk * 4 + lk];
+                        acc[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, w1g[ci][kk], acc[rt], 0, 0, 0);
+                    }
+                }
+#pragma unroll
+                for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) s_fh[(rt * 16 + 4 * lk + i) * FH + c * 16 + lrow] = acc[rt][i];
+            }
         }
     } else {
         for (int idx = tid; idx < GB * K; idx += kThreads) {
@@ -546,10 +747,7 @@ const BwdEntry kBwdKernels[] = {
     G4D_BWD_ENTRY(32, 3, 64), G4D_BWD_ENTRY(32, 3, 128),
 };
 
-size_t bwd_smem(int gb, int K, int HID, int rows) {
-    return ((size_t)gb * (K + 1) + 2 * (size_t)gb * (HID + 1) + (size_t)gb * 65 + (size_t)gb * 3 +
-            (size_t)rows * (HID + 1) + rows) * 4;
-}
+size_t bwd_smem(int gb, int K, int HID, int rows) { return (size_t)bwd_lds(gb, K, HID, rows).total * 4; }
 
 }  // namespace
 

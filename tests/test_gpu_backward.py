@@ -188,16 +188,19 @@ def _deform_compare(gpu, ref, name, tol):
 
 
 def _cell_edge_flags(means, planes, rel=4.0 * 2.0 ** -24):
-    """Means whose grid coordinate g = (x - bmin) (R - 1) / (bmax - bmin),
-    along any axis at any scale, lies within rel x (R - 1) cells of an integer
-    (the binary32 evaluation's reach: two roundings of g)."""
+    """Means strictly inside the box whose grid coordinate
+    g = (x - bmin) (R - 1) / (bmax - bmin), along any axis at any scale, lies
+    within rel x (R - 1) cells of an integer (the binary32 evaluation's reach:
+    two roundings of g).  A mean on or beyond the border has no slope along
+    that axis on either side (the border clamp), so it is not flagged."""
     x = np.asarray(means, np.float64)
     flag = np.zeros(x.shape[1], bool)
     for res in planes.res:
         for k in range(3):
             r = res[k] - 1
+            inside = (x[k] > planes.bmin[k]) & (x[k] < planes.bmax[k])
             gk = (x[k] - planes.bmin[k]) * r / (planes.bmax[k] - planes.bmin[k])
-            flag |= np.abs(gk - np.rint(gk)) <= rel * r + 1e-12
+            flag |= inside & (np.abs(gk - np.rint(gk)) <= rel * r + 1e-12)
     return flag
 
 
