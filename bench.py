@@ -231,9 +231,11 @@ def serving_bench(seconds: float, rate: float, budget_gb: float, slots: int, war
     return out
 
 
-def time_scene(sc, precision, steps, warmup, n_frames=None):
+def time_scene(sc, precision, steps, warmup, n_frames=None, layout="morton"):
     """frames/s and per-stage ms of deform + render over a scene's frame
-    sequence (camera k mod cameras, timestamp k mod timestamps)."""
+    sequence (camera k mod cameras, timestamp k mod timestamps), one frame at
+    a time; with layout="morton" the scene is first stored in the Morton
+    order of its means."""
     import torch
     from paper_2310_08528_amd import g4d
     dev = "cuda:0"
@@ -250,6 +252,8 @@ def time_scene(sc, precision, steps, warmup, n_frames=None):
     img = torch.empty((3, H, W), dtype=torch.float32, device=dev)
     capacity = 64 * G.n + 4096
     ws = g4d.RenderWorkspace(G.n, W, H, capacity, dev)
+    if layout == "morton":
+        g4d.store_in_order(G, g4d.spatial_order(G, sc.planes.bmin, sc.planes.bmax, ws))
     kmax = 0
     for (ci, t) in frames:
         g4d.deform(G, P, M, t, S)
@@ -295,10 +299,11 @@ def time_scene(sc, precision, steps, warmup, n_frames=None):
             "stages_ms": {k: round(v, 4) for k, v in stages.items()}, "instances_max": kmax}
 
 
-def time_composition(steps, warmup, n_each=50_000):
+def time_composition(steps, warmup, n_each=50_000, layout="morton"):
     """frames/s of the composition workload: two scenes (two deform kernel
     variants, so two launches) placed into one set by g4d_deform_compose,
-    then one render at 800x800."""
+    then one render at 800x800; with layout="morton" each scene is first
+    stored in the Morton order of its means."""
     import torch
     from paper_2310_08528_amd import g4d, synth
     dev = "cuda:0"
@@ -307,6 +312,11 @@ def time_composition(steps, warmup, n_each=50_000):
     dev_items = [(g4d.DeviceGaussians(g, dev), g4d.DevicePlanes(pl, dev), g4d.DeviceMLP(m, dev), g4d.placement(*p))
                  for g, pl, m, p in items]
     n = sum(it[0].n for it in dev_items)
+    if layout == "morton":
+        for (G_, _, _, _), (_, pl, _, _) in zip(dev_items, items):
+            ws_ = g4d.RenderWorkspace(G_.n, 16, 16, 4096, dev)
+            g4d.store_in_order(G_, g4d.spatial_order(G_, pl.bmin, pl.bmax, ws_))
+            del ws_
     S = g4d.DeviceSplats(n, 3, None, dev)
     cams = [g4d.camera_struct(c) for c in cams_h]
     W, H = cams_h[0].width, cams_h[0].height
@@ -457,7 +467,7 @@ def time_training_step(steps, warmup, which="small", layout="index"):
                                 "ns_per_pair": round(rb_ms * 1e6 / max(evals, 1), 4)}}
 
 
-def extra_measurements(steps, warmup):
+def extra_measurements(steps, warmup, layout="morton"):
     """The large configuration (300k Gaussians, planes 64/128/256 x t150,
     MLP 96-128-10, 1352x1014) with the FP32 and the BF16-input MFMA MLP, the
     100k workload with the colour and opacity heads, the composition
@@ -468,20 +478,21 @@ def extra_measurements(steps, warmup):
     sc4 = synth.config4()
     out["large"] = {"workload": "300k Gaussians (box + cluster, SH3), HexPlane 64/128/256 x t150 F32, "
                                 "MLP 96-128-10, 1352x1014, 20 ring cameras x 300 timestamps",
-                    "fp32_mlp": time_scene(sc4, g4d.MLP_F32, steps, warmup, n_frames=300),
-                    "bf16_mlp": time_scene(sc4, g4d.MLP_BF16, steps, warmup, n_frames=300)}
+                    "layout": layout,
+                    "fp32_mlp": time_scene(sc4, g4d.MLP_F32, steps, warmup, n_frames=300, layout=layout),
+                    "bf16_mlp": time_scene(sc4, g4d.MLP_BF16, steps, warmup, n_frames=300, layout=layout)}
     del sc4
     log("extra: colour and opacity heads")
     out["colour_opacity_heads"] = {
         "workload": "100k Gaussians, SH3, the 100k configuration's field; decoder with the colour "
                     "(48 rows) and opacity heads, 800x800",
-        "fp32_mlp": time_scene(synth.config2(colour_opacity=True), g4d.MLP_F32, steps, warmup)}
+        "fp32_mlp": time_scene(synth.config2(colour_opacity=True), g4d.MLP_F32, steps, warmup, layout=layout)}
     log("extra: composition")
-    out["composition"] = time_composition(steps, warmup)
+    out["composition"] = time_composition(steps, warmup, layout=layout)
     out["sweep_n"] = {}
     for n in (10_000, 30_000, 100_000, 300_000):
         log(f"extra: N = {n}")
-        out["sweep_n"][str(n)] = time_scene(synth.config2(n=n), g4d.MLP_F32, steps, warmup)
+        out["sweep_n"][str(n)] = time_scene(synth.config2(n=n), g4d.MLP_F32, steps, warmup, layout=layout)
     return out
 
 
@@ -809,7 +820,7 @@ def main():
     log("training iteration, 100k Gaussians")
     out["training_100k"] = time_training_step(50, 5, "100k", args.layout)
     if args.extra:
-        out["extra"] = extra_measurements(min(K, 200), 20)
+        out["extra"] = extra_measurements(min(K, 200), 20, args.layout)
     if not args.no_cpu_baseline:
         log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(sc, frames, args.cpu_frames, args.cpu_single_frames)

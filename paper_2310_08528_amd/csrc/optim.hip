@@ -7,7 +7,8 @@
 // loss += weight * tv, and dtv/dR[i, j] = 2/N_a (2 R[i,j] - R[i,j-1] -
 // R[i,j+1]) + 2/N_b (...) with the missing neighbours left out at the edges
 // (N_a = n_b (n_a - 1) F, N_b = (n_b - 1) n_a F differences).  One thread per
-// cell; each block reduces its loss terms and adds them with one atomic.
+// cell (32-bit indices: a plane holds at most 2^31 values; F = 16 or 32 is
+// a shift); each block reduces its loss terms and adds them with one atomic.
 //
 // Adam (Kingma & Ba): m <- b1 m + (1 - b1) g, v <- b2 v + (1 - b2) g^2,
 // p <- p - lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps); up to 64
@@ -29,28 +30,30 @@ __global__ __launch_bounds__(256) void k_tv(TvPlanes P, float *__restrict__ loss
     __shared__ float s_part[4];
     const int p = blockIdx.y;
     const int na = P.na[p], nb = P.nb[p], F = P.feat;
+    const int lf = F == 32 ? 5 : 4;
     const float *R = P.plane[p];
     float *G = P.grad[p];
-    const size_t cells = (size_t)na * nb * F;
+    const uint32_t cells = (uint32_t)(na * nb) << lf, row = (uint32_t)na << lf;
     const float ia = 1.0f / (float)((size_t)nb * (na - 1) * F);
     const float ib = 1.0f / (float)((size_t)(nb - 1) * na * F);
     float acc = 0.0f;
-    for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (size_t)gridDim.x * blockDim.x) {
-        const int j = (int)((c / F) % na), i = (int)(c / ((size_t)F * na));
+    for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += gridDim.x * blockDim.x) {
+        const uint32_t cell = c >> lf;
+        const uint32_t i = cell / (uint32_t)na, j = cell - i * (uint32_t)na;
         const float r = R[c];
         float g = 0.0f;
-        if (j + 1 < na) {
+        if (j + 1 < (uint32_t)na) {
             const float d = R[c + F] - r;
             acc += d * d * ia;
             g -= 2.0f * d * ia;
         }
         if (j > 0) g += 2.0f * (r - R[c - F]) * ia;
-        if (i + 1 < nb) {
-            const float d = R[c + (size_t)na * F] - r;
+        if (i + 1 < (uint32_t)nb) {
+            const float d = R[c + row] - r;
             acc += d * d * ib;
             g -= 2.0f * d * ib;
         }
-        if (i > 0) g += 2.0f * (r - R[c - (size_t)na * F]) * ib;
+        if (i > 0) g += 2.0f * (r - R[c - row]) * ib;
         if (G) G[c] += P.weight * g;
     }
 #pragma unroll
@@ -107,7 +110,7 @@ extern "C" g4d_status g4d_tv_loss(const g4d_planes *P, float weight, float *loss
             T.grad[q] = grad ? grad->plane[l][p] : nullptr;
             T.na[q] = P->res[l][ax[p][0]];
             T.nb[q] = P->res[l][ax[p][1]];
-            if (T.na[q] < 2 || T.nb[q] < 2) return G4D_EINVAL;
+            if (T.na[q] < 2 || T.nb[q] < 2 || (size_t)T.na[q] * T.nb[q] * P->feat > 0x7fffffffu) return G4D_EINVAL;
             max_cells = std::max(max_cells, (size_t)T.na[q] * T.nb[q] * P->feat);
         }
     T.n_planes = P->n_scales * 6;
@@ -115,8 +118,9 @@ extern "C" g4d_status g4d_tv_loss(const g4d_planes *P, float weight, float *loss
     T.weight = weight;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     if (loss) hipLaunchKernelGGL(g4d::k_zero_scalar, dim3(1), dim3(1), 0, s, loss);
-    // few blocks per plane: the loss adds one atomic per block
-    const unsigned bx = (unsigned)std::min<size_t>((max_cells + 255) / 256, 32);
+    // up to 128 blocks per plane (about one pass at the largest planes); the
+    // loss adds one atomic per block
+    const unsigned bx = (unsigned)std::min<size_t>((max_cells + 255) / 256, 128);
     hipLaunchKernelGGL(g4d::k_tv, dim3(bx, (unsigned)T.n_planes), dim3(256), 0, s, T, loss);
     G4D_HIP_CHECK(hipGetLastError());
     return G4D_OK;

@@ -87,8 +87,11 @@ template <int CTRL>
 __device__ __forceinline__ float dpp(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
 }
-// Sum over each row of 16 lanes; every lane of the row receives it.
+// Sum over each row of 16 lanes; every lane of the row receives it.  The
+// adds stay adds (no contraction with a product that feeds them, which would
+// split each DPP add into a move and an FMA).
 __device__ __forceinline__ float row_sum(float v) {
+#pragma clang fp contract(off)
     v += dpp<0xb1>(v);    // quad_perm [1, 0, 3, 2]: lane ^ 1
     v += dpp<0x4e>(v);    // quad_perm [2, 3, 0, 1]: lane ^ 2
     v += dpp<0x141>(v);   // row_half_mirror: the other quad of the half-row
@@ -170,7 +173,10 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const uint4 *__restrict__ ord
             const int slot = (int)__popcll(km & lt);
             R[3 * slot] = A4;
             R[3 * slot + 1] = make_float4(B4.x, __log2f(B4.y), B4.z, B4.w);
-            R[3 * slot + 2] = make_float4(C1, __int_as_float(pos1), B4.y, 0.0f);
+            // 1/o by the hardware reciprocal and one Newton step (o in (0, 1))
+            float io = __builtin_amdgcn_rcpf(B4.y);
+            io = __builtin_fmaf(__builtin_fmaf(-B4.y, io, 1.0f), io, io);
+            R[3 * slot + 2] = make_float4(C1, __int_as_float(pos1), io, 0.0f);
             Sl[slot] = (uint32_t)lane;
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -188,34 +194,39 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const uint4 *__restrict__ ord
             float alpha = fminf(0.99f, raw);
             alpha = alpha < a_min ? 0.0f : alpha;
             const bool act = inside && pos <= last && alpha > 0.0f;
+            // an entry no pixel of the quadrant composites changes nothing
+            if (__builtin_amdgcn_ballot_w64(act) == 0) continue;
+            // branch-free body: a lane that does not composite this entry
+            // takes alpha = 0, for which 1/(1 - alpha) = 1 exactly and T, S
+            // and every gradient term stay unchanged (zero)
+            const float al = act ? alpha : 0.0f;
+            const float om = 1.0f - al;
+            // 1/(1 - alpha): hardware reciprocal and one Newton step
+            float r = __builtin_amdgcn_rcpf(om);
+            r = __builtin_fmaf(__builtin_fmaf(-om, r, 1.0f), r, r);
+            const float Ti = T * r;
+            const float aT = al * Ti;
             float v[kG2];
-#pragma unroll
-            for (int k = 0; k < kG2; ++k) v[k] = 0.0f;
-            if (act) {
-                const float om = 1.0f - alpha;
-                const float Ti = T / om;
-                const float aT = alpha * Ti;
-                v[5] = aT * g0;
-                v[6] = aT * g1;
-                v[7] = aT * g2;
-                const float cg = (R1.z * g0 + R1.w * g1) + R2.x * g2;
-                const float sg = (S0 * g0 + S1 * g1) + S2 * g2;
-                const float dal = Ti * (cg - sg) - tnbg / om;
-                S0 = alpha * R1.z + om * S0;
-                S1 = alpha * R1.w + om * S1;
-                S2 = alpha * R2.x + om * S2;
-                T = Ti;
-                if (!(raw > 0.99f)) {
-                    const float dpw = dal * alpha;
-                    v[8] = dal * (alpha / R2.z);                  // dalpha/do = exp(power)
-                    v[0] = dpw * (2.0f * R0.z * dx + R1.x * dy);  // d power / du = -A dx - B dy
-                    v[1] = dpw * (2.0f * R0.w * dy + R1.x * dx);  // d power / dv = -C dy - B dx
-                    v[2] = -0.5f * dpw * dx * dx;                 // d power / dA
-                    v[3] = -dpw * dx * dy;                        // d power / dB
-                    v[4] = -0.5f * dpw * dy * dy;                 // d power / dC
-                }
-            }
-            if (__builtin_amdgcn_ballot_w64(act) != 0) {
+            v[5] = aT * g0;
+            v[6] = aT * g1;
+            v[7] = aT * g2;
+            const float cg = (R1.z * g0 + R1.w * g1) + R2.x * g2;
+            const float sg = (S0 * g0 + S1 * g1) + S2 * g2;
+            const float dal = Ti * (cg - sg) - tnbg * r;
+            S0 = al * R1.z + om * S0;
+            S1 = al * R1.w + om * S1;
+            S2 = al * R2.x + om * S2;
+            T = Ti;
+            // a clamped alpha passes nothing to o or the power
+            const float dpw = raw > 0.99f ? 0.0f : dal * al;
+            v[8] = dpw * R2.z;                                    // dalpha/do = alpha/o
+            v[0] = dpw * __builtin_fmaf(2.0f * R0.z, dx, R1.x * dy);   // d power / du = -A dx - B dy
+            v[1] = dpw * __builtin_fmaf(2.0f * R0.w, dy, R1.x * dx);   // d power / dv = -C dy - B dx
+            const float hd = -0.5f * dpw, hx = hd * dx;
+            v[2] = hx * dx;                                       // d power / dA
+            v[3] = (hx + hx) * dy;                                // d power / dB
+            v[4] = (hd * dy) * dy;                                // d power / dC
+            {
                 float sum[kG2];
 #pragma unroll
                 for (int k = 0; k < kG2; ++k) sum[k] = row_sum(v[k]);
