@@ -74,20 +74,42 @@ struct AdamList {
     float b1, b2, eps, c1, c2;   // c1 = 1 / (1 - b1^t), c2 = 1 / (1 - b2^t)
 };
 
+__device__ __forceinline__ void adam_one(const AdamList &A, float lr, float &p, float &m, float &v, float g) {
+    const float mi = A.b1 * m + (1.0f - A.b1) * g;
+    const float vi = A.b2 * v + (1.0f - A.b2) * g * g;
+    m = mi;
+    v = vi;
+    p -= lr * (mi * A.c1) / (sqrtf(vi * A.c2) + A.eps);
+}
+
+// Four consecutive values per thread (16-byte accesses) when all four arrays
+// of the tensor are 16-byte aligned, the remainder (and unaligned tensors)
+// one value per thread.
 __global__ __launch_bounds__(256) void k_adam(AdamList A) {
     const int a = blockIdx.y;
     if (a >= A.n) return;
     float *p = A.param[a], *m = A.m[a], *v = A.v[a];
     const float *g = A.grad[a];
     const float lr = A.lr[a];
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < A.count[a]; i += gridDim.x * blockDim.x) {
-        const float gi = g[i];
-        const float mi = A.b1 * m[i] + (1.0f - A.b1) * gi;
-        const float vi = A.b2 * v[i] + (1.0f - A.b2) * gi * gi;
-        m[i] = mi;
-        v[i] = vi;
-        p[i] -= lr * (mi * A.c1) / (sqrtf(vi * A.c2) + A.eps);
+    const uint32_t count = A.count[a];
+    const bool vec = ((reinterpret_cast<uintptr_t>(p) | reinterpret_cast<uintptr_t>(m) |
+                       reinterpret_cast<uintptr_t>(v) | reinterpret_cast<uintptr_t>(g)) & 15u) == 0;
+    const uint32_t n4 = vec ? count / 4 : 0;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) {
+        float4 pp = reinterpret_cast<float4 *>(p)[i], mm = reinterpret_cast<float4 *>(m)[i];
+        float4 vv = reinterpret_cast<float4 *>(v)[i];
+        const float4 gg = reinterpret_cast<const float4 *>(g)[i];
+        adam_one(A, lr, pp.x, mm.x, vv.x, gg.x);
+        adam_one(A, lr, pp.y, mm.y, vv.y, gg.y);
+        adam_one(A, lr, pp.z, mm.z, vv.z, gg.z);
+        adam_one(A, lr, pp.w, mm.w, vv.w, gg.w);
+        reinterpret_cast<float4 *>(p)[i] = pp;
+        reinterpret_cast<float4 *>(m)[i] = mm;
+        reinterpret_cast<float4 *>(v)[i] = vv;
     }
+    for (uint32_t i = 4 * n4 + blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride)
+        adam_one(A, lr, p[i], m[i], v[i], g[i]);
 }
 
 __global__ void k_zero_scalar(float *p) { *p = 0.0f; }
@@ -145,7 +167,7 @@ extern "C" g4d_status g4d_adam_step(const g4d_adam_tensor *t, int32_t n, float b
     A.c1 = (float)(1.0 / (1.0 - std::pow((double)beta1, step)));
     A.c2 = (float)(1.0 / (1.0 - std::pow((double)beta2, step)));
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    const unsigned bx = (unsigned)std::max<uint32_t>(1, std::min<uint32_t>((most + 255) / 256, 256));
+    const unsigned bx = (unsigned)std::max<uint32_t>(1, std::min<uint32_t>((most / 4 + 255) / 256, 1024));
     hipLaunchKernelGGL(g4d::k_adam, dim3(bx, (unsigned)n), dim3(256), 0, s, A);
     G4D_HIP_CHECK(hipGetLastError());
     return G4D_OK;
