@@ -1192,7 +1192,7 @@ __global__ __launch_bounds__(1024) void k_tile_order(DevStatus *__restrict__ st,
 // method) and the kept entries they composite; without it the loop carries
 // none of that bookkeeping.
 
-constexpr int kBlendUnroll = 8;   // entries composited per step of the loop (power of two, <= 64)
+constexpr int kBlendUnroll = 4;   // entries composited per step of the loop (power of two, <= 64)
 
 template <bool TRACK>
 __global__ __launch_bounds__(kTilePixels) void k_blend(const uint4 *__restrict__ order,
