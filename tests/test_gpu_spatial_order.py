@@ -29,6 +29,7 @@ def _morton_order(means, bmin, bmax):
     for k in range(3):
         sc = np.float32(1024.0 / (float(bmax[k]) - float(bmin[k])))
         x = (means[k].astype(np.float32) - np.float32(bmin[k])) * sc
+        x = np.where(np.isnan(x), np.float32(0.0), x)   # a NaN coordinate takes cell 0
         q.append(np.minimum(np.maximum(x, np.float32(0.0)), np.float32(1023.0)).astype(np.uint32))
     code = (_spread10(q[0]) << 2) | (_spread10(q[1]) << 1) | _spread10(q[2])
     idx = np.arange(means.shape[1])
@@ -49,6 +50,33 @@ def test_spatial_order_is_the_morton_order(dev):
     got = _order(G, sc.planes, dev).cpu().numpy().astype(np.int64)
     assert np.array_equal(np.sort(got), np.arange(G.n))
     np.testing.assert_array_equal(got, _morton_order(sc.gaussians.means, sc.planes.bmin, sc.planes.bmax))
+
+
+@pytest.mark.parametrize("case", ["one", "ragged_1025", "ragged_3001", "all_equal", "outside_and_nan"])
+def test_spatial_order_edge_cases(dev, case):
+    """One Gaussian; sizes one past a sort block and spanning three; every
+    code equal (the order is the identity: the sort is stable); means beyond
+    the box on both sides (clamped to the border cells) and a NaN coordinate
+    (cell 0)."""
+    import types
+    rng = np.random.default_rng(31)
+    n = {"one": 1, "ragged_1025": 1025, "ragged_3001": 3001, "all_equal": 2500, "outside_and_nan": 4096}[case]
+    means = rng.uniform(-1.0, 1.0, size=(3, n)).astype(np.float32)
+    if case == "all_equal":
+        means[:] = np.float32(0.25)
+    if case == "outside_and_nan":
+        means[:, : n // 4] *= np.float32(3.0)          # far outside [-1, 1]
+        means[1, 7] = np.float32(np.nan)
+    g = types.SimpleNamespace(n=n, sh_degree=0, means=means, log_scales=np.zeros((3, n), np.float32),
+                              quats=np.tile(np.array([[1.0], [0.0], [0.0], [0.0]], np.float32), (1, n)),
+                              opacity_logits=np.zeros(n, np.float32), sh=np.zeros((1, 3, n), np.float32))
+    planes = types.SimpleNamespace(bmin=(-1.0, -1.0, -1.0), bmax=(1.0, 1.0, 1.0))
+    G = g4d.DeviceGaussians(g, dev)
+    got = _order(G, planes, dev).cpu().numpy().astype(np.int64)
+    log(f"[spatial order] {case}: n={n}")
+    np.testing.assert_array_equal(got, _morton_order(means, planes.bmin, planes.bmax))
+    if case == "all_equal":
+        np.testing.assert_array_equal(got, np.arange(n))
 
 
 def _deform(G, P, M, t, dev):
