@@ -53,6 +53,26 @@ __device__ __forceinline__ uint64_t lanemask_lt64() {
     return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
+// Inclusive sum over the lanes of a wave (all 64 lanes active) with DPP:
+// shifts by 1, 2, 4 and 8 inside each row of 16 lanes (lanes shifted in
+// from outside the row read 0), then each row adds the last lane of the row
+// before (row broadcast 15) and rows 2 and 3 the last lane of row 1
+// (row broadcast 31).  No LDS round trips.
+template <int CTRL, int ROW_MASK, bool BOUND0>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xf, BOUND0);
+}
+// (unsigned: sums wrap modulo 2^32)
+__device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t v) {
+    v += dpp_u32<0x111, 0xf, true>(v);   // row_shr:1
+    v += dpp_u32<0x112, 0xf, true>(v);   // row_shr:2
+    v += dpp_u32<0x114, 0xf, true>(v);   // row_shr:4
+    v += dpp_u32<0x118, 0xf, true>(v);   // row_shr:8
+    v += dpp_u32<0x142, 0xa, false>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_u32<0x143, 0xc, false>(v);  // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
 // Frame descriptor as the kernels read it: camera, background and output
 // pointers.  It lives in the workspace: the first kernel of a render
 // (k_zero) writes it from its launch argument, so a captured render graph
@@ -512,15 +532,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_pass(
     {
         const uint32_t g = tid < NB ? s_g[tid] : 0u;
         const uint32_t t = tid < NB ? s_tot[tid] : 0u;
-        uint32_t gi = g, ti = t;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t gy = __shfl_up(gi, o, 64), ty = __shfl_up(ti, o, 64);
-            if (lane >= o) {
-                gi += gy;
-                ti += ty;
-            }
-        }
+        const uint32_t gi = wave_inclusive_sum(g), ti = wave_inclusive_sum(t);
         __shared__ uint32_t s_wg[4], s_wt[4];
         if (lane == 63) {
             s_wg[wave] = gi;
@@ -650,16 +662,14 @@ __global__ __launch_bounds__(256) void k_scan_offsets(int n, const uint32_t *__r
     }
 #pragma unroll
     for (int r = 0; r < 16; ++r) v[r] = gs[r] < (uint32_t)n ? touched[gs[r]] : 0u;
-    unsigned long long sum = 0;
+    // wave inclusive scan of per-thread sums: a Gaussian touches at most
+    // 65536 tiles (the largest frame), so a wave's 1024 Gaussians sum to
+    // below 2^26 and the scan runs in 32 bits
+    uint32_t sum32 = 0;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) sum += v[r];
-    // wave inclusive scan of per-thread sums
-    unsigned long long x = sum;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const unsigned long long y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
-    }
+    for (int r = 0; r < 16; ++r) sum32 += v[r];
+    const unsigned long long sum = sum32;
+    const unsigned long long x = wave_inclusive_sum(sum32);
     if (lane == 63) s_w[wave] = x;
     __syncthreads();
     unsigned long long wpre = 0, btotal = 0;
@@ -904,12 +914,7 @@ __global__ __launch_bounds__(256) void k_spine(uint32_t *__restrict__ cnt, int c
             v[r] = b + r < nlive ? row[b + r] : 0u;
             sum += v[r];
         }
-        uint32_t x = sum;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t y = __shfl_up(x, o, 64);
-            if (lane >= o) x += y;
-        }
+        const uint32_t x = wave_inclusive_sum(sum);
         if (lane == 63) s_w[wave] = x;
         __syncthreads();
         uint32_t before = carry;
@@ -993,15 +998,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_down(
         s_wcnt[3][tid] = t0 + t1 + t2;
         g = dtot[tid];
     }
-    uint32_t gi = g, ti = t;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t gy = __shfl_up(gi, o, 64), ty = __shfl_up(ti, o, 64);
-        if (lane >= o) {
-            gi += gy;
-            ti += ty;
-        }
-    }
+    const uint32_t gi = wave_inclusive_sum(g), ti = wave_inclusive_sum(t);
     if (lane == 63) {
         s_wg[wave] = gi;
         s_wt[wave] = ti;
@@ -1079,14 +1076,9 @@ __global__ __launch_bounds__(1024) void k_tile_order(DevStatus *__restrict__ st,
         int32_t carry = 0;
         for (int x0 = 0; x0 < tiles_x; x0 += 64) {
             const int x = x0 + lane;
-            int32_t v = x < tiles_x ? gr[y * gw + x] : 0;
-#pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const int32_t u = __shfl_up(v, o, 64);
-                if (lane >= o) v += u;
-            }
+            const int32_t v = (int32_t)wave_inclusive_sum(x < tiles_x ? (uint32_t)gr[y * gw + x] : 0u);
             if (x < tiles_x) gr[y * gw + x] = carry + v;
-            carry += __shfl(v, 63, 64);
+            carry += __builtin_amdgcn_readlane(v, 63);
         }
     }
     __syncthreads();
@@ -1094,14 +1086,9 @@ __global__ __launch_bounds__(1024) void k_tile_order(DevStatus *__restrict__ st,
         int32_t carry = 0;
         for (int y0 = 0; y0 < tiles_y; y0 += 64) {
             const int y = y0 + lane;
-            int32_t v = y < tiles_y ? gr[y * gw + x] : 0;
-#pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const int32_t u = __shfl_up(v, o, 64);
-                if (lane >= o) v += u;
-            }
+            const int32_t v = (int32_t)wave_inclusive_sum(y < tiles_y ? (uint32_t)gr[y * gw + x] : 0u);
             if (y < tiles_y) gr[y * gw + x] = carry + v;
-            carry += __shfl(v, 63, 64);
+            carry += __builtin_amdgcn_readlane(v, 63);
         }
     }
     __syncthreads();
@@ -1119,12 +1106,7 @@ __global__ __launch_bounds__(1024) void k_tile_order(DevStatus *__restrict__ st,
             if (++x == tiles_x) { x = 0; ++y; }
         }
     }
-    uint32_t xs = part;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t u = __shfl_up(xs, o, 64);
-        if (lane >= o) xs += u;
-    }
+    const uint32_t xs = wave_inclusive_sum(part);
     __shared__ uint32_t s_w[NW];
     __shared__ uint32_t hist[33];
     if (lane == 63) s_w[wave] = xs;
@@ -1146,13 +1128,13 @@ __global__ __launch_bounds__(1024) void k_tile_order(DevStatus *__restrict__ st,
     }
     if (tid == 1023 && (unsigned long long)base != st->k_total) atomicOr(&st->sort_error, 16u);
     __syncthreads();
-    if (tid == 0) {
-        uint32_t pos = 0;
-        for (int c = 32; c >= 0; --c) {
-            const uint32_t h = hist[c];
-            hist[c] = pos;
-            pos += h;
-        }
+    if (wave == 0) {
+        // positions of the length classes, longest first: an exclusive scan
+        // over classes 32 .. 0 (lane l holds class 32 - l)
+        const int c = 32 - lane;
+        const uint32_t h = c >= 0 ? hist[c] : 0u;
+        const uint32_t e = wave_inclusive_sum(h);
+        if (c >= 0) hist[c] = e - h;
     }
     __syncthreads();
     {
