@@ -103,11 +103,22 @@ struct Smem {
     static constexpr size_t fh_bytes = (size_t)kGB * FH_LD * sizeof(E);
     static constexpr size_t h_bytes = (size_t)kGB * H_LD * sizeof(E);
     static constexpr size_t act_bytes = fh_bytes > h_bytes ? fh_bytes : h_bytes;   // f_h, then h
-    static constexpr size_t w1_bytes = (size_t)HID * W1_LD * sizeof(E);
     static constexpr int DS = 16 * NT + 1;                 // delta row stride (floats)
     static constexpr size_t w2_bytes = (size_t)16 * NT * W2_LD * sizeof(E);
     static constexpr size_t delta_bytes = (size_t)kGB * DS * sizeof(float);
     static constexpr size_t bias_bytes = (size_t)(HID + 16 * NT) * sizeof(float);
+    // FP32 W1 is held in registers as MFMA fragments instead of an LDS copy
+    // when that copy would hold the kernel below 3 blocks per CU (160 KB of
+    // LDS) and dropping it lets more blocks in.  Otherwise the LDS copy is
+    // the faster of the two: its global loads are coalesced.
+    static constexpr size_t kLdsPerCu = 160 * 1024;
+    static constexpr size_t w1_lds_bytes = (size_t)HID * W1_LD * sizeof(E);
+    static constexpr size_t lds_without_w1 = act_bytes + bias_bytes + w2_bytes + delta_bytes;
+    static constexpr size_t lds_with_w1 = act_bytes + bias_bytes +
+        (w1_lds_bytes > w2_bytes + delta_bytes ? w1_lds_bytes : w2_bytes + delta_bytes);
+    static constexpr bool W1_REGS = !BF16 && kLdsPerCu / lds_with_w1 < 3 &&
+                                    kLdsPerCu / lds_without_w1 > kLdsPerCu / lds_with_w1;
+    static constexpr size_t w1_bytes = W1_REGS ? 0 : w1_lds_bytes;
     // W1 is dead once h is computed: the heads' weights and the deltas reuse its space
     static constexpr size_t wreg_bytes = w1_bytes > w2_bytes + delta_bytes ? w1_bytes : w2_bytes + delta_bytes;
     static constexpr size_t total = act_bytes + wreg_bytes + bias_bytes;
@@ -143,7 +154,7 @@ __device__ __forceinline__ void deform_block(const DeformBatch &batch) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     E *s_act = reinterpret_cast<E *>(smem);
     E *s_w1 = reinterpret_cast<E *>(smem + S::act_bytes);
-    E *s_w2 = reinterpret_cast<E *>(smem + S::act_bytes);                                  // after phase B
+    E *s_w2 = reinterpret_cast<E *>(smem + S::act_bytes);   // after phase B (W1 in registers: after the encoder)
     float *s_delta = reinterpret_cast<float *>(smem + S::act_bytes + S::w2_bytes);          // after phase C
     float *s_b1 = reinterpret_cast<float *>(smem + S::act_bytes + S::wreg_bytes);
     float *s_b2 = s_b1 + HID;
@@ -183,19 +194,37 @@ __device__ __forceinline__ void deform_block(const DeformBatch &batch) {
     }
 
     // ---- decoder weights (rows of W1; heads padded to 16 rows): the loads
-    // are issued here and stay in flight through the encoder's gathers; the
-    // LDS stores follow the encoder (registers are free here: LDS, not VGPRs,
-    // limits the blocks per CU).
-    constexpr int N1 = (HID * KP + kThreads - 1) / kThreads;
+    // are issued here and stay in flight through the encoder's gathers: rows
+    // of W1 for an LDS copy after the encoder or, with W1 in registers, each
+    // wave's W1 fragments for phase B (output column tiles w, w + 4: lane
+    // (r, k) holds W1[c*16 + r][4 kk + k]).
+    constexpr bool kW1Regs = S::W1_REGS;
+    constexpr int N1 = kW1Regs ? 0 : (HID * KP + kThreads - 1) / kThreads;
     constexpr int N2 = (16 * NT * HID + kThreads - 1) / kThreads;
-    float v1[N1], v2[N2];
+    constexpr int NC1 = kW1Regs ? (HID / 16 + 3) / 4 : 0;
+    // every wave owns a column tile in each of its NC1 groups unless HID / 16
+    // is not a multiple of 4 (HID = 32: waves 2 and 3 idle in phase B)
+    constexpr bool kAllOwn = (HID / 16) % 4 == 0;
+    float v1[N1 > 0 ? N1 : 1], v2[N2];
+    float w1f[NC1 > 0 ? NC1 : 1][kW1Regs ? K / 4 : 1];
     float vb1 = 0.0f, vb2 = 0.0f;
+    const int wave_u = __builtin_amdgcn_readfirstlane(tid >> 6);
     if (!features_only) {
 #pragma unroll
         for (int q = 0; q < N1; ++q) {
             const int i = tid + q * kThreads;
             const int r = i / KP, c = i - r * KP;
             v1[q] = (i < HID * KP && c < K) ? job.w1[r * K + c] : 0.0f;
+        }
+        if constexpr (kW1Regs) {
+            const int lr = tid & 15, lq = (tid >> 4) & 3;
+#pragma unroll
+            for (int ci = 0; ci < NC1; ++ci) {
+                const int c = wave_u + 4 * ci;
+#pragma unroll
+                for (int kk = 0; kk < K / 4; ++kk)
+                    w1f[ci][kk] = (kAllOwn || c < HID / 16) ? job.w1[(size_t)(c * 16 + lr) * K + kk * 4 + lq] : 0.0f;
+            }
         }
 #pragma unroll
         for (int q = 0; q < N2; ++q) {
@@ -275,6 +304,17 @@ __device__ __forceinline__ void deform_block(const DeformBatch &batch) {
                 else s_w1[r * S::W1_LD + c] = v1[q];
             }
         }
+        if constexpr (kW1Regs) {
+            // no W1 copy to alias: the heads' weights go to LDS now
+#pragma unroll
+            for (int q = 0; q < N2; ++q) {
+                const int i = tid + q * kThreads;
+                if (i < 16 * NT * HID) {
+                    const int r = i / HID, c = i - r * HID;
+                    s_w2[r * S::W2_LD + c] = v2[q];
+                }
+            }
+        }
         if (tid < HID) s_b1[tid] = vb1;
         if (tid < 16 * NT) s_b2[tid] = vb2;
     }
@@ -294,55 +334,94 @@ __device__ __forceinline__ void deform_block(const DeformBatch &batch) {
     const int row0 = wave * 16;        // this wave's Gaussians
 
     // ---- B. h = ReLU(W1 f_h + b1)
-    float4_t acc[HID / 16];
-#pragma unroll
-    for (int c = 0; c < HID / 16; ++c) acc[c] = float4_t{0.0f, 0.0f, 0.0f, 0.0f};
-    if constexpr (!BF16) {
+    if constexpr (kW1Regs) {
+        // wave w computes output column tiles w, w + 4 for all 64 Gaussians,
+        // B fragments from registers (the same products in the same k order
+        // as the row split below, so h does not depend on the split)
         const float *fh = reinterpret_cast<const float *>(s_act);
-        const float *w1 = reinterpret_cast<const float *>(s_w1);
-#pragma unroll 4
-        for (int kk = 0; kk < K / 4; ++kk) {
-            const float a = fh[(row0 + lrow) * S::FH_LD + kk * 4 + lk];
+        float4_t accb[NC1 > 0 ? NC1 : 1][kGB / 16];
 #pragma unroll
-            for (int c = 0; c < HID / 16; ++c) {
-                const float b = w1[(c * 16 + lrow) * S::W1_LD + kk * 4 + lk];
-                acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[c], 0, 0, 0);
+        for (int ci = 0; ci < NC1; ++ci)
+#pragma unroll
+            for (int rt = 0; rt < kGB / 16; ++rt) accb[ci][rt] = float4_t{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int kk = 0; kk < K / 4; ++kk) {
+#pragma unroll
+            for (int rt = 0; rt < kGB / 16; ++rt) {
+                const float a = fh[(rt * 16 + lrow) * S::FH_LD + kk * 4 + lk];
+#pragma unroll
+                for (int ci = 0; ci < NC1; ++ci)
+                    if (kAllOwn || wave_u + 4 * ci < HID / 16)
+                        accb[ci][rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, w1f[ci][kk], accb[ci][rt], 0, 0, 0);
+            }
+        }
+        __syncthreads();   // all waves done reading f_h before h overwrites it
+#pragma unroll
+        for (int ci = 0; ci < NC1; ++ci) {
+            const int c = wave_u + 4 * ci;
+            if (kAllOwn || c < HID / 16) {
+                const int col = c * 16 + lrow;
+                const float bias = s_b1[col];
+#pragma unroll
+                for (int rt = 0; rt < kGB / 16; ++rt)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        reinterpret_cast<float *>(s_act)[(rt * 16 + 4 * lk + i) * S::H_LD + col] =
+                            fmaxf(accb[ci][rt][i] + bias, 0.0f);
             }
         }
     } else {
-        const uint16_t *fh = reinterpret_cast<const uint16_t *>(s_act);
-        const uint16_t *w1 = reinterpret_cast<const uint16_t *>(s_w1);
+        // wave w computes its 16 Gaussians' rows, W1 tiles from LDS
+        float4_t acc[HID / 16];
 #pragma unroll
-        for (int kk = 0; kk < KP / 32; ++kk) {
-            const bf16x8_t a = *reinterpret_cast<const bf16x8_t *>(fh + (row0 + lrow) * S::FH_LD + kk * 32 + lk * 8);
+        for (int c = 0; c < HID / 16; ++c) acc[c] = float4_t{0.0f, 0.0f, 0.0f, 0.0f};
+        if constexpr (!BF16) {
+            const float *fh = reinterpret_cast<const float *>(s_act);
+            const float *w1 = reinterpret_cast<const float *>(s_w1);
+#pragma unroll 4
+            for (int kk = 0; kk < K / 4; ++kk) {
+                const float a = fh[(row0 + lrow) * S::FH_LD + kk * 4 + lk];
 #pragma unroll
-            for (int c = 0; c < HID / 16; ++c) {
-                const bf16x8_t b = *reinterpret_cast<const bf16x8_t *>(w1 + (c * 16 + lrow) * S::W1_LD + kk * 32 + lk * 8);
-                acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[c], 0, 0, 0);
+                for (int c = 0; c < HID / 16; ++c) {
+                    const float b = w1[(c * 16 + lrow) * S::W1_LD + kk * 4 + lk];
+                    acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[c], 0, 0, 0);
+                }
+            }
+        } else {
+            const uint16_t *fh = reinterpret_cast<const uint16_t *>(s_act);
+            const uint16_t *w1 = reinterpret_cast<const uint16_t *>(s_w1);
+#pragma unroll
+            for (int kk = 0; kk < KP / 32; ++kk) {
+                const bf16x8_t a = *reinterpret_cast<const bf16x8_t *>(fh + (row0 + lrow) * S::FH_LD + kk * 32 + lk * 8);
+#pragma unroll
+                for (int c = 0; c < HID / 16; ++c) {
+                    const bf16x8_t b = *reinterpret_cast<const bf16x8_t *>(w1 + (c * 16 + lrow) * S::W1_LD + kk * 32 + lk * 8);
+                    acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[c], 0, 0, 0);
+                }
             }
         }
-    }
-    __syncthreads();   // all waves done reading f_h and W1 before h and W2 overwrite them
+        __syncthreads();   // all waves done reading f_h and W1 before h and W2 overwrite them
 #pragma unroll
-    for (int q = 0; q < N2; ++q) {
-        const int i = tid + q * kThreads;
-        if (i < 16 * NT * HID) {
-            const int r = i / HID, c = i - r * HID;
-            if constexpr (BF16) s_w2[r * S::W2_LD + c] = f32_to_bf16_rne(v2[q]);
-            else s_w2[r * S::W2_LD + c] = v2[q];
+        for (int q = 0; q < N2; ++q) {
+            const int i = tid + q * kThreads;
+            if (i < 16 * NT * HID) {
+                const int r = i / HID, c = i - r * HID;
+                if constexpr (BF16) s_w2[r * S::W2_LD + c] = f32_to_bf16_rne(v2[q]);
+                else s_w2[r * S::W2_LD + c] = v2[q];
+            }
         }
-    }
-    // bias + ReLU; lane holds rows row0 + 4*lk + i of column c*16 + lrow
+        // bias + ReLU; lane holds rows row0 + 4*lk + i of column c*16 + lrow
 #pragma unroll
-    for (int c = 0; c < HID / 16; ++c) {
-        const int col = c * 16 + lrow;
-        const float bias = s_b1[col];
+        for (int c = 0; c < HID / 16; ++c) {
+            const int col = c * 16 + lrow;
+            const float bias = s_b1[col];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const float h = fmaxf(acc[c][i] + bias, 0.0f);
-            const int row = row0 + 4 * lk + i;
-            if constexpr (BF16) reinterpret_cast<uint16_t *>(s_act)[row * S::H_LD + col] = f32_to_bf16_rne(h);
-            else reinterpret_cast<float *>(s_act)[row * S::H_LD + col] = h;
+            for (int i = 0; i < 4; ++i) {
+                const float h = fmaxf(acc[c][i] + bias, 0.0f);
+                const int row = row0 + 4 * lk + i;
+                if constexpr (BF16) reinterpret_cast<uint16_t *>(s_act)[row * S::H_LD + col] = f32_to_bf16_rne(h);
+                else reinterpret_cast<float *>(s_act)[row * S::H_LD + col] = h;
+            }
         }
     }
     __syncthreads();
