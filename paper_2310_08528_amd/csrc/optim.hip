@@ -6,9 +6,9 @@
 //   tv = sum_planes ( mean (R[i, j+1] - R[i, j])^2 + mean (R[i+1, j] - R[i, j])^2 ),
 // loss += weight * tv, and dtv/dR[i, j] = 2/N_a (2 R[i,j] - R[i,j-1] -
 // R[i,j+1]) + 2/N_b (...) with the missing neighbours left out at the edges
-// (N_a = n_b (n_a - 1) F, N_b = (n_b - 1) n_a F differences).  One thread per
-// cell (32-bit indices: a plane holds at most 2^31 values; F = 16 or 32 is
-// a shift); each block reduces its loss terms and adds them with one atomic.
+// (N_a = n_b (n_a - 1) F, N_b = (n_b - 1) n_a F differences).  32-bit
+// indices (a plane holds at most 2^31 values; F = 16 or 32 is a shift); each
+// block reduces its loss terms and adds them with one atomic.
 //
 // Adam (Kingma & Ba): m <- b1 m + (1 - b1) g, v <- b2 v + (1 - b2) g^2,
 // p <- p - lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps); up to 64
@@ -26,8 +26,84 @@ struct TvPlanes {
     float weight;
 };
 
-__global__ __launch_bounds__(256) void k_tv(TvPlanes P, float *__restrict__ loss) {
+// The loss terms and gradient of one value, given its four neighbours'
+// differences (each present or not).
+__device__ __forceinline__ float tv_one(float r, float rr, float rl, float rd, float ru, bool has_r, bool has_l,
+                                        bool has_d, bool has_u, float ia, float ib, float &acc) {
+    float g = 0.0f;
+    if (has_r) {
+        const float d = rr - r;
+        acc += d * d * ia;
+        g -= 2.0f * d * ia;
+    }
+    if (has_l) g += 2.0f * (r - rl) * ia;
+    if (has_d) {
+        const float d = rd - r;
+        acc += d * d * ib;
+        g -= 2.0f * d * ib;
+    }
+    if (has_u) g += 2.0f * (r - ru) * ib;
+    return g;
+}
+
+__device__ __forceinline__ void tv_block_loss(float acc, float weight, float *__restrict__ loss) {
     __shared__ float s_part[4];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0 && loss) atomicAdd(loss, weight * ((s_part[0] + s_part[1]) + (s_part[2] + s_part[3])));
+}
+
+// Vector form (every plane and gradient 16-byte aligned): a thread takes
+// four consecutive channels of a cell (16-byte loads and stores), kTvSteps
+// such groups 256 apart, all independent; a block whose range starts past
+// its plane leaves at once (no loss term, no atomic).
+constexpr int kTvSteps = 4;
+
+__global__ __launch_bounds__(256) void k_tv4(TvPlanes P, float *__restrict__ loss) {
+    const int p = blockIdx.y;
+    const int na = P.na[p], nb = P.nb[p], F = P.feat;
+    const int lq = F == 32 ? 3 : 2;   // log2 of the 4-channel groups per cell
+    const uint32_t quads = (uint32_t)(na * nb) << lq;
+    const uint32_t q0 = blockIdx.x * (256u * kTvSteps);
+    if (q0 >= quads) return;
+    const float4 *R = reinterpret_cast<const float4 *>(P.plane[p]);
+    float4 *G = reinterpret_cast<float4 *>(P.grad[p]);
+    const uint32_t f4 = 1u << lq, row4 = (uint32_t)na << lq;
+    const float ia = 1.0f / (float)((size_t)nb * (na - 1) * F);
+    const float ib = 1.0f / (float)((size_t)(nb - 1) * na * F);
+    float acc = 0.0f;
+#pragma unroll
+    for (int k = 0; k < kTvSteps; ++k) {
+        const uint32_t q = q0 + k * 256u + threadIdx.x;
+        if (q < quads) {
+            const uint32_t cell = q >> lq;
+            const uint32_t i = cell / (uint32_t)na, j = cell - i * (uint32_t)na;
+            const bool hr = j + 1 < (uint32_t)na, hl = j > 0, hd = i + 1 < (uint32_t)nb, hu = i > 0;
+            const float4 r = R[q];
+            const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+            const float4 rr = hr ? R[q + f4] : z, rl = hl ? R[q - f4] : z;
+            const float4 rd = hd ? R[q + row4] : z, ru = hu ? R[q - row4] : z;
+            const float gx = tv_one(r.x, rr.x, rl.x, rd.x, ru.x, hr, hl, hd, hu, ia, ib, acc);
+            const float gy = tv_one(r.y, rr.y, rl.y, rd.y, ru.y, hr, hl, hd, hu, ia, ib, acc);
+            const float gz = tv_one(r.z, rr.z, rl.z, rd.z, ru.z, hr, hl, hd, hu, ia, ib, acc);
+            const float gw = tv_one(r.w, rr.w, rl.w, rd.w, ru.w, hr, hl, hd, hu, ia, ib, acc);
+            if (G) {
+                float4 o = G[q];
+                o.x += P.weight * gx;
+                o.y += P.weight * gy;
+                o.z += P.weight * gz;
+                o.w += P.weight * gw;
+                G[q] = o;
+            }
+        }
+    }
+    tv_block_loss(acc, P.weight, loss);
+}
+
+// Scalar form (any alignment): one value per thread, grid-stride.
+__global__ __launch_bounds__(256) void k_tv(TvPlanes P, float *__restrict__ loss) {
     const int p = blockIdx.y;
     const int na = P.na[p], nb = P.nb[p], F = P.feat;
     const int lf = F == 32 ? 5 : 4;
@@ -40,28 +116,12 @@ __global__ __launch_bounds__(256) void k_tv(TvPlanes P, float *__restrict__ loss
     for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += gridDim.x * blockDim.x) {
         const uint32_t cell = c >> lf;
         const uint32_t i = cell / (uint32_t)na, j = cell - i * (uint32_t)na;
-        const float r = R[c];
-        float g = 0.0f;
-        if (j + 1 < (uint32_t)na) {
-            const float d = R[c + F] - r;
-            acc += d * d * ia;
-            g -= 2.0f * d * ia;
-        }
-        if (j > 0) g += 2.0f * (r - R[c - F]) * ia;
-        if (i + 1 < (uint32_t)nb) {
-            const float d = R[c + row] - r;
-            acc += d * d * ib;
-            g -= 2.0f * d * ib;
-        }
-        if (i > 0) g += 2.0f * (r - R[c - row]) * ib;
+        const bool hr = j + 1 < (uint32_t)na, hl = j > 0, hd = i + 1 < (uint32_t)nb, hu = i > 0;
+        const float g = tv_one(R[c], hr ? R[c + F] : 0.0f, hl ? R[c - F] : 0.0f, hd ? R[c + row] : 0.0f,
+                               hu ? R[c - row] : 0.0f, hr, hl, hd, hu, ia, ib, acc);
         if (G) G[c] += P.weight * g;
     }
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
-    if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0 && loss)
-        atomicAdd(loss, P.weight * ((s_part[0] + s_part[1]) + (s_part[2] + s_part[3])));
+    tv_block_loss(acc, P.weight, loss);
 }
 
 struct AdamList {
@@ -140,10 +200,19 @@ extern "C" g4d_status g4d_tv_loss(const g4d_planes *P, float weight, float *loss
     T.weight = weight;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     if (loss) hipLaunchKernelGGL(g4d::k_zero_scalar, dim3(1), dim3(1), 0, s, loss);
-    // up to 128 blocks per plane (about one pass at the largest planes); the
-    // loss adds one atomic per block
-    const unsigned bx = (unsigned)std::min<size_t>((max_cells + 255) / 256, 128);
-    hipLaunchKernelGGL(g4d::k_tv, dim3(bx, (unsigned)T.n_planes), dim3(256), 0, s, T, loss);
+    bool aligned = true;
+    for (int q = 0; q < T.n_planes; ++q)
+        aligned = aligned && ((reinterpret_cast<uintptr_t>(T.plane[q]) | reinterpret_cast<uintptr_t>(T.grad[q])) & 15u) == 0;
+    if (aligned) {
+        // one block per 1024 four-channel groups of the largest plane; the
+        // loss adds one atomic per block with work
+        const unsigned bx = (unsigned)((max_cells / 4 + 256 * g4d::kTvSteps - 1) / (256 * g4d::kTvSteps));
+        hipLaunchKernelGGL(g4d::k_tv4, dim3(bx, (unsigned)T.n_planes), dim3(256), 0, s, T, loss);
+    } else {
+        // up to 128 blocks per plane, grid-stride
+        const unsigned bx = (unsigned)std::min<size_t>((max_cells + 255) / 256, 128);
+        hipLaunchKernelGGL(g4d::k_tv, dim3(bx, (unsigned)T.n_planes), dim3(256), 0, s, T, loss);
+    }
     G4D_HIP_CHECK(hipGetLastError());
     return G4D_OK;
 }

@@ -119,6 +119,49 @@ def test_tv_kernel_matches_oracle(dev):
             np.testing.assert_allclose(p.cpu().numpy(), ref, rtol=0, atol=1e-6 * np.abs(ref).max())
 
 
+def test_tv_unaligned_planes_equal_the_aligned_result(dev):
+    """Planes and gradients that are not 16-byte aligned take the kernel's
+    one-value-per-thread form; its gradients equal the four-channel form's
+    bit for bit (the same expressions per value) and the loss agrees up to
+    the order of the block sums."""
+    import torch
+    sc = synth.config2(plane_dist="uniform", n=500)
+    G, P, M = (g4d.DeviceGaussians(sc.gaussians, DEV), g4d.DevicePlanes(sc.planes, DEV),
+               g4d.DeviceMLP(sc.mlp, DEV))
+    rng = np.random.default_rng(5)
+    base = [[rng.normal(size=tuple(t.shape)).astype(np.float32) for t in lv] for lv in P.tensors]
+
+    def shifted(t):
+        # a copy 4 bytes past a 16-byte boundary
+        buf = torch.empty(t.numel() + 1, dtype=t.dtype, device=t.device)
+        v = buf[1:].view(t.shape)
+        v.copy_(t)
+        return v
+
+    def run(unaligned):
+        d = g4d.DeviceDeformGrad(G, P, M, DEV)
+        for lv, bl in zip(d.planes, base):
+            for q, b in enumerate(bl):
+                lv[q].copy_(torch.as_tensor(b))
+        keep = P.tensors
+        if unaligned:
+            P.tensors = [[shifted(t) for t in lv] for lv in keep]
+            d.planes = [[shifted(t) for t in lv] for lv in d.planes]
+        loss = torch.empty((), device=DEV)
+        g4d.tv_loss(P, 0.25, loss, d)
+        torch.cuda.synchronize()
+        P.tensors = keep
+        return float(loss), [[t.cpu().numpy() for t in lv] for lv in d.planes]
+
+    la, ga = run(False)
+    lu, gu = run(True)
+    log(f"[tv] aligned {la:.7f} unaligned {lu:.7f}")
+    assert abs(la - lu) <= 1e-6 * abs(la)
+    for lva, lvu in zip(ga, gu):
+        for a, u in zip(lva, lvu):
+            np.testing.assert_array_equal(a, u)
+
+
 def test_adam_kernel_matches_oracle(dev):
     import torch
     from oracle import train as ot
