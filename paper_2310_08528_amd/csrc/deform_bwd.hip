@@ -521,23 +521,29 @@ __global__ __launch_bounds__(kThreads) void k_deform_bwd(BwdJob J, int rows) {
     __shared__ int s_woff[kMaxScalesB * 6], s_wa0[kMaxScalesB * 6], s_wb0[kMaxScalesB * 6];
     __shared__ int s_wn[kMaxScalesB * 6], s_wm[kMaxScalesB * 6];
     __shared__ int s_wtotal;
-    if (tid < 3 * L) {
-        s_lo[tid] = 0x7fffffff;
-        s_hi[tid] = -1;
-    }
-    __syncthreads();
-    if (tid < GB && g0 + tid < n) {
-        const int g = g0 + tid;
+    if (wave_u == 0) {
+        // lane = Gaussian of the block; the extremes by wave reductions (LDS
+        // atomics from all 64 lanes on one address would serialise)
+        const int g = g0 + lane;
+        const bool ok = lane < GB && g < n;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const float xk = J.means[(size_t)k * n + g] - J.bmin[k];
+            const float xk = ok ? J.means[(size_t)k * n + g] - J.bmin[k] : 0.0f;
 #pragma unroll
             for (int l = 0; l < L; ++l) {
                 int i0;
                 float w;
                 grid_coord(xk, J.gscale[l][k], J.res[l][k], i0, w);
-                atomicMin(&s_lo[l * 3 + k], i0);
-                atomicMax(&s_hi[l * 3 + k], i0);
+                int lo = ok ? i0 : 0x7fffffff, hi = ok ? i0 : -1;
+#pragma unroll
+                for (int o = 32; o >= 1; o >>= 1) {
+                    lo = min(lo, __shfl_xor(lo, o, 64));
+                    hi = max(hi, __shfl_xor(hi, o, 64));
+                }
+                if (lane == 0) {
+                    s_lo[l * 3 + k] = lo;
+                    s_hi[l * 3 + k] = hi;
+                }
             }
         }
     }
