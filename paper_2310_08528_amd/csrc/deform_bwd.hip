@@ -516,7 +516,10 @@ __global__ __launch_bounds__(kThreads) void k_deform_bwd(BwdJob J, int rows) {
     __syncthreads();
     // ---- plane-cell windows of this block: the range of the Gaussians'
     // lower corner cells along each spatial grid axis, per scale; a window
-    // spans that range plus one (the upper corners)
+    // spans that range plus one (the upper corners).  A cell takes F + 1
+    // floats there: with F (a multiple of 32) the eight Gaussians of a wave
+    // would add into only 16 of the 64 LDS banks (4-way conflicts).
+    constexpr int WF = F + 1;
     __shared__ int s_lo[kMaxScalesB * 3], s_hi[kMaxScalesB * 3];
     __shared__ int s_woff[kMaxScalesB * 6], s_wa0[kMaxScalesB * 6], s_wb0[kMaxScalesB * 6];
     __shared__ int s_wn[kMaxScalesB * 6], s_wm[kMaxScalesB * 6];
@@ -559,7 +562,7 @@ __global__ __launch_bounds__(kThreads) void k_deform_bwd(BwdJob J, int rows) {
                 const int la = s_lo[l * 3 + a], ha = s_hi[l * 3 + a];
                 const int lb = b == 3 ? it : s_lo[l * 3 + b], hb = b == 3 ? it : s_hi[l * 3 + b];
                 const int wn = ha - la + 2, wm = hb - lb + 2;
-                const int need = wn * wm * F;
+                const int need = wn * wm * WF;
                 if (ha >= la && hb >= lb && used + need <= win_cap) {
                     s_woff[q] = used;
                     s_wa0[q] = la;
@@ -652,15 +655,15 @@ __global__ __launch_bounds__(kThreads) void k_deform_bwd(BwdJob J, int rows) {
                     const int wo = s_woff[q];
                     if (wo >= 0) {
                         // this block's window of the plane, in LDS
-                        const int wrow = s_wn[q] * F;
-                        float *lb = s_win + wo + ((ib_[p] - s_wb0[q]) * s_wn[q] + (ia_[p] - s_wa0[q])) * F + 4 * c4;
+                        const int wrow = s_wn[q] * WF;
+                        float *lb = s_win + wo + ((ib_[p] - s_wb0[q]) * s_wn[q] + (ia_[p] - s_wa0[q])) * WF + 4 * c4;
 #pragma unroll
                         for (int c = 0; c < 4; ++c) {
                             if (dvv[c] == 0.0f) continue;
                             if (w00 != 0.0f) atomicAdd(lb + c, w00 * dvv[c]);
-                            if (w10 != 0.0f) atomicAdd(lb + F + c, w10 * dvv[c]);
+                            if (w10 != 0.0f) atomicAdd(lb + WF + c, w10 * dvv[c]);
                             if (w01 != 0.0f) atomicAdd(lb + wrow + c, w01 * dvv[c]);
-                            if (w11 != 0.0f) atomicAdd(lb + wrow + F + c, w11 * dvv[c]);
+                            if (w11 != 0.0f) atomicAdd(lb + wrow + WF + c, w11 * dvv[c]);
                         }
                     } else {
                         float *gb = J.d_planes[q] + off[p];
@@ -718,9 +721,9 @@ __global__ __launch_bounds__(kThreads) void k_deform_bwd(BwdJob J, int rows) {
         const int na = J.res[q / 6][axis_a(q % 6)];
         float *dst = J.d_planes[q] + ((size_t)s_wb0[q] * na + s_wa0[q]) * F;
         for (int i = tid; i < cnt; i += kThreads) {
-            const float v = s_win[wo + i];
-            if (v == 0.0f) continue;
             const int cell = i / F, f = i - cell * F;
+            const float v = s_win[wo + cell * WF + f];
+            if (v == 0.0f) continue;
             const int cb = cell / wn, ca = cell - cb * wn;
             atomicAdd(dst + ((size_t)cb * na + ca) * F + f, v);
         }
