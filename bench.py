@@ -536,7 +536,9 @@ def rasterizer_traffic():
 
 def main():
     import faulthandler
-    faulthandler.dump_traceback_later(90, repeat=True, file=sys.stderr)
+    # a hang names where it is stuck: every thread's stack to stderr after
+    # four minutes without the run ending (the default run takes about two)
+    faulthandler.dump_traceback_later(240, repeat=True, file=sys.stderr)
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=400)
