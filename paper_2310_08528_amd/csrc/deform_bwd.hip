@@ -580,10 +580,15 @@ __global__ __launch_bounds__(kThreads) void k_deform_bwd(BwdJob J, int rows) {
     __syncthreads();
     for (int i = tid; i < s_wtotal; i += kThreads) s_win[i] = 0.0f;
     __syncthreads();
-    // ---- encoder backward (Eq. 7)
+    // ---- encoder backward (Eq. 7).  The Gaussians of a wave are taken 4 NPASS
+    // apart in the block (Gaussian j of wave w in pass p is j * 4 NPASS +
+    // 4 p + w): spatially ordered neighbours share plane cells, and the LDS
+    // adds of one instruction into a shared cell serialise.
 #pragma unroll
     for (int pass = 0; pass < NPASS; ++pass) {
-        const int gl = pass * GPP + tid / LPG, c4 = tid % LPG, g = g0 + gl;
+        constexpr int WPG = GPP / 4;   // Gaussians per wave and pass
+        const int q = tid / LPG;
+        const int gl = (q % WPG) * (4 * NPASS) + pass * 4 + q / WPG, c4 = tid % LPG, g = g0 + gl;
         const bool valid = gl < GB && g < n;
         float x[4];
         bool inner[3];
