@@ -55,6 +55,23 @@ def test_deform_colour_opacity_heads_full_size(dev, t):
     assert max(errs.values()) <= def_tol(sc.planes), errs
 
 
+def test_colour_heads_three_scales_hidden64(dev):
+    """The large configuration's three-scale field (f_h 96) with a 64-wide
+    decoder and SH degree 3 colour + opacity heads, on a ragged 5003
+    Gaussians: the four-tile kernel shape whose W1 is held as per-wave
+    register fragments (an LDS copy would limit the blocks per CU)."""
+    import dataclasses
+    sc = synth.config4(plane_dist="uniform", n=5003)
+    mlp = synth.make_mlp(np.random.default_rng(9), sc.planes.in_dim, 64, colour_rows=synth.sh_rows(3),
+                         opacity=True)
+    sc = dataclasses.replace(sc, mlp=mlp)
+    host, _ = gpu_deform(sc, 0.41)
+    d = oracle.deform(sc.gaussians, sc.planes, sc.mlp, 0.41)
+    errs = _errors(host, d)
+    log("[colour heads, 3 scales, hidden 64] " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+    assert max(errs.values()) <= def_tol(sc.planes), errs
+
+
 def test_zero_heads_leave_the_base_outputs_bitwise_unchanged(dev):
     """All-zero colour and opacity heads: the four-tile kernel gives the same
     means, scales, quats and opacity as the one-tile kernel without heads,
