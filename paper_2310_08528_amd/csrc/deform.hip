@@ -119,6 +119,11 @@ struct Smem {
     static constexpr bool W1_REGS = !BF16 && kLdsPerCu / lds_with_w1 < 3 &&
                                     kLdsPerCu / lds_without_w1 > kLdsPerCu / lds_with_w1;
     static constexpr size_t w1_bytes = W1_REGS ? 0 : w1_lds_bytes;
+    // FP32 decoders whose W1 rows in flight through the encoder take at most
+    // 16 registers fit 128 VGPRs without spilling: held to four waves per
+    // SIMD (more plane gathers in flight); the others are left unconstrained
+    static constexpr int W1_IN_FLIGHT = W1_REGS ? 0 : (HID * KP + 255) / 256;
+    static constexpr int WAVES = !BF16 && NT == 1 && W1_IN_FLIGHT <= 16 ? 4 : 1;
     // W1 is dead once h is computed: the heads' weights and the deltas reuse its space
     static constexpr size_t wreg_bytes = w1_bytes > w2_bytes + delta_bytes ? w1_bytes : w2_bytes + delta_bytes;
     static constexpr size_t total = act_bytes + wreg_bytes + bias_bytes;
@@ -550,7 +555,8 @@ __device__ __forceinline__ void deform_block(const DeformBatch &batch) {
 }
 
 template <int F, int L, int HID, bool BF16>
-__global__ __launch_bounds__(kThreads) void k_deform(DeformBatch batch) {
+__global__ __launch_bounds__(kThreads)
+__attribute__((amdgpu_waves_per_eu(Smem<F, L, HID, BF16, 1>::WAVES))) void k_deform(DeformBatch batch) {
     deform_block<F, L, HID, BF16, 1>(batch);
 }
 
