@@ -183,61 +183,102 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const uint4 *__restrict__ ord
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         const int cnt = (int)__popcll(km);
-        for (int j = 0; j < cnt; ++j) {   // decreasing list position
-            const float4 R0 = R[3 * j], R1 = R[3 * j + 1], R2 = R[3 * j + 2];
-            const int pos = __float_as_int(R2.y);
-            const float dx = R0.x - fpx, dy = R0.y - fpy;
+        // Entries in groups of four, in decreasing list position: the
+        // transmittance and colour recursions stay in order, while the
+        // entries' gradient terms and row sums are independent work for the
+        // scheduler.
+        struct Ent {
+            float4 R0, R1, R2;
+            float dx, dy, raw, alpha;
+            bool act;
+        };
+        auto load_ent = [&](int e) -> Ent {
+            Ent q;
+            q.R0 = R[3 * e];
+            q.R1 = R[3 * e + 1];
+            q.R2 = R[3 * e + 2];
+            const int pos = __float_as_int(q.R2.y);
+            q.dx = q.R0.x - fpx;
+            q.dy = q.R0.y - fpy;
             // the forward's expressions, so that the skip decisions are its own
-            const float power = __builtin_fmaf(dx, __builtin_fmaf(R0.z, dx, R1.x * dy), (R0.w * dy) * dy);
+            const float power = __builtin_fmaf(q.dx, __builtin_fmaf(q.R0.z, q.dx, q.R1.x * q.dy), (q.R0.w * q.dy) * q.dy);
             const float pw = power > 0.0f ? -INFINITY : power;
-            const float raw = __builtin_amdgcn_exp2f(__builtin_fmaf(pw, 1.44269504f, R1.y));
-            float alpha = fminf(0.99f, raw);
-            alpha = alpha < a_min ? 0.0f : alpha;
-            const bool act = inside && pos <= last && alpha > 0.0f;
-            // an entry no pixel of the quadrant composites changes nothing
-            if (__builtin_amdgcn_ballot_w64(act) == 0) continue;
-            // branch-free body: a lane that does not composite this entry
-            // takes alpha = 0, for which 1/(1 - alpha) = 1 exactly and T, S
-            // and every gradient term stay unchanged (zero)
-            const float al = act ? alpha : 0.0f;
+            q.raw = __builtin_amdgcn_exp2f(__builtin_fmaf(pw, 1.44269504f, q.R1.y));
+            float alpha = fminf(0.99f, q.raw);
+            q.alpha = alpha < a_min ? 0.0f : alpha;
+            q.act = inside && pos <= last && q.alpha > 0.0f;
+            return q;
+        };
+        // branch-free body: a lane that does not composite the entry takes
+        // alpha = 0, for which 1/(1 - alpha) = 1 exactly and T, S and every
+        // gradient term stay unchanged (zero)
+        auto grad_of = [&](const Ent &q, float (&v)[kG2]) {
+            const float al = q.act ? q.alpha : 0.0f;
             const float om = 1.0f - al;
             // 1/(1 - alpha): hardware reciprocal and one Newton step
             float r = __builtin_amdgcn_rcpf(om);
             r = __builtin_fmaf(__builtin_fmaf(-om, r, 1.0f), r, r);
             const float Ti = T * r;
             const float aT = al * Ti;
-            float v[kG2];
             v[5] = aT * g0;
             v[6] = aT * g1;
             v[7] = aT * g2;
-            const float cg = (R1.z * g0 + R1.w * g1) + R2.x * g2;
+            const float cg = (q.R1.z * g0 + q.R1.w * g1) + q.R2.x * g2;
             const float sg = (S0 * g0 + S1 * g1) + S2 * g2;
             const float dal = Ti * (cg - sg) - tnbg * r;
-            S0 = al * R1.z + om * S0;
-            S1 = al * R1.w + om * S1;
-            S2 = al * R2.x + om * S2;
+            S0 = al * q.R1.z + om * S0;
+            S1 = al * q.R1.w + om * S1;
+            S2 = al * q.R2.x + om * S2;
             T = Ti;
             // a clamped alpha passes nothing to o or the power
-            const float dpw = raw > 0.99f ? 0.0f : dal * al;
-            v[8] = dpw * R2.z;                                    // dalpha/do = alpha/o
-            v[0] = dpw * __builtin_fmaf(2.0f * R0.z, dx, R1.x * dy);   // d power / du = -A dx - B dy
-            v[1] = dpw * __builtin_fmaf(2.0f * R0.w, dy, R1.x * dx);   // d power / dv = -C dy - B dx
-            const float hd = -0.5f * dpw, hx = hd * dx;
-            v[2] = hx * dx;                                       // d power / dA
-            v[3] = (hx + hx) * dy;                                // d power / dB
-            v[4] = (hd * dy) * dy;                                // d power / dC
-            {
-                float sum[kG2];
+            const float dpw = q.raw > 0.99f ? 0.0f : dal * al;
+            v[8] = dpw * q.R2.z;                                          // dalpha/do = alpha/o
+            v[0] = dpw * __builtin_fmaf(2.0f * q.R0.z, q.dx, q.R1.x * q.dy);   // d power / du = -A dx - B dy
+            v[1] = dpw * __builtin_fmaf(2.0f * q.R0.w, q.dy, q.R1.x * q.dx);   // d power / dv = -C dy - B dx
+            const float hd = -0.5f * dpw, hx = hd * q.dx;
+            v[2] = hx * q.dx;                                             // d power / dA
+            v[3] = (hx + hx) * q.dy;                                      // d power / dB
+            v[4] = (hd * q.dy) * q.dy;                                    // d power / dC
+        };
+        // lane k of each row adds component k of its row's sum into the chunk
+        // accumulator (LDS atomics: the rows and the four quadrants meet there)
+        auto add_sums = [&](const float (&v)[kG2], int e) {
+            float sum[kG2];
 #pragma unroll
-                for (int k = 0; k < kG2; ++k) sum[k] = row_sum(v[k]);
-                // lane k of each row adds component k of its row's sum into the
-                // chunk accumulator (LDS atomics: the rows and the four
-                // quadrants meet there)
-                const int rk = lane & 15;
-                float mine = sum[0];
+            for (int k = 0; k < kG2; ++k) sum[k] = row_sum(v[k]);
+            const int rk = lane & 15;
+            float mine = sum[0];
 #pragma unroll
-                for (int k = 1; k < kG2; ++k) mine = rk == k ? sum[k] : mine;
-                if (rk < kG2 && mine != 0.0f) atomicAdd(&sAcc[Sl[j] * kG2 + rk], mine);
+            for (int k = 1; k < kG2; ++k) mine = rk == k ? sum[k] : mine;
+            if (rk < kG2 && mine != 0.0f) atomicAdd(&sAcc[Sl[e] * kG2 + rk], mine);
+        };
+        constexpr int kGrp = 4;   // entries per group
+        int j = 0;
+        for (; j + kGrp <= cnt; j += kGrp) {
+            Ent q[kGrp];
+            bool u[kGrp];
+            bool any = false;
+#pragma unroll
+            for (int e = 0; e < kGrp; ++e) {
+                q[e] = load_ent(j + e);
+                // an entry no pixel of the quadrant composites changes nothing
+                u[e] = __builtin_amdgcn_ballot_w64(q[e].act) != 0;
+                any = any || u[e];
+            }
+            if (!any) continue;
+            float v[kGrp][kG2];
+#pragma unroll
+            for (int e = 0; e < kGrp; ++e) grad_of(q[e], v[e]);
+#pragma unroll
+            for (int e = 0; e < kGrp; ++e)
+                if (u[e]) add_sums(v[e], j + e);
+        }
+        for (; j < cnt; ++j) {
+            const Ent qa = load_ent(j);
+            if (__builtin_amdgcn_ballot_w64(qa.act) != 0) {
+                float va[kG2];
+                grad_of(qa, va);
+                add_sums(va, j);
             }
         }
         __syncthreads();
