@@ -79,6 +79,7 @@ __global__ void k_fill_zero(float *__restrict__ p, size_t n) {
 }
 
 constexpr int kG2 = 9;   // 2D gradient components per Gaussian
+constexpr int kBlendBwdWideN = 16384;   // up to this many Gaussians: eight entries per group
 
 // Sum over the 64 lanes of a wave (every lane active): butterflies inside
 // each row of 16 lanes with DPP (quad permutes, half-row and row mirrors,
@@ -99,6 +100,7 @@ __device__ __forceinline__ float row_sum(float v) {
     return v;
 }
 
+template <int GRP>
 __global__ __launch_bounds__(256) void k_blend_bwd(const uint4 *__restrict__ order, const uint32_t *__restrict__ gids,
                                                    uint32_t gmask, const float4 *__restrict__ recA,
                                                    const float4 *__restrict__ recB, const float4 *__restrict__ recC,
@@ -183,7 +185,7 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const uint4 *__restrict__ ord
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         const int cnt = (int)__popcll(km);
-        // Entries in groups of four, in decreasing list position: the
+        // Entries in groups of GRP, in decreasing list position: the
         // transmittance and colour recursions stay in order, while the
         // entries' gradient terms and row sums are independent work for the
         // scheduler.
@@ -252,7 +254,7 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const uint4 *__restrict__ ord
             for (int k = 1; k < kG2; ++k) mine = rk == k ? sum[k] : mine;
             if (rk < kG2 && mine != 0.0f) atomicAdd(&sAcc[Sl[e] * kG2 + rk], mine);
         };
-        constexpr int kGrp = 4;   // entries per group
+        constexpr int kGrp = GRP;   // entries per group
         int j = 0;
         for (; j + kGrp <= cnt; j += kGrp) {
             Ent q[kGrp];
@@ -552,7 +554,12 @@ g4d_status render_backward(const g4d_splats *G, const g4d_camera *C, const g4d_w
     float *g2d = ws_at<float>(ws, L.grad2d);
     hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)std::min<size_t>(((size_t)kG2 * n + 255) / 256, 4096)), dim3(256),
                        0, s, g2d, (size_t)kG2 * n);
-    hipLaunchKernelGGL(k_blend_bwd, dim3(tiles), dim3(256), 0, s, ws_at<uint4>(ws, L.order), gids, gmask,
+    // entries per group: eight (130 VGPRs, three waves per SIMD) where few
+    // Gaussians leave the kernel latency-bound, four (82 VGPRs) where many
+    // tiles keep the chip busy and occupancy pays (measured at 2000 and at
+    // 100k Gaussians, 800x800)
+    auto blend_bwd = n <= kBlendBwdWideN ? k_blend_bwd<8> : k_blend_bwd<4>;
+    hipLaunchKernelGGL(blend_bwd, dim3(tiles), dim3(256), 0, s, ws_at<uint4>(ws, L.order), gids, gmask,
                        ws_at<float4>(ws, L.recA), ws_at<float4>(ws, L.recB), ws_at<float4>(ws, L.recC), C->width,
                        C->height, tiles_x, tiles, cam, final_T, n_contrib, grad_image, g2d, n);
     hipLaunchKernelGGL(k_preprocess_bwd, dim3((n + 255) / 256), dim3(256), 0, s, n, G->sh_degree, G->means,

@@ -112,6 +112,18 @@ def test_render_backward_small_config_subset(dev):
     assert max(errs.values()) <= GRAD_TOL, errs
 
 
+def test_render_backward_many_gaussians(dev):
+    """20000 Gaussians of the 100k configuration's generator (SH degree 3) at
+    96x96: more Gaussians than the kernel takes eight entries per group for,
+    so the four-entry form runs (the one the 100k training step uses)."""
+    sc = synth.config2(plane_dist="uniform", n=20_000, n_cams=1, n_times=1)
+    cam = synth.look_at_camera((0.0, 0.0, 4.0), (0.0, 0.0, 0.0), 96, 96, 50.0)
+    d = oracle.deform(sc.gaussians, sc.planes, sc.mlp, 0.5)
+    s32 = oracle.to_splats32(d, sc.gaussians.sh, 3)
+    errs = _render_bwd_case(s32, cam, "C2 generator 20k @ 96x96", seed=5)
+    assert max(errs.values()) <= GRAD_TOL, errs
+
+
 def test_backward_empty_and_fully_culled(dev):
     """No Gaussians: both backward calls succeed and the deformation
     backward still clears every plane and decoder gradient.  Every Gaussian
