@@ -189,14 +189,16 @@ def test_deform_config2_full_size(dev, t):
     assert max(errs.values()) <= def_tol(sc.planes)
 
 
-def test_deform_two_scales_hidden128(dev):
+@pytest.mark.parametrize("n", [8001, 37])
+def test_deform_two_scales_hidden128(dev, n):
     """The 100k configuration's field (two scales, f_h 64) with a 128-wide
-    hidden layer, on a ragged 8001 Gaussians: the decoder shape whose W1 the
-    kernel keeps as per-wave register fragments (an LDS copy would limit the
-    blocks per CU), against the FP64 oracle at def_tol."""
-    sc = synth.config2(plane_dist="uniform", n=8001)
+    hidden layer, on a ragged 8001 Gaussians and on 37 (one partial block):
+    the decoder shape whose W1 the kernel keeps as per-wave register
+    fragments (an LDS copy would limit the blocks per CU), against the FP64
+    oracle at def_tol."""
+    sc = synth.config2(plane_dist="uniform", n=n)
     sc.mlp = synth.make_mlp(np.random.default_rng(7), sc.planes.in_dim, 128)
-    errs, _, _ = _check_deform(sc, 0.61, "C2 field, MLP 64-128-10")
+    errs, _, _ = _check_deform(sc, 0.61, f"C2 field, MLP 64-128-10, {n} Gaussians")
     assert max(errs.values()) <= def_tol(sc.planes)
 
 
